@@ -1,0 +1,274 @@
+"""Float64 reference for everything the HIP path computes.
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` use it; the product path never does.
+
+Conventions (shared by the definitions below and the paper's Secs. 3-5):
+  * waveform s in C^N, zero outside [0, N); lags tau in [-T, T]; Doppler bins
+    k in [0, M), M a power of two; centred bin k_c = ((k + M/2) mod M) - M/2.
+  * chi[tau, k] = sum_n s[n] conj(s[n - tau]) exp(-j 2 pi k n / M)   (Eqs. 7-11)
+  * E = sum |s|^2 = chi[0, 0] (the maximum of |chi|, Eq. 17's normaliser)
+  * p = |chi|^2 / E^2 (the paper's chi, Eq. 12, divided by its peak)
+  * a = sqrt(p + eps) (the eps-stabilised normalised magnitude)
+  * every gradient is the conjugate Wirtinger derivative dL/d conj(.)
+    (Sec. 3.3 Eq. 6 and Sec. 4.2 Eqs. 13-14).
+Arrays are numpy; grids are [2T+1, M] with row i <-> tau = i - T.
+"""
+import math
+
+import numpy as np
+from scipy.special import erf
+
+from . import _native
+
+__all__ = [
+    "to_c64_exact", "energy", "chi", "magnitude", "power",
+    "centred_bins", "mainlobe_mask", "isl_weights", "LossParams", "loss_terms",
+    "loss_and_grad", "magnitude_backward", "grad_from_upstream", "phase_grad",
+    "adam_step", "bf16_round", "gelu", "gelu_grad", "mlp_forward",
+    "mlp_backward", "psl_db",
+]
+
+
+# ----------------------------------------------------------------------------
+# inputs
+# ----------------------------------------------------------------------------
+
+def to_c64_exact(s):
+    """The complex64 value of s, widened to complex128 (the bits the GPU sees)."""
+    return np.asarray(s).astype(np.complex64).astype(np.complex128)
+
+
+def energy(s):
+    """E = sum_n |s[n]|^2 (Sec. 4.3: the value of chi at the origin)."""
+    s = np.asarray(s, dtype=np.complex128)
+    return float(np.sum(s.real * s.real + s.imag * s.imag))
+
+
+# ----------------------------------------------------------------------------
+# the ambiguity function (Sec. 4.1, Eqs. 7-12)
+# ----------------------------------------------------------------------------
+
+def chi(s, m, max_lag=None):
+    """Complex AF by its defining sum (C core, direct DFT, no FFT)."""
+    s = np.asarray(s, dtype=np.complex128)
+    T = s.shape[0] - 1 if max_lag is None or max_lag < 0 else int(max_lag)
+    return _native.chi(s, int(m), T)
+
+
+def power(c, E):
+    """p = |chi|^2 / E^2."""
+    return (c.real * c.real + c.imag * c.imag) / (E * E)
+
+
+def magnitude(c, E, eps):
+    """a = sqrt(|chi|^2 / E^2 + eps)."""
+    return np.sqrt(power(c, E) + eps)
+
+
+def psl_db(a_or_p, sidelobe, is_power=True):
+    """Peak sidelobe level, Eq. 18, in dB of power relative to the origin."""
+    v = a_or_p[sidelobe]
+    pk = float(v.max()) if is_power else float(v.max()) ** 2
+    return 10.0 * math.log10(pk) if pk > 0 else -math.inf
+
+
+# ----------------------------------------------------------------------------
+# regions and weights (Eqs. 18-19: the sidelobe region Omega_s)
+# ----------------------------------------------------------------------------
+
+def centred_bins(m):
+    k = np.arange(m)
+    return ((k + m // 2) % m) - m // 2
+
+
+def mainlobe_mask(m, max_lag, h_tau, h_k):
+    """True on the mainlobe |tau| <= h_tau and |k_c| <= h_k."""
+    taus = np.arange(-max_lag, max_lag + 1)
+    kc = centred_bins(m)
+    return (np.abs(taus)[:, None] <= h_tau) & (np.abs(kc)[None, :] <= h_k)
+
+
+def isl_weights(n, m, max_lag, h_tau, h_k, u=None, v=None):
+    """ISL weight per cell: 0 on the mainlobe; 1 elsewhere, or the separable
+    shaping weight u[floor(31|tau|/N)] * v[floor(31|k_c|/(M/2+1))] when the
+    31-entry vectors u, v are given (integer floor division)."""
+    main = mainlobe_mask(m, max_lag, h_tau, h_k)
+    if u is None:
+        W = np.ones((2 * max_lag + 1, m))
+    else:
+        u = np.asarray(u, dtype=np.float64)
+        v = np.asarray(v, dtype=np.float64)
+        taus = np.abs(np.arange(-max_lag, max_lag + 1))
+        kc = np.abs(centred_bins(m))
+        iu = (31 * taus) // n
+        iv = (31 * kc) // (m // 2 + 1)
+        W = u[iu][:, None] * v[iv][None, :]
+    W[main] = 0.0
+    return W
+
+
+class LossParams:
+    """L = w_isl * ISL + w_psl * softPSL over the sidelobe region.
+
+    ISL = sum_{Omega_s} W p                         (Eq. 19, weighted)
+    softPSL = T log sum_{Omega_s} exp(a / T)        (smooth stand-in for Eq. 18)
+    """
+
+    def __init__(self, w_isl=1.0, w_psl=0.0, temp=0.05, h_tau=1, h_k=1,
+                 u=None, v=None, eps=1e-12):
+        self.w_isl, self.w_psl, self.temp = float(w_isl), float(w_psl), float(temp)
+        self.h_tau, self.h_k = int(h_tau), int(h_k)
+        self.u = None if u is None else np.asarray(u, dtype=np.float64)
+        self.v = None if v is None else np.asarray(v, dtype=np.float64)
+        self.eps = float(eps)
+
+
+def loss_terms(c, E, n, params):
+    """Loss value and its pieces from a complex grid c (no gradient)."""
+    T = (c.shape[0] - 1) // 2
+    m = c.shape[1]
+    p = power(c, E)
+    a = np.sqrt(p + params.eps)
+    side = ~mainlobe_mask(m, T, params.h_tau, params.h_k)
+    W = isl_weights(n, m, T, params.h_tau, params.h_k, params.u, params.v)
+    isl = float(np.sum(W * p))
+    av = a[side]
+    mx = float(av.max())
+    S = float(np.sum(np.exp((av - mx) / params.temp)))
+    soft = mx + params.temp * math.log(S)
+    loss = params.w_isl * isl + params.w_psl * soft
+    return dict(loss=loss, isl=isl, softpsl=soft, psl_db=psl_db(p, side),
+                p=p, a=a, side=side, W=W, lse_max=mx, lse_sum=S)
+
+
+def loss_and_grad(s, m, max_lag, params):
+    """Loss of Sec. 5 and dL/d conj(s) through chi, E and a (Eqs. 13-15).
+
+    Per cell: dL/d conj(chi) = w_isl W chi / E^2 + w_psl q chi / (2 E^2 a),
+    q = softmax over Omega_s of a/T.  Energy: dL/dE = -2 w_isl ISL / E
+    - w_psl sum q p / (E a).  Then g = adjoint(G) + dL/dE * s.
+    """
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
+    T = n - 1 if max_lag is None or max_lag < 0 else int(max_lag)
+    E = energy(s)
+    c = chi(s, m, T)
+    t = loss_terms(c, E, n, params)
+    a, p, side, W = t["a"], t["p"], t["side"], t["W"]
+    q = np.zeros_like(a)
+    q[side] = np.exp((a[side] - t["lse_max"]) / params.temp) / t["lse_sum"]
+    coef = params.w_isl * W / (E * E) + params.w_psl * q / (2.0 * E * E * a)
+    G = coef * c
+    dLdE = (-2.0 * params.w_isl * t["isl"] / E
+            - params.w_psl * float(np.sum(q * p / (E * a))))
+    g = grad_from_upstream(s, m, T, G, dLdE)
+    t.update(g=g, G=G, dLdE=dLdE, chi=c, E=E)
+    return t
+
+
+def magnitude_backward(s, m, max_lag, grad_mag, eps):
+    """dL/d conj(s) for an upstream dL/da on the magnitude grid.
+
+    dL/d conj(chi) = g_a chi / (2 E^2 a); dL/dE = -sum g_a p / (E a).
+    """
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
+    T = n - 1 if max_lag is None or max_lag < 0 else int(max_lag)
+    E = energy(s)
+    c = chi(s, m, T)
+    p = power(c, E)
+    a = np.sqrt(p + eps)
+    ga = np.asarray(grad_mag, dtype=np.float64)
+    G = ga * c / (2.0 * E * E * a)
+    dLdE = -float(np.sum(ga * p / (E * a)))
+    return grad_from_upstream(s, m, T, G, dLdE)
+
+
+def grad_from_upstream(s, m, max_lag, G, dLdE):
+    """g = sum over the chain rule of Eq. 15: the lag-product adjoint applied to
+    the inverse DFT of G, plus the energy term dL/dE * s (dE/d conj(s) = s)."""
+    s = np.asarray(s, dtype=np.complex128)
+    return _native.adjoint(s, int(m), int(max_lag), G) + dLdE * s
+
+
+def phase_grad(s, g):
+    """dL/dphi for s = exp(j phi): 2 Im(conj(s) * dL/d conj(s))."""
+    return 2.0 * np.imag(np.conj(s) * g)
+
+
+# ----------------------------------------------------------------------------
+# optimiser (Sec. 6.2 update, Sec. 7.1.2 settings: Adam, lr 0.01)
+# ----------------------------------------------------------------------------
+
+def adam_step(x, grad, m, v, t, lr=0.01, b1=0.9, b2=0.999, eps=1e-8):
+    """One bias-corrected Adam step (Kingma & Ba), eps outside the square root.
+    t is the 1-based step index.  Returns the new (x, m, v)."""
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return x - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ----------------------------------------------------------------------------
+# proposal network (Sec. 6.1, Fig. 1: parameters -> network -> waveform)
+# ----------------------------------------------------------------------------
+
+def bf16_round(x):
+    """Round float64 values to the nearest bfloat16 (ties to even), returned as
+    float64.  Goes through float32 first, which is exact for values that are
+    already float32 and otherwise adds one float32 rounding."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    rnd = ((u >> 16) & 1) + 0x7FFF
+    u = ((u + rnd) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def gelu(x):
+    """Exact GELU: x * Phi(x)."""
+    return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
+
+
+def gelu_grad(x):
+    """d GELU / dx = Phi(x) + x * phi(x)."""
+    return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+
+
+def mlp_forward(x, weights, biases, emulate_bf16=True):
+    """Z_i = A_{i-1} W_i^T + b_i; A_i = GELU(Z_i) for hidden layers; the last
+    layer is linear.  With emulate_bf16 the GEMM operands (inputs, weights,
+    activations) are rounded to bfloat16 exactly where the GPU stores them in
+    bfloat16; sums are exact float64.  Returns (output, cache)."""
+    r = bf16_round if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    A = r(x)
+    acts, pres = [A], []
+    L = len(weights)
+    for i, (W, b) in enumerate(zip(weights, biases)):
+        Z = A @ r(W).T + np.asarray(b, dtype=np.float64)
+        pres.append(Z)
+        if i < L - 1:
+            A = r(gelu(Z))
+            acts.append(A)
+        else:
+            A = Z
+    return A, dict(acts=acts, pres=pres)
+
+
+def mlp_backward(dout, weights, cache, emulate_bf16=True):
+    """Gradients of the network in mlp_forward for an upstream dL/d out.
+    The upstream of every GEMM is rounded to bfloat16 where the GPU rounds it.
+    Returns (dW list, db list)."""
+    r = bf16_round if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    L = len(weights)
+    dW, db = [None] * L, [None] * L
+    dZ = np.asarray(dout, dtype=np.float64)
+    for i in range(L - 1, -1, -1):
+        dZr = r(dZ)
+        dW[i] = dZr.T @ cache["acts"][i]
+        db[i] = dZ.sum(axis=0)
+        if i > 0:
+            dA = dZr @ r(weights[i])
+            dZ = dA * gelu_grad(cache["pres"][i - 1])
+    return dW, db

@@ -1,0 +1,416 @@
+"""Pins for the float64 oracle: closed forms, identities, brute force and
+independent routes (numpy FFT, torch autograd, finite differences).
+
+Each test checks the oracle against something other than itself, so a
+dropped term, a wrong sign, a swapped index or a transposed operand in
+``oracle/`` fails at least one of them.  CPU only.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rand_complex(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def rand_unimodular(n, seed):
+    rng = np.random.default_rng(seed)
+    return np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+
+
+def fft_route(s, m, T):
+    """chi through numpy's FFT of each zero-padded lag product."""
+    n = len(s)
+    out = np.empty((2 * T + 1, m), dtype=np.complex128)
+    for i in range(2 * T + 1):
+        tau = i - T
+        r = np.zeros(m, dtype=np.complex128)
+        lo, hi = max(0, tau), min(n, n + tau)
+        r[lo:hi] = s[lo:hi] * np.conj(s[lo - tau:hi - tau])
+        out[i] = np.fft.fft(r)
+    return out
+
+
+# --------------------------------------------------------------------------
+# chi: closed forms and identities
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m", [(37, 128), (16, 16), (64, 128)])
+def test_origin_is_energy_and_peak(n, m):
+    s = rand_complex(n, 1)
+    c = O.chi(s, m)
+    E = O.energy(s)
+    T = n - 1
+    assert abs(c[T, 0] - E) <= 1e-12 * E
+    assert np.max(np.abs(c)) <= E * (1 + 1e-12)  # Cauchy-Schwarz
+
+
+def test_matches_fft_route():
+    s = rand_complex(50, 2)
+    for m, T in [(128, 49), (64, 20), (256, 0)]:
+        c = O.chi(s, m, T)
+        ref = fft_route(s, m, T)
+        assert np.max(np.abs(c - ref)) <= 1e-11 * O.energy(s)
+
+
+def test_lag_doppler_symmetry():
+    n, m = 33, 64
+    s = rand_complex(n, 3)
+    c = O.chi(s, m)
+    T = n - 1
+    taus = np.arange(-T, T + 1)
+    k = np.arange(m)
+    # chi(-tau, -k) = exp(-j 2 pi k tau / M) conj(chi(tau, k))
+    lhs = c[::-1][:, (-k) % m]
+    rhs = np.exp(-2j * np.pi * np.outer(taus, k) / m) * np.conj(c)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-11 * O.energy(s)
+
+
+@pytest.mark.parametrize("n,m", [(32, 32), (32, 64), (20, 128)])
+def test_moyal_volume(n, m):
+    s = rand_complex(n, 4)
+    c = O.chi(s, m)
+    E = O.energy(s)
+    assert abs(np.sum(np.abs(c) ** 2) - m * E * E) <= 1e-10 * m * E * E
+
+
+def test_rectangular_pulse_dirichlet():
+    n, m = 24, 64
+    s = np.ones(n, dtype=np.complex128)
+    c = O.chi(s, m)
+    T = n - 1
+    for i in range(2 * T + 1):
+        L = n - abs(i - T)
+        for k in range(m):
+            if k == 0:
+                ref = L
+            else:
+                ref = abs(math.sin(math.pi * k * L / m) / math.sin(math.pi * k / m))
+            assert abs(abs(c[i, k]) - ref) <= 1e-10 * n
+    # zero-Doppler cut is the triangle (N - |tau|) / N
+    tri = (n - np.abs(np.arange(-T, T + 1))) / n
+    assert np.allclose(np.abs(c[:, 0]) / n, tri, atol=1e-13)
+
+
+def test_unimodular_zero_lag_row_is_phase_free():
+    n, m = 40, 128
+    s = rand_unimodular(n, 5)
+    c = O.chi(s, m)
+    row = np.abs(c[n - 1])
+    k = np.arange(1, m)
+    ref = np.abs(np.sin(np.pi * k * n / m) / np.sin(np.pi * k / m))
+    assert abs(row[0] - n) < 1e-10
+    assert np.max(np.abs(row[1:] - ref)) < 1e-10
+
+
+def test_barker13_golden():
+    code = abs_acf = None
+    with open(os.path.join(HERE, "golden", "barker13.txt")) as f:
+        for line in f:
+            if line.startswith("code:"):
+                code = np.array([float(x) for x in line.split()[1:]])
+            elif line.startswith("abs_acf:"):
+                abs_acf = np.array([float(x) for x in line.split()[1:]])
+    s = code.astype(np.complex128)
+    c = O.chi(s, 32)
+    cut = np.abs(c[:, 0])
+    T = 12
+    assert np.allclose(cut[T:], abs_acf, atol=1e-12)
+    assert np.allclose(cut[:T + 1][::-1], abs_acf, atol=1e-12)
+    # PSL of the zero-Doppler cut: 1/13 in amplitude = -22.3 dB
+    side = np.ones(2 * T + 1, dtype=bool)
+    side[T] = False
+    assert abs(20 * math.log10(cut[side].max() / 13.0) - (-22.2788)) < 1e-3
+
+
+def test_invariances():
+    n, m = 21, 64
+    s = rand_complex(n, 6)
+    a = np.abs(O.chi(s, m))
+    k = np.arange(m)
+    # global phase: chi unchanged
+    assert np.allclose(O.chi(s * np.exp(0.7j), m), O.chi(s, m), atol=1e-11)
+    # a frequency offset only adds a lag-dependent phase: |chi| unchanged
+    k0 = 5
+    sm = s * np.exp(2j * np.pi * k0 * np.arange(n) / m)
+    assert np.allclose(np.abs(O.chi(sm, m)), a, atol=1e-11)
+    # a quadratic phase exp(j pi c n^2 / M) shears it: row tau moves by c*tau bins
+    c = 3
+    sq = s * np.exp(1j * np.pi * c * np.arange(n) ** 2 / m)
+    aq = np.abs(O.chi(sq, m))
+    for i, tau in enumerate(range(-(n - 1), n)):
+        assert np.allclose(aq[i], a[i, (k - c * tau) % m], atol=1e-11)
+    # conjugation flips Doppler
+    assert np.allclose(np.abs(O.chi(np.conj(s), m)), a[:, (-k) % m], atol=1e-11)
+    # time reversal keeps |chi|
+    assert np.allclose(np.abs(O.chi(s[::-1].copy(), m)), a, atol=1e-11)
+
+
+def test_lag_window_is_subgrid():
+    n, m = 30, 64
+    s = rand_complex(n, 7)
+    full = O.chi(s, m)
+    win = O.chi(s, m, 7)
+    assert np.array_equal(win, full[n - 1 - 7:n - 1 + 8])
+
+
+# --------------------------------------------------------------------------
+# losses
+# --------------------------------------------------------------------------
+
+def test_isl_full_grid_moyal_pin():
+    # uniform-weight ISL over the full grid = M - sum over the mainlobe of p
+    n, m = 32, 64
+    s = rand_unimodular(n, 8)
+    c = O.chi(s, m)
+    E = O.energy(s)
+    t = O.loss_terms(c, E, n, O.LossParams(h_tau=1, h_k=1))
+    main = O.mainlobe_mask(m, n - 1, 1, 1)
+    assert abs(t["isl"] - (m - np.sum(O.power(c, E)[main]))) < 1e-9
+
+
+def test_zero_lag_neighbour_power_at_m_2n():
+    n, m = 256, 512
+    s = rand_unimodular(n, 9)
+    c = O.chi(s, m, 0)
+    p = O.power(c, O.energy(s))
+    exact = (math.sin(math.pi * n / m) / (n * math.sin(math.pi / m))) ** 2
+    assert abs(p[0, 1] - exact) < 1e-12
+    assert abs(exact - (2 / math.pi) ** 2) < 1e-4
+
+
+def test_softpsl_bounds_and_limit():
+    n, m = 24, 64
+    s = rand_unimodular(n, 10)
+    c = O.chi(s, m)
+    E = O.energy(s)
+    for temp in [0.05, 0.01, 0.001]:
+        t = O.loss_terms(c, E, n, O.LossParams(temp=temp, w_psl=1.0))
+        amax = t["a"][t["side"]].max()
+        count = int(t["side"].sum())
+        assert amax - 1e-12 <= t["softpsl"] <= amax + temp * math.log(count) + 1e-12
+    t = O.loss_terms(c, E, n, O.LossParams(temp=1e-4, w_psl=1.0))
+    assert abs(t["softpsl"] - t["a"][t["side"]].max()) < 1e-3
+
+
+def test_weighted_isl_brute_force():
+    n, m, T = 12, 32, 11
+    rng = np.random.default_rng(11)
+    u, v = rng.uniform(size=31), rng.uniform(size=31)
+    s = rand_unimodular(n, 11)
+    c = O.chi(s, m)
+    E = O.energy(s)
+    t = O.loss_terms(c, E, n, O.LossParams(h_tau=2, h_k=3, u=u, v=v))
+    ref = 0.0
+    for i in range(2 * T + 1):
+        tau = i - T
+        for k in range(m):
+            kc = k - m if k >= m // 2 else k
+            if abs(tau) <= 2 and abs(kc) <= 3:
+                continue
+            w = u[(31 * abs(tau)) // n] * v[(31 * abs(kc)) // (m // 2 + 1)]
+            ref += w * abs(c[i, k]) ** 2 / E ** 2
+    assert abs(t["isl"] - ref) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# gradients
+# --------------------------------------------------------------------------
+
+def _loss_value(s, m, T, params):
+    return O.loss_terms(O.chi(s, m, T), O.energy(s), len(s), params)["loss"]
+
+
+def _fd_grad(f, s, h=1e-6):
+    g = np.zeros(len(s), dtype=np.complex128)
+    for p in range(len(s)):
+        e = np.zeros(len(s), dtype=np.complex128)
+        e[p] = h
+        dx = (f(s + e) - f(s - e)) / (2 * h)
+        dy = (f(s + 1j * e) - f(s - 1j * e)) / (2 * h)
+        g[p] = 0.5 * (dx + 1j * dy)
+    return g
+
+
+CASES = [
+    dict(w_isl=1.0, w_psl=0.0),
+    dict(w_isl=0.0, w_psl=1.0, temp=0.05),
+    dict(w_isl=1.0, w_psl=1.0, temp=0.05),
+    dict(w_isl=0.7, w_psl=0.3, temp=0.2, h_tau=2, h_k=2, weighted=True),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("n,m,T", [(8, 16, 7), (13, 32, 12), (16, 32, 5)])
+def test_loss_grad_finite_differences(case, n, m, T):
+    case = dict(case)
+    if case.pop("weighted", False):
+        rng = np.random.default_rng(12)
+        case.update(u=rng.uniform(size=31), v=rng.uniform(size=31))
+    params = O.LossParams(**case)
+    s = rand_complex(n, 13)
+    g = O.loss_and_grad(s, m, T, params)["g"]
+    fd = _fd_grad(lambda x: _loss_value(x, m, T, params), s)
+    assert np.max(np.abs(g - fd)) <= 1e-6 * max(1.0, np.max(np.abs(fd)))
+
+
+def test_magnitude_backward_finite_differences():
+    n, m, T, eps = 11, 32, 10, 1e-12
+    s = rand_complex(n, 14)
+    ga = np.random.default_rng(15).standard_normal((2 * T + 1, m))
+    g = O.magnitude_backward(s, m, T, ga, eps)
+
+    def f(x):
+        return float(np.sum(ga * O.magnitude(O.chi(x, m, T), O.energy(x), eps)))
+
+    fd = _fd_grad(f, s)
+    assert np.max(np.abs(g - fd)) <= 1e-6 * np.max(np.abs(fd))
+
+
+def test_adjoint_dot_product_exact():
+    # L = 2 Re <G, chi(s)>: dL/d conj(s) = adjoint(G); chi is quadratic in
+    # (s, conj s), so a central difference of chi is exact up to rounding.
+    n, m, T = 19, 64, 12
+    s = rand_complex(n, 16)
+    d = rand_complex(n, 17)
+    rng = np.random.default_rng(18)
+    G = rng.standard_normal((2 * T + 1, m)) + 1j * rng.standard_normal((2 * T + 1, m))
+    g = O.grad_from_upstream(s, m, T, G, 0.0)
+    t = 0.5
+    dchi = (O.chi(s + t * d, m, T) - O.chi(s - t * d, m, T)) / (2 * t)
+    lhs = 2 * np.real(np.vdot(g, d))
+    rhs = 2 * np.real(np.vdot(G, dchi))
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+
+
+@pytest.mark.parametrize("case", CASES[:3])
+def test_normalised_loss_gradient_orthogonal_to_s(case):
+    # scale and phase invariance of normalised losses: sum conj(s) g = 0
+    n, m = 64, 128
+    s = rand_complex(n, 19)
+    g = O.loss_and_grad(s, m, n - 1, O.LossParams(**case))["g"]
+    assert abs(np.vdot(s, g)) <= 1e-10 * np.linalg.norm(s) * np.linalg.norm(g)
+
+
+def test_torch_autograd_route():
+    # torch's .grad of a real loss w.r.t. a complex leaf is 2 dL/d conj(s)
+    n, m, T = 24, 64, 23
+    params = O.LossParams(w_isl=1.0, w_psl=0.5, temp=0.1, h_tau=1, h_k=1)
+    s = rand_complex(n, 20)
+    g = O.loss_and_grad(s, m, T, params)["g"]
+
+    st = torch.tensor(s, dtype=torch.complex128, requires_grad=True)
+    E = (st.abs() ** 2).sum()
+    rows = []
+    for tau in range(-T, T + 1):
+        lo, hi = max(0, tau), min(n, n + tau)
+        r = torch.zeros(m, dtype=torch.complex128)
+        r = r.index_put((torch.arange(lo, hi),), st[lo:hi] * torch.conj(st[lo - tau:hi - tau]))
+        rows.append(torch.fft.fft(r))
+    c = torch.stack(rows)
+    p = (c.abs() ** 2) / E ** 2
+    a = torch.sqrt(p + params.eps)
+    side = torch.tensor(~O.mainlobe_mask(m, T, 1, 1))
+    isl = p[side].sum()
+    soft = params.temp * torch.logsumexp(a[side] / params.temp, dim=0)
+    (params.w_isl * isl + params.w_psl * soft).backward()
+    assert np.max(np.abs(st.grad.numpy() / 2 - g)) <= 1e-9 * np.max(np.abs(g))
+
+
+def test_phase_grad_chain():
+    n, m = 16, 32
+    phi = np.random.default_rng(21).uniform(0, 2 * np.pi, n)
+    params = O.LossParams(w_isl=1.0, w_psl=1.0)
+
+    def f(ph):
+        return _loss_value(np.exp(1j * ph), m, n - 1, params)
+
+    s = np.exp(1j * phi)
+    dphi = O.phase_grad(s, O.loss_and_grad(s, m, n - 1, params)["g"])
+    h = 1e-6
+    fd = np.array([(f(phi + h * e) - f(phi - h * e)) / (2 * h) for e in np.eye(n)])
+    assert np.max(np.abs(dphi - fd)) <= 1e-6 * np.max(np.abs(fd))
+
+
+# --------------------------------------------------------------------------
+# optimiser and network
+# --------------------------------------------------------------------------
+
+def test_adam_matches_torch():
+    rng = np.random.default_rng(22)
+    x0 = rng.standard_normal(10)
+    grads = [rng.standard_normal(10) for _ in range(5)]
+    xt = torch.tensor(x0, requires_grad=True)
+    opt = torch.optim.Adam([xt], lr=0.01, betas=(0.9, 0.999), eps=1e-8)
+    x, m, v = x0.copy(), np.zeros(10), np.zeros(10)
+    for t, gr in enumerate(grads, start=1):
+        opt.zero_grad()
+        xt.grad = torch.tensor(gr)
+        opt.step()
+        x, m, v = O.adam_step(x, gr, m, v, t)
+    assert np.max(np.abs(x - xt.detach().numpy())) < 1e-14
+
+
+def test_adam_first_step_is_signed_lr():
+    x, m, v = O.adam_step(np.zeros(3), np.array([2.0, -3.0, 0.5]), np.zeros(3), np.zeros(3), 1)
+    assert np.allclose(x, -0.01 * np.sign([2.0, -3.0, 0.5]), atol=1e-9)
+
+
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(23)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-5, 5, 10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 65504.0]])
+    x32 = x.astype(np.float32)
+    ref = torch.tensor(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(O.bf16_round(x32), ref)
+
+
+def test_gelu_and_grad():
+    x = np.linspace(-6, 6, 101)
+    xt = torch.tensor(x, requires_grad=True)
+    y = torch.nn.functional.gelu(xt)
+    y.sum().backward()
+    assert np.max(np.abs(O.gelu(x) - y.detach().numpy())) < 1e-14
+    assert np.max(np.abs(O.gelu_grad(x) - xt.grad.numpy())) < 1e-14
+
+
+def test_mlp_backward_matches_torch_and_fd():
+    rng = np.random.default_rng(24)
+    sizes = [6, 8, 8, 5]
+    Ws = [rng.standard_normal((sizes[i + 1], sizes[i])) * 0.5 for i in range(3)]
+    bs = [rng.standard_normal(sizes[i + 1]) * 0.1 for i in range(3)]
+    x = rng.standard_normal((4, 6))
+    up = rng.standard_normal((4, 5))
+    out, cache = O.mlp_forward(x, Ws, bs, emulate_bf16=False)
+    dW, db = O.mlp_backward(up, Ws, cache, emulate_bf16=False)
+
+    Wt = [torch.tensor(w, requires_grad=True) for w in Ws]
+    bt = [torch.tensor(b, requires_grad=True) for b in bs]
+    a = torch.tensor(x)
+    for i in range(3):
+        a = a @ Wt[i].T + bt[i]
+        if i < 2:
+            a = torch.nn.functional.gelu(a)
+    assert np.max(np.abs(a.detach().numpy() - out)) < 1e-13
+    (a * torch.tensor(up)).sum().backward()
+    for i in range(3):
+        assert np.max(np.abs(dW[i] - Wt[i].grad.numpy())) < 1e-12
+        assert np.max(np.abs(db[i] - bt[i].grad.numpy())) < 1e-12
+    # finite difference on one weight
+    h = 1e-6
+    Wp = [w.copy() for w in Ws]
+    Wp[1][2, 3] += h
+    Wm = [w.copy() for w in Ws]
+    Wm[1][2, 3] -= h
+    fp = np.sum(O.mlp_forward(x, Wp, bs, False)[0] * up)
+    fm = np.sum(O.mlp_forward(x, Wm, bs, False)[0] * up)
+    assert abs((fp - fm) / (2 * h) - dW[1][2, 3]) < 1e-7
