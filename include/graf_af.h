@@ -1,0 +1,172 @@
+/*
+ * graf_af.h -- C ABI of the MI355X differentiable ambiguity-function library
+ * (libgraf_af.so).
+ *
+ * What is computed (paper "Differentiable Radar Ambiguity Functions", Sec. 4.1,
+ * Eqs. 7-12, with aperiodic lags and the library FFT sign):
+ *
+ *   chi[tau, k] = sum_n s[n] conj(s[n - tau]) exp(-j 2 pi k n / M)
+ *
+ * for a complex waveform s of N samples (s[n] = 0 outside [0, N)), lags
+ * tau in [-T, T] and Doppler bins k in [0, M).  The energy E = sum |s|^2 is the
+ * value of chi at the origin and its maximum, so it is the normaliser of
+ * Sec. 4.3 (Eq. 17).  The library returns the eps-stabilised magnitude
+ *
+ *   a[tau, k] = sqrt(|chi[tau, k]|^2 / E^2 + eps)
+ *
+ * and the conjugate Wirtinger gradient dL/d conj(s) (Sec. 3.3 Eq. 6, Sec. 4.2
+ * Eqs. 13-15) of either a user loss given through dL/da, or the built-in loss
+ *
+ *   L = w_isl * ISL + w_psl * softPSL
+ *   ISL     = sum over Omega_s of W[tau, k] |chi|^2 / E^2        (Eq. 19)
+ *   softPSL = T_psl * log sum over Omega_s of exp(a / T_psl)     (smooth Eq. 18)
+ *
+ * where Omega_s is every cell outside the mainlobe |tau| <= h_tau, |k_c| <= h_k
+ * (k_c = ((k + M/2) mod M) - M/2) and W is 1, or the separable shaping weight
+ * u[floor(31 |tau| / N)] * v[floor(31 |k_c| / (M/2 + 1))] from 62 floats per
+ * waveform (u = first 31, v = last 31).
+ *
+ * Conventions
+ *  - Every pointer argument named "device" is device memory owned by the
+ *    caller; the library never frees it.  Host structs are read during the
+ *    call only.
+ *  - complex64 = interleaved (re, im) float32.  A batch packs its waveforms
+ *    into one complex64 array; waveform b starts at element waves[b].s_off.
+ *  - Grids are row-major [2T+1][M] float32 (or complex64) starting at element
+ *    waves[b].grid_off; row i holds tau = i - T, bins in natural DFT order
+ *    (the centring of Algorithm 1, step 5, is left to the caller).
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  The status reports host-side validation and launch errors only.
+ *  - Compute calls allocate nothing and never synchronise, so they can be
+ *    captured in a HIP graph.  They use the caller's workspace; calls on one
+ *    plan must not overlap in time (they share the plan's work-queue counters).
+ *  - No exception crosses the ABI.  Zero energy gives NaN results, as 0/0.
+ */
+#ifndef GRAF_AF_H
+#define GRAF_AF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AF_OK = 0,
+    AF_ERR_INVALID_ARG = -1, /* null pointer, bad size, bad offset */
+    AF_ERR_UNSUPPORTED = -2, /* M not a power of two, M < 2N, M > 32768, N too long for M */
+    AF_ERR_BUDGET = -3,      /* workspace cannot fit the budget even with recomputation */
+    AF_ERR_HIP = -4,         /* a HIP runtime call failed */
+    AF_ERR_WORKSPACE = -5,   /* workspace smaller than af_plan_workspace_size */
+    AF_ERR_NO_DEVICE = -6    /* no usable gfx950 device */
+} af_status;
+
+/* One waveform of a batch. */
+typedef struct {
+    int32_t n;        /* samples, >= 1 */
+    int32_t m;        /* Doppler bins: power of two with 2n <= m, 128 <= m <= 32768 */
+    int32_t max_lag;  /* T: lags -T..T with 0 <= T <= n - 1; -1 means n - 1 */
+    int32_t h_tau;    /* mainlobe half-width in lags (built-in loss only) */
+    int32_t h_k;      /* mainlobe half-width in Doppler bins (built-in loss only) */
+    int32_t reserved; /* must be 0 */
+    int64_t s_off;    /* first complex64 sample of this waveform in the packed input */
+    int64_t grid_off; /* first element of this waveform's [2T+1][M] grids */
+} af_wave;
+
+/* Plan options (zero-initialise, then set what you need). */
+typedef struct {
+    float eps;                 /* eps in a = sqrt(p + eps); e.g. 1e-12 */
+    int32_t store_mode;        /* 0: decide by budget, 1: store spectra, 2: recompute */
+    int64_t budget_bytes;      /* workspace budget; <= 0 means unlimited */
+    int32_t variant;           /* -1: library default; >= 0 forces a kernel variant */
+    int32_t segment_iters;     /* lag iterations per work item; 0: planner's choice */
+} af_plan_opts;
+
+typedef struct af_plan af_plan;
+
+/* Built-in loss parameters (Sec. 5.1).  band_w: device float[batch][62] or NULL. */
+typedef struct {
+    float w_isl;
+    float w_psl;
+    float psl_temp; /* > 0 */
+    const float* band_w;
+} af_loss_params;
+
+/* Adam settings for af_optim_step (Kingma & Ba; eps outside the square root). */
+typedef struct {
+    float lr, beta1, beta2, eps;
+} af_adam_params;
+
+/* Plan summary for callers and benchmarks. */
+typedef struct {
+    int64_t cells;          /* sum over waveforms of (2T+1) * M */
+    int64_t store_bytes;    /* bytes of stored spectra when storing */
+    int64_t workspace_bytes;
+    int32_t segments;       /* work items */
+    int32_t grid;           /* persistent work groups launched */
+    int32_t variant;        /* kernel variant in use */
+    int32_t stores;         /* 1 when the backward reads stored spectra */
+} af_plan_summary;
+
+/* Create a plan for `batch` waveforms (host array `waves`).  Validates every
+ * waveform, chooses a kernel variant and a work split, decides store versus
+ * recompute against the budget, and uploads small device tables (twiddles,
+ * work list).  May call hipMalloc; not capturable.  On error *out is NULL. */
+af_status af_plan_create(int32_t batch, const af_wave* waves, const af_plan_opts* opts, af_plan** out);
+void af_plan_destroy(af_plan* plan);
+
+/* Bytes of caller-allocated device workspace the compute calls need. */
+af_status af_plan_workspace_size(const af_plan* plan, size_t* bytes);
+af_status af_plan_get_summary(const af_plan* plan, af_plan_summary* out);
+
+/* Re-pick the kernel variant by timing every candidate on this plan's shapes
+ * (forward + fused loss) with the given device inputs; synchronises `stream`.
+ * ws must hold af_plan_workspace_size bytes for every candidate, which the
+ * function checks.  Not capturable. */
+af_status af_plan_autotune(af_plan* plan, const void* s, void* ws, size_t ws_bytes, void* stream,
+                           int32_t* chosen_variant, float* best_ms);
+
+/* Forward (Sec. 4.1).  s: device complex64 input.  mag: device float32 grids
+ * of a (nullable).  chi: device complex64 grids of chi (nullable).  energy:
+ * device float[batch] of E (nullable).  When the plan stores spectra, the
+ * forward also leaves them in ws for af_backward. */
+af_status af_forward(const af_plan* plan, const void* s, float* mag, void* chi, float* energy, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Backward for a user loss (Sec. 4.2): grad_mag holds dL/da on the grids
+ * (device float32); grad_s receives dL/d conj(s) (device complex64, packed like
+ * s).  In store mode it reads the spectra the last af_forward on this plan
+ * left in the same ws; otherwise it recomputes them from s. */
+af_status af_backward(const af_plan* plan, const void* s, const float* grad_mag, void* grad_s, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Built-in loss forward and backward.  terms: device float[batch][4] receiving
+ * (L, ISL, softPSL, E) per waveform (nullable).  mag (nullable): the a grids.
+ * grad_s (nullable: loss only): dL/d conj(s).  With w_psl == 0 one fused pass
+ * does everything; with w_psl != 0 a forward pass finds the soft-PSL
+ * normaliser first. */
+af_status af_loss(const af_plan* plan, const void* s, const af_loss_params* loss, float* terms, float* mag,
+                  void* grad_s, void* ws, size_t ws_bytes, void* stream);
+
+/* s[i] = exp(j phi[i]) for i < count (device arrays). */
+af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream);
+
+/* One optimiser step on phases (Sec. 6.2 update, Sec. 7.1.2 optimiser):
+ * loss and dL/d conj(s) at s, dL/dphi = 2 Im(conj(s) dL/d conj(s)), one Adam
+ * step on phi (with m, v and the device int step counter, incremented on the
+ * device), and s <- exp(j phi) in place.  s must equal exp(j phi) on entry
+ * (af_phase_to_signal once before the first step).  terms: device
+ * float[batch][4] (nullable) gets the loss terms at the entry point. */
+af_status af_optim_step(const af_plan* plan, float* phi, float* adam_m, float* adam_v, void* s, int32_t* step,
+                        const af_loss_params* loss, const af_adam_params* adam, float* terms, void* ws,
+                        size_t ws_bytes, void* stream);
+
+const char* af_status_string(af_status status);
+int32_t af_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAF_AF_H */

@@ -24,9 +24,9 @@ from . import _native
 __all__ = [
     "to_c64_exact", "energy", "chi", "magnitude", "power",
     "centred_bins", "mainlobe_mask", "isl_weights", "LossParams", "loss_terms",
-    "loss_and_grad", "magnitude_backward", "grad_from_upstream", "phase_grad",
+    "loss_and_grad", "loss_grad_from_chi", "magnitude_backward", "grad_from_upstream", "phase_grad",
     "adam_step", "bf16_round", "gelu", "gelu_grad", "mlp_forward",
-    "mlp_backward", "psl_db",
+    "mlp_backward", "psl_db", "chi_rows_fft", "magnitude_backward_fft",
 ]
 
 
@@ -152,8 +152,15 @@ def loss_and_grad(s, m, max_lag, params):
     s = np.asarray(s, dtype=np.complex128)
     n = s.shape[0]
     T = n - 1 if max_lag is None or max_lag < 0 else int(max_lag)
+    return loss_grad_from_chi(s, m, T, chi(s, m, T), params)
+
+
+def loss_grad_from_chi(s, m, T, c, params):
+    """loss_and_grad with the complex grid c supplied (c = chi(s) for the
+    reference; tests pass a perturbed grid to measure conditioning)."""
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
     E = energy(s)
-    c = chi(s, m, T)
     t = loss_terms(c, E, n, params)
     a, p, side, W = t["a"], t["p"], t["side"], t["W"]
     q = np.zeros_like(a)
@@ -272,3 +279,54 @@ def mlp_backward(dout, weights, cache, emulate_bf16=True):
             dA = dZr @ r(weights[i])
             dZ = dA * gelu_grad(cache["pres"][i - 1])
     return dW, db
+
+
+# ----------------------------------------------------------------------------
+# the same definitions with numpy's FFT as the Doppler-sum step, for sizes the
+# direct sums cannot reach in seconds (pinned against the direct sums by tests)
+# ----------------------------------------------------------------------------
+
+def _lag_product(s, m, tau):
+    n = s.shape[0]
+    r = np.zeros(m, dtype=np.complex128)
+    lo, hi = max(0, tau), min(n, n + tau)
+    r[lo:hi] = s[lo:hi] * np.conj(s[lo - tau:hi - tau])
+    return r, lo, hi
+
+
+def chi_rows_fft(s, m, taus):
+    """chi rows for the given lags: the Doppler sum of Eq. 11 by FFT."""
+    s = np.asarray(s, dtype=np.complex128)
+    out = np.empty((len(taus), m), dtype=np.complex128)
+    for i, tau in enumerate(taus):
+        out[i] = np.fft.fft(_lag_product(s, m, int(tau))[0])
+    return out
+
+
+def magnitude_backward_fft(s, m, max_lag, grad_mag, eps, rows_per_block=64):
+    """magnitude_backward with FFT steps, streamed over lag rows: per row
+    chi = FFT(r), G = g_a chi / (2 E^2 a), Q = M * IFFT(G), then the two
+    adjoint terms of the lag product and the energy term."""
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
+    T = int(max_lag)
+    E = energy(s)
+    g = np.zeros(n, dtype=np.complex128)
+    dLdE = 0.0
+    for i0 in range(0, 2 * T + 1, rows_per_block):
+        i1 = min(2 * T + 1, i0 + rows_per_block)
+        for i in range(i0, i1):
+            tau = i - T
+            r, lo, hi = _lag_product(s, m, tau)
+            c = np.fft.fft(r)
+            p = power(c, E)
+            a = np.sqrt(p + eps)
+            ga = np.asarray(grad_mag[i], dtype=np.float64)
+            G = ga * c / (2.0 * E * E * a)
+            dLdE -= float(np.sum(ga * p / (E * a)))
+            Q = np.fft.ifft(G) * m
+            # Q_tau[p] s[p - tau] for p in [lo, hi)
+            g[lo:hi] += Q[lo:hi] * s[lo - tau:hi - tau]
+            # conj(Q_tau[q]) s[q] added at p = q - tau for q in [lo, hi)
+            g[lo - tau:hi - tau] += np.conj(Q[lo:hi]) * s[lo:hi]
+    return g + dLdE * s

@@ -1,0 +1,212 @@
+"""Python face of libgraf_af.so: plans, the three AF calls and the phase
+optimiser step, on torch device tensors.  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels.
+
+Conventions (see include/graf_af.h): packed complex64 waveforms, packed
+float32 grids [2T+1][M] per waveform, gradients as dL/d conj(s).
+"""
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_DEV = "cuda"
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+class Plan:
+    """A batch layout: per waveform N, M, lag half-width T and mainlobe
+    half-widths.  Waveforms pack back to back in s; grids pack back to back.
+    """
+
+    def __init__(self, lengths, ms, max_lags=None, h_tau=1, h_k=1, eps=1e-12, store_mode=0,
+                 budget_bytes=0, variant=-1, segment_iters=0):
+        lengths = [int(n) for n in lengths]
+        ms = [int(m) for m in ms]
+        B = len(lengths)
+        if len(ms) != B:
+            raise ValueError("lengths and ms differ in length")
+        max_lags = [n - 1 for n in lengths] if max_lags is None else [int(t) for t in max_lags]
+        max_lags = [n - 1 if t < 0 else t for n, t in zip(lengths, max_lags)]
+        h_tau = [int(h_tau)] * B if isinstance(h_tau, int) else [int(x) for x in h_tau]
+        h_k = [int(h_k)] * B if isinstance(h_k, int) else [int(x) for x in h_k]
+        waves = (L.AfWave * B)()
+        s_off = g_off = 0
+        self.s_offsets, self.grid_offsets, self.rows = [], [], []
+        for b in range(B):
+            w = waves[b]
+            w.n, w.m, w.max_lag = lengths[b], ms[b], max_lags[b]
+            w.h_tau, w.h_k, w.reserved = h_tau[b], h_k[b], 0
+            w.s_off, w.grid_off = s_off, g_off
+            self.s_offsets.append(s_off)
+            self.grid_offsets.append(g_off)
+            self.rows.append(2 * max_lags[b] + 1)
+            s_off += lengths[b]
+            g_off += (2 * max_lags[b] + 1) * ms[b]
+        self.batch, self.lengths, self.ms, self.max_lags = B, lengths, ms, max_lags
+        self.total_samples, self.total_cells = s_off, g_off
+        opts = L.AfPlanOpts(eps=float(eps), store_mode=int(store_mode), budget_bytes=int(budget_bytes),
+                            variant=int(variant), segment_iters=int(segment_iters))
+        h = ctypes.c_void_p()
+        L.check("af_plan_create", L.lib().af_plan_create(B, waves, ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._refresh()
+
+    def _refresh(self):
+        sz = ctypes.c_size_t()
+        L.check("af_plan_workspace_size", L.lib().af_plan_workspace_size(self._h, ctypes.byref(sz)))
+        self.workspace_bytes = int(sz.value)
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                L.lib().af_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # ------------------------------------------------------------------
+    def summary(self):
+        s = L.AfPlanSummary()
+        L.check("af_plan_get_summary", L.lib().af_plan_get_summary(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in L.AfPlanSummary._fields_}
+
+    def new_workspace(self):
+        return torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=_DEV)
+
+    @property
+    def workspace(self):
+        if self._ws is None or self._ws.numel() < self.workspace_bytes:
+            self._ws = self.new_workspace()
+        return self._ws
+
+    def grid(self, flat, b):
+        """View of waveform b's [2T+1, M] grid inside a packed grid tensor."""
+        o = self.grid_offsets[b]
+        return flat[o:o + self.rows[b] * self.ms[b]].view(self.rows[b], self.ms[b])
+
+    def owner_index(self, device):
+        """int64[total_samples]: the waveform each packed sample belongs to."""
+        if getattr(self, "_owner", None) is None or self._owner.device != torch.device(device):
+            self._owner = torch.repeat_interleave(torch.arange(self.batch, device=device),
+                                                  torch.tensor(self.lengths, device=device))
+        return self._owner
+
+    def signal(self, flat, b):
+        o = self.s_offsets[b]
+        return flat[o:o + self.lengths[b]]
+
+    def autotune(self, s):
+        _need(s, torch.complex64, "s")
+        ws = torch.empty(max(self.workspace_bytes * 4, 1 << 20), dtype=torch.uint8, device=_DEV)
+        v = ctypes.c_int32()
+        ms = ctypes.c_float()
+        L.check("af_plan_autotune", L.lib().af_plan_autotune(self._h, _ptr(s), _ptr(ws), ws.numel(), _stream(),
+                                                              ctypes.byref(v), ctypes.byref(ms)))
+        self._refresh()
+        return int(v.value), float(ms.value)
+
+    # ------------------------------------------------------------------
+    def forward(self, s, mag=True, chi=False, ws=None, out_mag=None):
+        """Returns (a grids float32 or None, chi complex64 or None, E float32[B])."""
+        _need(s, torch.complex64, "s")
+        ws = self.workspace if ws is None else ws
+        m = None
+        if mag:
+            m = out_mag if out_mag is not None else torch.empty(self.total_cells, dtype=torch.float32, device=_DEV)
+        c = torch.empty(self.total_cells, dtype=torch.complex64, device=_DEV) if chi else None
+        e = torch.empty(self.batch, dtype=torch.float32, device=_DEV)
+        L.check("af_forward", L.lib().af_forward(self._h, _ptr(s), _ptr(m), _ptr(c), _ptr(e), _ptr(ws),
+                                                 ws.numel(), _stream()))
+        return m, c, e
+
+    def backward(self, s, grad_mag, ws=None, out=None):
+        """dL/d conj(s) for an upstream dL/da (packed float32 grids)."""
+        _need(s, torch.complex64, "s")
+        _need(grad_mag, torch.float32, "grad_mag")
+        ws = self.workspace if ws is None else ws
+        g = out if out is not None else torch.empty(self.total_samples, dtype=torch.complex64, device=_DEV)
+        L.check("af_backward", L.lib().af_backward(self._h, _ptr(s), _ptr(grad_mag), _ptr(g), _ptr(ws),
+                                                   ws.numel(), _stream()))
+        return g
+
+    @staticmethod
+    def loss_params(w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None):
+        if band_w is not None:
+            _need(band_w, torch.float32, "band_w")
+        p = L.AfLossParams(w_isl=float(w_isl), w_psl=float(w_psl), psl_temp=float(temp),
+                           band_w=None if band_w is None else band_w.data_ptr())
+        p._keep = band_w  # keep the tensor alive while the struct is in use
+        return p
+
+    def loss(self, s, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, grad=True, mag=False, ws=None,
+             out_terms=None, out_grad=None):
+        """Built-in loss.  Returns (terms float32[B,4] = (L, ISL, softPSL, E),
+        dL/d conj(s) or None, a grids or None)."""
+        _need(s, torch.complex64, "s")
+        ws = self.workspace if ws is None else ws
+        lp = self.loss_params(w_isl, w_psl, temp, band_w)
+        t = out_terms if out_terms is not None else torch.empty(self.batch, 4, dtype=torch.float32, device=_DEV)
+        g = None
+        if grad:
+            g = out_grad if out_grad is not None else torch.empty(self.total_samples, dtype=torch.complex64,
+                                                                 device=_DEV)
+        m = torch.empty(self.total_cells, dtype=torch.float32, device=_DEV) if mag else None
+        L.check("af_loss", L.lib().af_loss(self._h, _ptr(s), ctypes.byref(lp), _ptr(t), _ptr(m), _ptr(g),
+                                           _ptr(ws), ws.numel(), _stream()))
+        return t, g, m
+
+    def optim_step(self, state, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, lr=0.01, betas=(0.9, 0.999),
+                   eps=1e-8, ws=None, terms=None):
+        """One Adam step on the phases held in `state` (see PhaseState)."""
+        ws = self.workspace if ws is None else ws
+        lp = self.loss_params(w_isl, w_psl, temp, band_w)
+        ad = L.AfAdamParams(lr=float(lr), beta1=float(betas[0]), beta2=float(betas[1]), eps=float(eps))
+        L.check("af_optim_step", L.lib().af_optim_step(
+            self._h, _ptr(state.phi), _ptr(state.m), _ptr(state.v), _ptr(state.s), _ptr(state.step),
+            ctypes.byref(lp), ctypes.byref(ad), _ptr(terms), _ptr(ws), ws.numel(), _stream()))
+
+
+class PhaseState:
+    """Phases, Adam moments, the device step counter and s = exp(j phi)."""
+
+    def __init__(self, phi):
+        _need(phi, torch.float32, "phi")
+        self.phi = phi
+        self.m = torch.zeros_like(phi)
+        self.v = torch.zeros_like(phi)
+        self.step = torch.zeros(1, dtype=torch.int32, device=phi.device)
+        self.s = torch.empty(phi.numel(), dtype=torch.complex64, device=phi.device)
+        phase_to_signal(self.phi, self.s)
+
+
+def phase_to_signal(phi, s):
+    _need(phi, torch.float32, "phi")
+    _need(s, torch.complex64, "s")
+    L.check("af_phase_to_signal", L.lib().af_phase_to_signal(_ptr(phi), _ptr(s), phi.numel(), _stream()))
+    return s
+
+
+def single(n, m=None, max_lag=-1, **kw):
+    """Plan for one waveform of n samples (M defaults to 2n rounded up to a power of two)."""
+    m = m or 1 << (2 * n - 1).bit_length()
+    return Plan([n], [m], [max_lag], **kw)

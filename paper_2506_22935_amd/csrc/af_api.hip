@@ -1,0 +1,656 @@
+// Host side of libgraf_af.so: argument validation, the work planner
+// (segments, longest-first order, store-versus-recompute under a budget),
+// the variant autotuner and the launch sequences behind the C ABI declared
+// in include/graf_af.h.
+#include "../../include/graf_af.h"
+#include "af_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using graf::AfArgs;
+using graf::ReduceArgs;
+using graf::SegDesc;
+using graf::VariantInfo;
+using graf::WaveDesc;
+
+namespace {
+
+constexpr int kMaxLds = 160 * 1024;
+constexpr int kMinM = 128;
+constexpr int kMaxM = 32768;
+constexpr int kCtrlWords = 64;  // 2 per size class + 2 for the optimiser step
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int64_t x) {
+    int r = 0;
+    while ((int64_t(1) << r) < x) ++r;
+    return r;
+}
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct af_plan {
+    int device = -1;
+    int cus = 0;
+    int batch = 0;
+    std::vector<af_wave> waves;
+    float eps = 0.f;
+    int store_mode = 0;
+    int64_t budget = 0;
+    int seg_iters_opt = 0;
+
+    // schedule: one class per distinct M, each with its own kernel variant,
+    // slice of the execution order, grid and work-queue counters
+    struct Class {
+        int lg = 0;          // log2(M/2)
+        int variant = -1;
+        int begin = 0, count = 0;  // slice of the execution order
+        int grid[4] = {0, 0, 0, 0};
+        int dyn_lds = 0;
+        int max_n = 0;
+        double cost = 0.0;
+    };
+    std::vector<Class> classes;
+    std::vector<int> forced;  // per class: variant forced by the autotuner (-1: default)
+    int opt_variant = -1;
+    bool stores = false;
+    int n_segs = 0, n_chunks = 0;
+    int log2_mmax = 0;
+    int max_n = 0;
+    int64_t cells = 0, store_bytes = 0;
+    size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_store = 0, ws_total = 0;
+
+    // plan-owned device tables
+    WaveDesc* d_waves = nullptr;
+    SegDesc* d_segs = nullptr;
+    int* d_order = nullptr;
+    int2* d_chunks = nullptr;
+    float2* d_tw = nullptr;
+    unsigned* d_ctrl = nullptr;
+    size_t cap_segs = 0, cap_chunks = 0;
+};
+
+namespace {
+
+void free_tables(af_plan* p) {
+    if (p->d_waves) (void)hipFree(p->d_waves);
+    if (p->d_segs) (void)hipFree(p->d_segs);
+    if (p->d_order) (void)hipFree(p->d_order);
+    if (p->d_chunks) (void)hipFree(p->d_chunks);
+    if (p->d_tw) (void)hipFree(p->d_tw);
+    if (p->d_ctrl) (void)hipFree(p->d_ctrl);
+    p->d_waves = nullptr;
+    p->d_segs = nullptr;
+    p->d_order = nullptr;
+    p->d_chunks = nullptr;
+    p->d_tw = nullptr;
+    p->d_ctrl = nullptr;
+}
+
+// Can variant v run transform size 2^lg for waveforms up to max_n samples?
+bool variant_fits(int v, int lg, int max_n) {
+    const VariantInfo vi = graf::variant_info(v, lg);
+    if (!vi.fits) return false;
+    const int lds = vi.fft_lds + (vi.s_lds ? 8 * max_n : 0);
+    return lds <= kMaxLds;
+}
+
+int default_variant(int lg, int max_n) {
+    const int order[] = {0, 1, 2};
+    for (int v : order)
+        if (variant_fits(v, lg, max_n)) return v;
+    return -1;
+}
+
+int lags_per_iter(const VariantInfo& vi, int m) {
+    const int L = (m / 2) / vi.p;
+    const int groups = vi.wgs / L;
+    return vi.split ? groups / 2 : groups;
+}
+
+af_status hip_fail() { return AF_ERR_HIP; }
+
+// Build classes, segments, order, chunks and the workspace layout, and
+// upload the device tables.  Variant per class: forced[c] if set, else
+// opt_variant if it fits, else the default for that size.
+af_status build_schedule(af_plan* p) {
+    const int B = p->batch;
+    // classes by transform size, largest first
+    std::vector<int> lgs;
+    for (const af_wave& w : p->waves) lgs.push_back(ilog2(w.m) - 1);
+    std::sort(lgs.begin(), lgs.end());
+    lgs.erase(std::unique(lgs.begin(), lgs.end()), lgs.end());
+    std::reverse(lgs.begin(), lgs.end());
+    const int C = (int)lgs.size();
+    if ((int)p->forced.size() != C) p->forced.assign(C, -1);
+    std::vector<af_plan::Class> cls(C);
+    std::vector<int> cls_of_wave(B);
+    for (int b = 0; b < B; ++b) {
+        const int lg = ilog2(p->waves[b].m) - 1;
+        const int c = (int)(std::find(lgs.begin(), lgs.end(), lg) - lgs.begin());
+        cls_of_wave[b] = c;
+        cls[c].lg = lg;
+        cls[c].max_n = std::max(cls[c].max_n, p->waves[b].n);
+    }
+    int total_slots = 0;
+    for (int c = 0; c < C; ++c) {
+        af_plan::Class& k = cls[c];
+        int v = p->forced[c];
+        if (v < 0 && p->opt_variant >= 0 && variant_fits(p->opt_variant, k.lg, k.max_n)) v = p->opt_variant;
+        if (v < 0) v = default_variant(k.lg, k.max_n);
+        if (v < 0 || !variant_fits(v, k.lg, k.max_n)) return AF_ERR_UNSUPPORTED;
+        k.variant = v;
+        const VariantInfo vi = graf::variant_info(v, k.lg);
+        k.dyn_lds = vi.fft_lds + (vi.s_lds ? 8 * k.max_n : 0);
+        for (int mode = 0; mode < 4; ++mode) {
+            const int r = graf::variant_max_resident(mode, v, k.lg, k.dyn_lds);
+            if (r <= 0) return AF_ERR_UNSUPPORTED;
+            k.grid[mode] = r * p->cus;  // capped by the segment count below
+        }
+        total_slots = std::max(total_slots, k.grid[graf::MODE_FUSED_ISL]);
+    }
+
+    // per-waveform iteration counts and costs
+    std::vector<int> lpi(B), iters(B);
+    std::vector<double> cost_iter(B);
+    double total = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const af_wave& w = p->waves[b];
+        const af_plan::Class& k = cls[cls_of_wave[b]];
+        const VariantInfo vi = graf::variant_info(k.variant, k.lg);
+        lpi[b] = lags_per_iter(vi, w.m);
+        iters[b] = (w.max_lag + 1 + lpi[b] - 1) / lpi[b];
+        cost_iter[b] = (double)lpi[b] * w.m * ilog2(w.m);
+        total += iters[b] * cost_iter[b];
+    }
+    const double target = total / (2.0 * std::max(1, total_slots));
+
+    std::vector<WaveDesc> wd(B);
+    std::vector<SegDesc> segs;
+    std::vector<double> seg_cost;
+    std::vector<int2> chunks;
+    int64_t slab_elems = 0, store_elems = 0;
+    for (int b = 0; b < B; ++b) {
+        const af_wave& w = p->waves[b];
+        int per = p->seg_iters_opt > 0 ? p->seg_iters_opt
+                                       : std::max(1, (int)std::lround(target / std::max(cost_iter[b], 1.0)));
+        per = std::min(per, iters[b]);
+        WaveDesc& d = wd[b];
+        d.n = w.n;
+        d.m = w.m;
+        d.T = w.max_lag;
+        d.log2m = ilog2(w.m);
+        d.s_off = w.s_off;
+        d.grid_off = w.grid_off;
+        d.store_off = store_elems;
+        d.slab_off = slab_elems;
+        d.seg_begin = (int)segs.size();
+        d.h_tau = w.h_tau;
+        d.h_k = w.h_k;
+        d.band_off = 62 * b;
+        d.full_window = w.max_lag == w.n - 1 ? 1 : 0;
+        for (int it = 0; it < iters[b]; it += per) {
+            SegDesc sd;
+            sd.wave = b;
+            sd.tau_begin = it * lpi[b];
+            sd.tau_end = std::min(w.max_lag + 1, (it + per) * lpi[b]);
+            sd.rec = (int)segs.size();
+            segs.push_back(sd);
+            seg_cost.push_back(std::min(per, iters[b] - it) * cost_iter[b]);
+        }
+        d.seg_count = (int)segs.size() - d.seg_begin;
+        slab_elems += (int64_t)d.seg_count * w.n;
+        store_elems += (int64_t)(w.max_lag + 1) * w.m;
+        for (int c = 0; c < w.n; c += 256) chunks.push_back(make_int2(b, c));
+    }
+    // execution order: by class, longest segment first within a class
+    std::vector<int> order;
+    order.reserve(segs.size());
+    for (int c = 0; c < C; ++c) {
+        cls[c].begin = (int)order.size();
+        for (size_t i = 0; i < segs.size(); ++i)
+            if (cls_of_wave[segs[i].wave] == c) order.push_back((int)i);
+        std::stable_sort(order.begin() + cls[c].begin, order.end(),
+                         [&](int a, int b) { return seg_cost[a] > seg_cost[b]; });
+        cls[c].count = (int)order.size() - cls[c].begin;
+        for (int i = cls[c].begin; i < (int)order.size(); ++i) cls[c].cost += seg_cost[order[i]];
+        for (int mode = 0; mode < 4; ++mode) cls[c].grid[mode] = std::min(cls[c].grid[mode], cls[c].count);
+    }
+
+    // workspace layout and the store decision
+    const size_t parts_b = align256(segs.size() * sizeof(graf::Part));
+    const size_t energy_b = align256((size_t)B * sizeof(float));
+    const size_t slabs_b = align256((size_t)slab_elems * sizeof(float2));
+    const size_t store_b = align256((size_t)store_elems * sizeof(float2));
+    const size_t base = parts_b + energy_b + slabs_b;
+    bool stores;
+    if (p->store_mode == 1)
+        stores = true;
+    else if (p->store_mode == 2)
+        stores = false;
+    else
+        stores = p->budget <= 0 || (int64_t)(base + store_b) <= p->budget;
+    if (p->budget > 0 && (int64_t)(base + (stores ? store_b : 0)) > p->budget) return AF_ERR_BUDGET;
+
+    // upload
+    if (segs.size() > p->cap_segs) {
+        if (p->d_segs) (void)hipFree(p->d_segs);
+        if (p->d_order) (void)hipFree(p->d_order);
+        p->d_segs = nullptr;
+        p->d_order = nullptr;
+        if (hipMalloc(&p->d_segs, segs.size() * sizeof(SegDesc)) != hipSuccess) return hip_fail();
+        if (hipMalloc(&p->d_order, segs.size() * sizeof(int)) != hipSuccess) return hip_fail();
+        p->cap_segs = segs.size();
+    }
+    if (chunks.size() > p->cap_chunks) {
+        if (p->d_chunks) (void)hipFree(p->d_chunks);
+        p->d_chunks = nullptr;
+        if (hipMalloc(&p->d_chunks, chunks.size() * sizeof(int2)) != hipSuccess) return hip_fail();
+        p->cap_chunks = chunks.size();
+    }
+    if (!p->d_waves && hipMalloc(&p->d_waves, (size_t)B * sizeof(WaveDesc)) != hipSuccess) return hip_fail();
+    if (!p->d_ctrl) {
+        if (hipMalloc(&p->d_ctrl, kCtrlWords * sizeof(unsigned)) != hipSuccess) return hip_fail();
+        if (hipMemset(p->d_ctrl, 0, kCtrlWords * sizeof(unsigned)) != hipSuccess) return hip_fail();
+    }
+    if (2 * C + 2 > kCtrlWords) return AF_ERR_UNSUPPORTED;
+    if (hipMemcpy(p->d_waves, wd.data(), (size_t)B * sizeof(WaveDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_segs, segs.data(), segs.size() * sizeof(SegDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_chunks, chunks.data(), chunks.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        return hip_fail();
+
+    p->classes = cls;
+    p->stores = stores;
+    p->n_segs = (int)segs.size();
+    p->n_chunks = (int)chunks.size();
+    p->store_bytes = (int64_t)store_elems * (int64_t)sizeof(float2);
+    p->off_parts = 0;
+    p->off_energy = parts_b;
+    p->off_slabs = parts_b + energy_b;
+    p->off_store = base;
+    p->ws_total = base + (stores ? store_b : 0);
+    return AF_OK;
+}
+
+af_status validate_plan_inputs(int32_t batch, const af_wave* waves, const af_plan_opts* opts) {
+    if (batch <= 0 || !waves || !opts) return AF_ERR_INVALID_ARG;
+    if (!(opts->eps >= 0.f) || opts->store_mode < 0 || opts->store_mode > 2) return AF_ERR_INVALID_ARG;
+    for (int b = 0; b < batch; ++b) {
+        const af_wave& w = waves[b];
+        if (w.n < 1 || w.s_off < 0 || w.grid_off < 0 || w.h_tau < 0 || w.h_k < 0 || w.reserved != 0)
+            return AF_ERR_INVALID_ARG;
+        if (w.grid_off % 4 != 0) return AF_ERR_INVALID_ARG;  // rows move as 16-byte vectors
+        const int T = w.max_lag < 0 ? w.n - 1 : w.max_lag;
+        if (w.max_lag < -1 || T > w.n - 1) return AF_ERR_INVALID_ARG;
+        if (!is_pow2(w.m) || w.m < kMinM || w.m > kMaxM || w.m < 2 * (int64_t)w.n) return AF_ERR_UNSUPPORTED;
+    }
+    return AF_OK;
+}
+
+struct WsView {
+    graf::Part* parts;
+    float* energy;
+    float2* slabs;
+    float2* store;
+};
+
+WsView ws_view(const af_plan* p, void* ws) {
+    char* b = (char*)ws;
+    WsView v;
+    v.parts = (graf::Part*)(b + p->off_parts);
+    v.energy = (float*)(b + p->off_energy);
+    v.slabs = (float2*)(b + p->off_slabs);
+    v.store = p->stores ? (float2*)(b + p->off_store) : nullptr;
+    return v;
+}
+
+AfArgs base_args(const af_plan* p, const void* s, const WsView& v) {
+    AfArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.s = (const float2*)s;
+    a.waves = p->d_waves;
+    a.segs = p->d_segs;
+    a.order = p->d_order;
+    a.n_segs = 0;
+    a.log2_mmax = p->log2_mmax;
+    a.tw = p->d_tw;
+    a.eps = p->eps;
+    a.w_isl = 0.f;
+    a.w_psl = 0.f;
+    a.temp = 1.f;
+    a.parts = v.parts;
+    a.slabs = v.slabs;
+    a.energy = v.energy;
+    a.ctrl = nullptr;
+    return a;
+}
+
+ReduceArgs reduce_args(const af_plan* p, const void* s, const WsView& v) {
+    ReduceArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.s = (const float2*)s;
+    r.waves = p->d_waves;
+    r.chunks = p->d_chunks;
+    r.n_chunks = p->n_chunks;
+    r.parts = v.parts;
+    r.slabs = v.slabs;
+    r.energy = v.energy;
+    r.temp = 1.f;
+    r.ctrl = p->d_ctrl + (kCtrlWords - 2);
+    return r;
+}
+
+// one persistent launch per size class, each on its own slice of the order
+af_status launch(const af_plan* p, int mode, const AfArgs& a0, hipStream_t st, int only_class = -1) {
+    for (int c = 0; c < (int)p->classes.size(); ++c) {
+        if (only_class >= 0 && c != only_class) continue;
+        const af_plan::Class& k = p->classes[c];
+        AfArgs a = a0;
+        a.order = p->d_order + k.begin;
+        a.n_segs = k.count;
+        a.ctrl = p->d_ctrl + 2 * c;
+        hipError_t e = graf::launch_af(mode, k.variant, k.lg, a, k.grid[mode], k.dyn_lds, st);
+        if (e != hipSuccess) return AF_ERR_HIP;
+    }
+    return AF_OK;
+}
+
+bool aligned(const void* x, uintptr_t a) { return ((uintptr_t)x & (a - 1)) == 0; }
+
+af_status check_common(const af_plan* p, const void* s, void* ws, size_t ws_bytes) {
+    if (!p || !s) return AF_ERR_INVALID_ARG;
+    if (!aligned(s, 8) || (ws && !aligned(ws, 256))) return AF_ERR_INVALID_ARG;
+    if (p->ws_total > 0 && (!ws || ws_bytes < p->ws_total)) return AF_ERR_WORKSPACE;
+    return AF_OK;
+}
+
+af_status check_loss(const af_loss_params* lp) {
+    if (!lp) return AF_ERR_INVALID_ARG;
+    if (!(lp->psl_temp > 0.f) || !std::isfinite(lp->w_isl) || !std::isfinite(lp->w_psl)) return AF_ERR_INVALID_ARG;
+    return AF_OK;
+}
+
+// loss forward/backward into slabs and parts (no reduce)
+af_status loss_passes(const af_plan* p, const void* s, const af_loss_params* lp, float* mag, bool want_grad,
+                      const WsView& v, hipStream_t st, int only_class = -1) {
+    AfArgs a = base_args(p, s, v);
+    a.w_isl = lp->w_isl;
+    a.w_psl = lp->w_psl;
+    a.temp = lp->psl_temp;
+    a.band_w = lp->band_w;
+    a.mag = mag;
+    if (!want_grad) return launch(p, graf::MODE_FWD, a, st, only_class);
+    if (lp->w_psl == 0.f) return launch(p, graf::MODE_FUSED_ISL, a, st, only_class);
+    a.ystore = v.store;
+    af_status rc = launch(p, graf::MODE_FWD, a, st, only_class);
+    if (rc != AF_OK) return rc;
+    a.mag = nullptr;
+    a.load_store = v.store != nullptr;
+    return launch(p, graf::MODE_BWD_LOSS, a, st, only_class);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* af_status_string(af_status s) {
+    switch (s) {
+        case AF_OK: return "ok";
+        case AF_ERR_INVALID_ARG: return "invalid argument";
+        case AF_ERR_UNSUPPORTED: return "unsupported shape (M must be a power of two in [128, 32768] with M >= 2N)";
+        case AF_ERR_BUDGET: return "workspace does not fit the budget";
+        case AF_ERR_HIP: return "HIP runtime error";
+        case AF_ERR_WORKSPACE: return "workspace too small";
+        case AF_ERR_NO_DEVICE: return "no gfx950 device";
+    }
+    return "unknown status";
+}
+
+int32_t af_version(void) { return 100; }
+
+af_status af_plan_create(int32_t batch, const af_wave* waves, const af_plan_opts* opts, af_plan** out) {
+    if (!out) return AF_ERR_INVALID_ARG;
+    *out = nullptr;
+    af_status rc = validate_plan_inputs(batch, waves, opts);
+    if (rc != AF_OK) return rc;
+
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return AF_ERR_NO_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return AF_ERR_NO_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return AF_ERR_NO_DEVICE;
+
+    af_plan* p = new (std::nothrow) af_plan();
+    if (!p) return AF_ERR_HIP;
+    p->device = dev;
+    p->cus = prop.multiProcessorCount;
+    p->batch = batch;
+    p->waves.assign(waves, waves + batch);
+    int64_t mmax = 0;
+    for (af_wave& w : p->waves) {
+        if (w.max_lag < 0) w.max_lag = w.n - 1;
+        mmax = std::max<int64_t>(mmax, w.m);
+        p->max_n = std::max(p->max_n, w.n);
+        p->cells += (int64_t)(2 * w.max_lag + 1) * w.m;
+    }
+    p->eps = opts->eps;
+    p->store_mode = opts->store_mode;
+    p->budget = opts->budget_bytes;
+    p->seg_iters_opt = opts->segment_iters;
+    p->log2_mmax = ilog2(mmax);
+
+    // twiddles exp(-j 2 pi i / MMAX), computed in double, rounded once
+    std::vector<float2> tw((size_t)mmax);
+    for (int64_t i = 0; i < mmax; ++i) {
+        const double ang = -2.0 * M_PI * (double)i / (double)mmax;
+        tw[(size_t)i] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    if (hipMalloc(&p->d_tw, tw.size() * sizeof(float2)) != hipSuccess ||
+        hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+        free_tables(p);
+        delete p;
+        return AF_ERR_HIP;
+    }
+
+    p->opt_variant = opts->variant;
+    if (opts->variant >= graf::kNumVariants) rc = AF_ERR_INVALID_ARG;
+    else rc = build_schedule(p);
+    if (rc != AF_OK) {
+        free_tables(p);
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return AF_OK;
+}
+
+void af_plan_destroy(af_plan* p) {
+    if (!p) return;
+    free_tables(p);
+    delete p;
+}
+
+af_status af_plan_workspace_size(const af_plan* p, size_t* bytes) {
+    if (!p || !bytes) return AF_ERR_INVALID_ARG;
+    *bytes = p->ws_total;
+    return AF_OK;
+}
+
+af_status af_plan_get_summary(const af_plan* p, af_plan_summary* o) {
+    if (!p || !o) return AF_ERR_INVALID_ARG;
+    o->cells = p->cells;
+    o->store_bytes = p->store_bytes;
+    o->workspace_bytes = (int64_t)p->ws_total;
+    o->segments = p->n_segs;
+    o->grid = p->classes.empty() ? 0 : p->classes[0].grid[graf::MODE_FUSED_ISL];
+    o->variant = p->classes.empty() ? -1 : p->classes[0].variant;
+    o->stores = p->stores ? 1 : 0;
+    return AF_OK;
+}
+
+af_status af_forward(const af_plan* p, const void* s, float* mag, void* chi, float* energy, void* ws,
+                     size_t ws_bytes, void* stream) {
+    af_status rc = check_common(p, s, ws, ws_bytes);
+    if (rc != AF_OK) return rc;
+    if (!aligned(mag, 16) || !aligned(chi, 8) || !aligned(energy, 4)) return AF_ERR_INVALID_ARG;
+    const WsView v = ws_view(p, ws);
+    AfArgs a = base_args(p, s, v);
+    a.mag = mag;
+    a.chi = (float2*)chi;
+    a.ystore = v.store;
+    if (energy) a.energy = energy;
+    return launch(p, graf::MODE_FWD, a, (hipStream_t)stream);
+}
+
+af_status af_backward(const af_plan* p, const void* s, const float* grad_mag, void* grad_s, void* ws,
+                      size_t ws_bytes, void* stream) {
+    af_status rc = check_common(p, s, ws, ws_bytes);
+    if (rc != AF_OK) return rc;
+    if (!grad_mag || !grad_s) return AF_ERR_INVALID_ARG;
+    if (!aligned(grad_mag, 16) || !aligned(grad_s, 8)) return AF_ERR_INVALID_ARG;
+    const WsView v = ws_view(p, ws);
+    AfArgs a = base_args(p, s, v);
+    a.grad_mag = grad_mag;
+    a.ystore = v.store;
+    a.load_store = v.store != nullptr;
+    rc = launch(p, graf::MODE_BWD_MAG, a, (hipStream_t)stream);
+    if (rc != AF_OK) return rc;
+    ReduceArgs r = reduce_args(p, s, v);
+    r.grad = (float2*)grad_s;
+    return graf::launch_reduce(r, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
+}
+
+af_status af_loss(const af_plan* p, const void* s, const af_loss_params* lp, float* terms, float* mag, void* grad_s,
+                  void* ws, size_t ws_bytes, void* stream) {
+    af_status rc = check_common(p, s, ws, ws_bytes);
+    if (rc != AF_OK) return rc;
+    if ((rc = check_loss(lp)) != AF_OK) return rc;
+    if (!aligned(mag, 16) || !aligned(grad_s, 8) || !aligned(terms, 4) || !aligned(lp->band_w, 4))
+        return AF_ERR_INVALID_ARG;
+    const WsView v = ws_view(p, ws);
+    rc = loss_passes(p, s, lp, mag, grad_s != nullptr, v, (hipStream_t)stream);
+    if (rc != AF_OK) return rc;
+    if (!terms && !grad_s) return AF_OK;
+    ReduceArgs r = reduce_args(p, s, v);
+    r.w_isl = lp->w_isl;
+    r.w_psl = lp->w_psl;
+    r.temp = lp->psl_temp;
+    r.uniform_w = lp->band_w == nullptr;
+    r.grad = (float2*)grad_s;
+    r.terms = terms;
+    r.skip_slabs = grad_s ? 0 : 1;
+    return graf::launch_reduce(r, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
+}
+
+af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream) {
+    if (count < 0 || (count > 0 && (!phi || !s))) return AF_ERR_INVALID_ARG;
+    return graf::launch_phase_to_signal(phi, (float2*)s, count, (hipStream_t)stream) == hipSuccess ? AF_OK
+                                                                                                 : AF_ERR_HIP;
+}
+
+af_status af_optim_step(const af_plan* p, float* phi, float* adam_m, float* adam_v, void* s, int32_t* step,
+                        const af_loss_params* lp, const af_adam_params* ad, float* terms, void* ws, size_t ws_bytes,
+                        void* stream) {
+    af_status rc = check_common(p, s, ws, ws_bytes);
+    if (rc != AF_OK) return rc;
+    if ((rc = check_loss(lp)) != AF_OK) return rc;
+    if (!phi || !adam_m || !adam_v || !step || !ad) return AF_ERR_INVALID_ARG;
+    if (!(ad->lr > 0.f) || !(ad->beta1 >= 0.f && ad->beta1 < 1.f) || !(ad->beta2 >= 0.f && ad->beta2 < 1.f) ||
+        !(ad->eps >= 0.f))
+        return AF_ERR_INVALID_ARG;
+    const WsView v = ws_view(p, ws);
+    rc = loss_passes(p, s, lp, nullptr, true, v, (hipStream_t)stream);
+    if (rc != AF_OK) return rc;
+    ReduceArgs r = reduce_args(p, s, v);
+    r.w_isl = lp->w_isl;
+    r.w_psl = lp->w_psl;
+    r.temp = lp->psl_temp;
+    r.uniform_w = lp->band_w == nullptr;
+    r.terms = terms;
+    r.phi = phi;
+    r.adam_m = adam_m;
+    r.adam_v = adam_v;
+    r.s_next = (float2*)s;
+    r.step = step;
+    r.lr = ad->lr;
+    r.beta1 = ad->beta1;
+    r.beta2 = ad->beta2;
+    r.adam_eps = ad->eps;
+    return graf::launch_reduce_adam(r, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
+}
+
+af_status af_plan_autotune(af_plan* p, const void* s, void* ws, size_t ws_bytes, void* stream, int32_t* chosen,
+                           float* best_ms) {
+    if (!p || !s || !ws) return AF_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return AF_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return AF_ERR_HIP;
+    }
+    af_loss_params lp;
+    lp.w_isl = 1.f;
+    lp.w_psl = 0.f;
+    lp.psl_temp = 0.05f;
+    lp.band_w = nullptr;
+    const int C = (int)p->classes.size();
+    std::vector<int> best(C, -1);
+    float total_best = 0.f;
+    af_status rc = AF_OK;
+    // time each class with every variant that fits it, forward + fused loss
+    for (int c = 0; c < C && rc == AF_OK; ++c) {
+        float best_t = 0.f;
+        for (int v = 0; v < graf::kNumVariants; ++v) {
+            if (!variant_fits(v, p->classes[c].lg, p->classes[c].max_n)) continue;
+            p->forced[c] = v;
+            if (build_schedule(p) != AF_OK || p->ws_total > ws_bytes) continue;
+            const WsView view = ws_view(p, ws);
+            bool ok = true;
+            for (int it = 0; it < 2 && ok; ++it) ok = loss_passes(p, s, &lp, nullptr, true, view, st, c) == AF_OK;
+            if (!ok || hipStreamSynchronize(st) != hipSuccess) continue;
+            const int reps = 5;
+            (void)hipEventRecord(e0, st);
+            for (int it = 0; it < reps && ok; ++it) {
+                AfArgs a = base_args(p, s, view);
+                ok = launch(p, graf::MODE_FWD, a, st, c) == AF_OK &&
+                     loss_passes(p, s, &lp, nullptr, true, view, st, c) == AF_OK;
+            }
+            (void)hipEventRecord(e1, st);
+            if (!ok || hipEventSynchronize(e1) != hipSuccess) continue;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= reps;
+            if (best[c] < 0 || ms < best_t) {
+                best[c] = v;
+                best_t = ms;
+            }
+        }
+        if (best[c] < 0) rc = AF_ERR_UNSUPPORTED;
+        p->forced[c] = best[c];
+        total_best += best_t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != AF_OK) {
+        p->forced.assign(C, -1);
+        (void)build_schedule(p);
+        return rc;
+    }
+    rc = build_schedule(p);
+    if (rc != AF_OK) return rc;
+    if (chosen) *chosen = C ? best[0] : -1;
+    if (best_ms) *best_ms = total_best;
+    return AF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+// Device building blocks for the ambiguity-function kernels (gfx950).
+//
+// * complex64 arithmetic on float2 (re, im)
+// * compile-time twiddle constants (constexpr Taylor series, double precision)
+// * register DFTs of size 2..32, decimation in time, either sign
+// * one Stockham autosort pass over a lane group whose lanes each hold P
+//   points, exchanging through LDS with one padding slot per 32 entries
+//
+// Sign convention: SIGN = -1 is the forward transform sum x[n] e^{-j2pi kn/R}
+// (the "FFT" of Algorithm 1, step 3), SIGN = +1 the unnormalised inverse.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace graf {
+
+// ---------------------------------------------------------------- complex --
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float cabs2(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
+
+// ------------------------------------------------- compile-time twiddles --
+// cos / sin of 2*pi*k/R in double precision, reduced to the first octant and
+// evaluated with a Taylor series (error far below float rounding).
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double taylor_sin(double x) {
+    double term = x, sum = x;
+    for (int i = 1; i < 14; ++i) {
+        term *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double taylor_cos(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int i = 1; i < 14; ++i) {
+        term *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+        sum += term;
+    }
+    return sum;
+}
+// cos(2 pi k / R) for integer k, R > 0
+constexpr double ccos(long k, long R) {
+    k = ((k % R) + R) % R;
+    // use the quadrant symmetry to keep the Taylor argument within [0, pi/4]
+    long k8 = 8 * k;  // angle in units of 2pi/(8R): octant = k8 / R
+    if (k8 <= R) return taylor_cos(2.0 * kPi * k / R);
+    if (k8 <= 2 * R) return taylor_sin(2.0 * kPi * (R - 4 * k) / (4.0 * R));
+    if (k8 <= 3 * R) return -taylor_sin(2.0 * kPi * (4 * k - R) / (4.0 * R));
+    if (k8 <= 4 * R) return -taylor_cos(2.0 * kPi * (R - 2 * k) / (2.0 * R));
+    return ccos(R - k, R);
+}
+constexpr double csin(long k, long R) { return ccos(R - 4 * k, 4 * R); }
+
+// v * exp(SIGN * j 2 pi K / R) for a compile-time K, with the trivial
+// multiples of pi/4 spelled out so they cost no multiplications.
+template <int K, int R, int SIGN>
+__device__ __forceinline__ float2 twiddle_const(float2 v) {
+    constexpr int k = ((K % R) + R) % R;
+    constexpr int e8 = (8 * k) % R == 0 ? (8 * k) / R : -1;  // multiple of pi/4?
+    if constexpr (e8 == 0) {
+        return v;
+    } else if constexpr (e8 == 2) {  // e^{SIGN j pi/2} = SIGN j
+        return SIGN < 0 ? make_float2(v.y, -v.x) : make_float2(-v.y, v.x);
+    } else if constexpr (e8 == 4) {
+        return make_float2(-v.x, -v.y);
+    } else if constexpr (e8 == 6) {  // e^{SIGN j 3pi/2} = -SIGN j
+        return SIGN < 0 ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+    } else if constexpr (e8 == 1 || e8 == 3 || e8 == 5 || e8 == 7) {
+        constexpr float h = 0.70710678118654752440f;
+        // (x + jy)(c + jSs) with |c| = |s| = 1/sqrt2
+        constexpr float c = (e8 == 1 || e8 == 7) ? h : -h;
+        constexpr float s = (e8 == 1 || e8 == 3) ? h : -h;
+        constexpr float ss = SIGN < 0 ? -s : s;
+        if constexpr (c == ss) {
+            return make_float2((v.x - v.y) * c, (v.x + v.y) * c);
+        } else {
+            return make_float2((v.x + v.y) * c, (v.y - v.x) * c);
+        }
+    } else {
+        constexpr float c = (float)ccos(k, R);
+        constexpr float s = (float)(SIGN < 0 ? -csin(k, R) : csin(k, R));
+        return make_float2(fmaf(v.x, c, -v.y * s), fmaf(v.x, s, v.y * c));
+    }
+}
+
+// -------------------------------------------------------- register DFTs --
+// In-place DFT of R values held in registers, natural order in and out.
+template <int R, int SIGN>
+struct Dft {
+    template <int K>
+    __device__ __forceinline__ static void combine(float2* e, float2* o, float2* v) {
+        if constexpr (K < R / 2) {
+            float2 t = twiddle_const<K, R, SIGN>(o[K]);
+            v[K] = cadd(e[K], t);
+            v[K + R / 2] = csub(e[K], t);
+            combine<K + 1>(e, o, v);
+        }
+    }
+    __device__ __forceinline__ static void run(float2* v) {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        Dft<R / 2, SIGN>::run(e);
+        Dft<R / 2, SIGN>::run(o);
+        combine<0>(e, o, v);
+    }
+};
+template <int SIGN>
+struct Dft<1, SIGN> {
+    __device__ __forceinline__ static void run(float2*) {}
+};
+template <int SIGN>
+struct Dft<2, SIGN> {
+    __device__ __forceinline__ static void run(float2* v) {
+        float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+template <int SIGN>
+struct Dft<4, SIGN> {
+    __device__ __forceinline__ static void run(float2* v) {
+        float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        float2 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+        // t3 * (SIGN j)
+        float2 u = SIGN < 0 ? make_float2(t3.y, -t3.x) : make_float2(-t3.y, t3.x);
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, u);
+        v[3] = csub(t1, u);
+    }
+};
+
+// ----------------------------------------------------------- LDS layout --
+// One padding slot per 32 complex entries spreads stride-R stores over banks.
+__device__ __forceinline__ int lds_index(int i) { return i + (i >> 5); }
+template <int N>
+struct LdsSize {
+    static constexpr int value = N + (N >> 5);
+};
+
+// --------------------------------------------------------- Stockham FFT --
+// Lane group of L lanes, P points per lane, transform size MH = L * P.
+// Register layout at entry: v[r] = x[l + r*L]  (l = lane in the group).
+// Register layout at exit:  v[q] = X[l + q*L].
+// Passes use radix P except the last, whose radix RL divides P; each lane
+// runs P/R butterflies per pass.  Twiddles exp(SIGN j 2pi i / MMAX) come from
+// tw[i] (i < MMAX), the table of the largest transform in the launch.
+template <int MH, int P>
+struct Plan {
+    static constexpr int L = MH / P;
+    static constexpr int log2(int x) { return x <= 1 ? 0 : 1 + log2(x / 2); }
+    static constexpr int LOG_MH = log2(MH);
+    static constexpr int LOG_P = log2(P);
+    static constexpr int NPASS = (LOG_MH + LOG_P - 1) / LOG_P;
+    static constexpr int RLAST = 1 << (LOG_MH - (NPASS - 1) * LOG_P);
+};
+
+// Pass number PASS (0-based) with stride NS = P^PASS and radix R.
+// in: v laid out as slots [b*R + r] = x[j + r*MH/R], j = l + L*b
+// out: written to LDS y[(j/NS)*NS*R + j%NS + r*NS] unless LAST, in which
+//      case the values stay in registers: slot [b*R + r] = X[j + r*MH/R].
+template <int MH, int P, int R, int NS, int SIGN, bool LAST>
+__device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, const float2* __restrict__ tw,
+                                              int tw_shift) {
+    constexpr int L = MH / P;
+    constexpr int NB = P / R;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = l + L * b;
+        const int k = j & (NS - 1);
+        float2* u = v + b * R;
+        if constexpr (NS > 1) {
+            // exp(SIGN j 2pi r k / (NS R)) = w_MMAX^(r k MMAX/(NS R))
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[(r * k) << tw_shift];
+                if (SIGN > 0) w.y = -w.y;
+                u[r] = cmul(u[r], w);
+            }
+        }
+        Dft<R, SIGN>::run(u);
+        if constexpr (!LAST) {
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_index(base + r * NS)] = u[r];
+        }
+    }
+}
+
+// Full transform of one lane group.  Synchronisation between passes goes
+// through SYNC(), which must make every lane's LDS stores visible to every
+// lane of the group (a work-group barrier or a wavefront-level fence).
+// tw is the table for MMAX = MH << (tw_shift_base): exp(-j 2pi i / MMAX).
+template <int MH, int P, int SIGN, typename Sync>
+__device__ __forceinline__ void fft_group(float2* v, float2* lds, int l, const float2* __restrict__ tw,
+                                          int mmax_over_mh, Sync sync) {
+    using PL = Plan<MH, P>;
+    constexpr int L = PL::L;
+    constexpr int NPASS = PL::NPASS;
+    constexpr int RL = PL::RLAST;
+    // tw index for pass with NS, R: (r k) * (MMAX / (NS R))
+    // MMAX / (NS R) = mmax_over_mh * MH / (NS R), a power of two -> shift
+    const int sh0 = __builtin_ctz(mmax_over_mh);
+    static_assert(NPASS >= 1 && NPASS <= 4, "transform size out of range");
+    if constexpr (NPASS == 1) {
+        stockham_pass<MH, P, RL, 1, SIGN, true>(v, lds, l, tw, 0);
+    } else {
+        stockham_pass<MH, P, P, 1, SIGN, false>(v, lds, l, tw, 0);
+        sync();
+        constexpr int NS1 = P;
+        constexpr int R1 = NPASS == 2 ? RL : P;
+#pragma unroll
+        for (int b = 0; b < P / R1; ++b)
+#pragma unroll
+            for (int r = 0; r < R1; ++r) v[b * R1 + r] = lds[lds_index(l + L * b + r * (MH / R1))];
+        sync();
+        stockham_pass<MH, P, R1, NS1, SIGN, NPASS == 2>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS1 * R1));
+        if constexpr (NPASS >= 3) {
+            sync();
+            constexpr int NS2 = P * P;
+            constexpr int R2 = NPASS == 3 ? RL : P;
+#pragma unroll
+            for (int b = 0; b < P / R2; ++b)
+#pragma unroll
+                for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[lds_index(l + L * b + r * (MH / R2))];
+            sync();
+            stockham_pass<MH, P, R2, NS2, SIGN, NPASS == 3>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS2 * R2));
+            if constexpr (NPASS >= 4) {
+                sync();
+                constexpr int NS3 = P * P * P;
+                constexpr int R3 = RL;
+#pragma unroll
+                for (int b = 0; b < P / R3; ++b)
+#pragma unroll
+                    for (int r = 0; r < R3; ++r) v[b * R3 + r] = lds[lds_index(l + L * b + r * (MH / R3))];
+                sync();
+                stockham_pass<MH, P, R3, NS3, SIGN, true>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS3 * R3));
+            }
+        }
+    }
+    // exit layout: slot [b*RL + r] = X[l + L*b + r*MH/RL] = X[l + L*(b + r*P/RL)]
+    // reorder to slot q = b + r*(P/RL) so that v[q] = X[l + q*L]
+    if constexpr (RL != P) {
+        float2 t[P];
+#pragma unroll
+        for (int b = 0; b < P / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) t[b + r * (P / RL)] = v[b * RL + r];
+#pragma unroll
+        for (int q = 0; q < P; ++q) v[q] = t[q];
+    }
+}
+
+}  // namespace graf

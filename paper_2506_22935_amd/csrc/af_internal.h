@@ -1,0 +1,108 @@
+// Types shared by the host planner (af_api.hip) and the kernels
+// (af_kernels.hip).  Not part of the public C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace graf {
+
+// One waveform of a batch, as the kernels see it.
+struct WaveDesc {
+    int n, m, T, log2m;       // length, Doppler bins, lag half-width, log2(M)
+    int64_t s_off;            // first sample in the packed complex64 input
+    int64_t grid_off;         // first element of its [2T+1][M] grids
+    int64_t store_off;        // first element of its [T+1][M] spectrum store
+    int64_t slab_off;         // first complex64 of its slabs ([segs][N])
+    int seg_begin, seg_count; // its segments (consecutive partial records)
+    int h_tau, h_k;           // mainlobe half-widths (lags, bins)
+    int band_off;             // first of its 62 shaping weights, or -1
+    int full_window;          // T = N - 1: with uniform ISL weights the ISL is
+                              // taken as M - (mainlobe power), Moyal's identity
+};
+
+// One work item: lags [tau_begin, tau_end) (tau >= 0) of one waveform.
+struct SegDesc {
+    int wave, tau_begin, tau_end, rec;  // rec = slab / partial-record index
+};
+
+// Per-segment partial results, accumulated in float64 where they are sums
+// over many cells.  isl: the segment's share of the ISL (for a complement
+// waveform, minus its mainlobe power: ISL = M + sum of these); lse_m, lse_s:
+// soft-PSL log-sum-exp pair (max a, sum exp((a - max)/T)); dle: dL/dE share.
+struct Part {
+    double isl;
+    double lse_s;
+    double dle;
+    float lse_m;
+    float pad;
+};
+
+enum Mode : int {
+    MODE_FWD = 0,       // spectra -> magnitude / AF / stored spectra / loss parts
+    MODE_BWD_MAG = 1,   // upstream dL/da grid -> gradient slabs
+    MODE_BWD_LOSS = 2,  // ISL + soft-PSL loss -> gradient slabs (needs MODE_FWD parts)
+    MODE_FUSED_ISL = 3  // ISL loss forward and backward in one pass
+};
+
+struct AfArgs {
+    const float2* s;
+    const WaveDesc* waves;
+    const SegDesc* segs;
+    const int* order;     // execution order of segment indices
+    int n_segs;
+    int log2_mmax;
+    const float2* tw;     // exp(-j 2 pi i / MMAX), i < MMAX
+    float eps;
+    float w_isl, w_psl, temp;
+    const float* band_w;  // [62] per waveform, or null
+    float* mag;           // [grid] fp32, nullable (MODE_FWD, MODE_FUSED_ISL)
+    float2* chi;          // [grid] complex64, nullable (MODE_FWD)
+    float2* ystore;       // spectra store [T+1][M], nullable
+    int load_store;       // backward reads spectra from ystore instead of recomputing
+    const float* grad_mag;  // [grid] (MODE_BWD_MAG)
+    Part* parts;          // [records]
+    float2* slabs;        // [sum segs*N]
+    float* energy;        // [B], written by the segment holding lag 0
+    unsigned* ctrl;       // [2] work-queue ticket and exit counters
+};
+
+struct ReduceArgs {
+    const float2* s;
+    const WaveDesc* waves;
+    const int2* chunks;   // (wave, first sample) per block of 256 samples
+    int n_chunks;
+    const Part* parts;
+    const float2* slabs;
+    const float* energy;
+    float w_isl, w_psl, temp;
+    float2* grad;         // dL/d conj(s), packed like s; nullable
+    float* terms;         // [B][4] = loss, ISL, soft-PSL, E; nullable
+    int skip_slabs;       // loss only: do not read gradient slabs
+    int uniform_w;        // no shaping weights: full-window ISL uses the complement
+    // fused Adam on phases (grad == null then): phi, m, v packed like s
+    float* phi;
+    float* adam_m;
+    float* adam_v;
+    float2* s_next;       // exp(j phi_new)
+    int* step;            // device step counter (1-based after increment)
+    unsigned* ctrl;       // [2] exit counter for the step increment
+    float lr, beta1, beta2, adam_eps;
+};
+
+// launchers (af_kernels.hip)
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+hipError_t launch_reduce_adam(const ReduceArgs& a, hipStream_t st);
+hipError_t launch_phase_to_signal(const float* phi, float2* s, int64_t count, hipStream_t st);
+
+// Kernel variants.  Variant v at transform size MH = 2^lg (M = 2 MH): fits
+// tells whether an instance exists; its dynamic LDS is fft_lds bytes plus,
+// when s_lds, 8 bytes per sample of the longest waveform it runs.
+struct VariantInfo {
+    int lo, hi, p, split, wgs, s_lds, fits, fft_lds, nacc;
+};
+constexpr int kNumVariants = 5;
+VariantInfo variant_info(int v, int lg);
+int variant_max_resident(int mode, int variant, int lg, int dyn_lds_bytes);
+hipError_t launch_af(int mode, int variant, int lg, const AfArgs& a, int grid, int dyn_lds_bytes, hipStream_t st);
+
+}  // namespace graf

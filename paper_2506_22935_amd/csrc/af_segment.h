@@ -1,0 +1,528 @@
+// Ambiguity-function segment processor and persistent kernel template (gfx950).
+//
+// One persistent kernel per mode walks a work queue of segments; a segment
+// is a contiguous range of non-negative lags of one waveform.  For each lag
+// tau >= 0 the kernel forms the shifted lag product
+//     r'[m] = s[m + tau] * conj(s[m]),  m in [0, N - tau)
+// whose spectrum Y' = DFT_M(r') gives both AF rows (paper Sec. 4.1, Eqs.
+// 7-12, aperiodic lags, Doppler sign e^{-j}):
+//     chi(tau, k)  = exp(-j 2pi k tau / M) Y'[k]
+//     chi(-tau, k) = conj(Y'[-k])
+// so |chi(+-tau, .)| need one transform per lag pair.  Since r' is zero on
+// [M/2, M) when M >= 2N, Y'[2k'] = DFT_{M/2}(r')[k'] and
+// Y'[2k'+1] = DFT_{M/2}(r' w_M^m)[k']: two independent half transforms.
+//
+// Backward (Sec. 4.2, Eqs. 13-15): every loss here depends on chi only
+// through |chi|, so dL/d conj(chi) = c * chi with real c per cell, and the
+// upstream of Y' is H[k] = (c(tau,k) + c(-tau,-k)) Y'[k] (tau > 0; c(0,k)
+// Y'[k] for tau = 0).  Q' = IDFT_M(H) (unnormalised, e^{+j}) is needed only on
+// [0, N - tau) and splits the same way:
+//     Q'[m] = IDFT_{M/2}(H_even)[m] + w_M^{-m} IDFT_{M/2}(H_odd)[m].
+// The lag-product adjoint then adds, for every lag tau >= 0,
+//     g[p] += conj(Q'[p]) s[p + tau]    (p < N - tau)
+//     g[p] += Q'[p - tau] s[p - tau]    (p >= tau)
+// into per-thread accumulators owned by the work group.  Each segment writes
+// its own slab, and a second kernel sums slabs in a fixed order and adds
+// dL/dE * s (dE/d conj(s) = s): no atomics touch the gradient, so results are
+// bitwise reproducible.
+#pragma once
+#include "af_device.h"
+#include "af_internal.h"
+
+#include <math.h>
+
+namespace graf {
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// ----------------------------------------------------------- reductions --
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// log-sum-exp pair (max, sum of exp((x - max)/T)) merge; inv_t2 = log2(e)/T
+__device__ __forceinline__ void lse_merge(float& m, double& s, float m2, double s2, float inv_t2) {
+    float mn = fmaxf(m, m2);
+    if (mn == -INFINITY) return;
+    s = s * (double)exp2f((m - mn) * inv_t2) + s2 * (double)exp2f((m2 - mn) * inv_t2);
+    m = mn;
+}
+
+__device__ __forceinline__ void wave_lse(float& m, double& s, float inv_t2) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        float m2 = __shfl_xor(m, o, 64);
+        double s2 = __shfl_xor(s, o, 64);
+        lse_merge(m, s, m2, s2, inv_t2);
+    }
+}
+
+// Sum over the work group in a fixed order: wavefront butterflies, then the
+// per-wave results in wave order.  Every thread receives the total.
+template <int WGS, typename Tv>
+__device__ Tv block_sum(Tv v, double* scratch) {
+    constexpr int NW = WGS / 64;
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[w] = (double)v;
+    __syncthreads();
+    Tv t = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) t += (Tv)scratch[i];
+    return t;
+}
+
+// ------------------------------------------------------- band weights ----
+// separable ISL shaping weight u[floor(31|tau|/N)] * v[floor(31|k_c|/(M/2+1))]
+__device__ __forceinline__ int floor_div_small(int a, int d) {
+    // exact floor(a / d) for 0 <= a < 2^24, d > 0
+    int q = (int)((float)a * (1.0f / (float)d));
+    if ((q + 1) * d <= a) ++q;
+    if (q * d > a) --q;
+    return q;
+}
+
+// ------------------------------------------------------- one segment -----
+// Thread layout: lane groups of L = MH/P lanes.  SPLIT = 1: the even and the
+// odd half transform of a lag run on two neighbouring groups (2L threads per
+// lag).  SPLIT = 0: one group runs both halves in turn (L threads per lag).
+// In SPLIT mode the magnitude / upstream rows of a lag are staged through the
+// lag's two transform buffers (2 * (MH + MH/32) complex >= 2 rows of M floats)
+// so that global traffic is coalesced 16-byte row accesses.
+template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC>
+__device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, float2* s_lds,
+                                                bool s_in_lds, double* scratch) {
+    constexpr int L = MH / P;
+    constexpr int G = WGS / L;
+    constexpr int LPI = SPLIT ? G / 2 : G;
+    constexpr int BUF = LdsSize<MH>::value;
+    constexpr int TPL = SPLIT ? 2 * L : L;  // threads per lag
+    constexpr int M_ = 2 * MH;
+    constexpr bool NEEDS_INV = MODE != MODE_FWD;
+    constexpr bool HAS_MAG_OUT = MODE == MODE_FWD || MODE == MODE_FUSED_ISL;
+    static_assert(L >= 1 && G >= (SPLIT ? 2 : 1), "group does not fit the work group");
+    static_assert(!SPLIT || (2 * BUF * 2 >= 2 * M_), "row staging does not fit");
+
+    const int tid = threadIdx.x;
+    const int grp = tid / L;
+    const int l = tid - grp * L;
+    const int lam = SPLIT ? (grp >> 1) : grp;
+    const int hsel = SPLIT ? (grp & 1) : 0;
+    const int t2 = tid - lam * TPL;  // thread index among the lag's threads
+    float2* buf = lds + grp * BUF;
+    float* rowbuf = reinterpret_cast<float*>(lds + (SPLIT ? 2 * lam : lam) * BUF);
+
+    const WaveDesc w = a.waves[sg.wave];
+    const int N = w.n, T = w.T;
+    constexpr int M = M_;
+    const int tshift = a.log2_mmax - w.log2m;  // w_M^i = tw[i << tshift]
+    const float2* __restrict__ sg_s = a.s + w.s_off;
+    const float2* __restrict__ tw = a.tw;
+    const int tw_mh = 1 << (a.log2_mmax - Plan<MH, P>::LOG_MH);
+    auto sync = []() { __syncthreads(); };
+
+    // energy E = sum |s|^2, fixed reduction order
+    float e = 0.f;
+    for (int p = tid; p < N; p += WGS) e += cabs2(sg_s[p]);
+    const float E = block_sum<WGS, float>(e, scratch);
+    if (sg.tau_begin == 0 && tid == 0) a.energy[sg.wave] = E;
+    const float invE = 1.0f / E;
+    const float invE2 = invE * invE;
+
+    const float2* __restrict__ sv = sg_s;
+    if (s_in_lds) {
+        for (int p = tid; p < N; p += WGS) s_lds[p] = sg_s[p];
+        __syncthreads();
+        sv = s_lds;
+    }
+
+    const float inv_t2 = kLog2e / a.temp;
+    const bool want_lse = MODE == MODE_FWD && a.w_psl != 0.f;
+    float glob_m = 0.f, glob_inv_s = 0.f;
+    if (MODE == MODE_BWD_LOSS && a.w_psl != 0.f) {
+        float m = -INFINITY;
+        double s = 0.0;
+        for (int j = 0; j < w.seg_count; ++j) {
+            const Part pr = a.parts[w.seg_begin + j];
+            lse_merge(m, s, pr.lse_m, pr.lse_s, inv_t2);
+        }
+        glob_m = m;
+        glob_inv_s = (float)(1.0 / s);
+    }
+    const bool banded = a.band_w != nullptr && w.band_off >= 0;
+    const float* bu = banded ? a.band_w + w.band_off : nullptr;
+    const float* bv = banded ? a.band_w + w.band_off + 31 : nullptr;
+    const bool mag_out = HAS_MAG_OUT && a.mag != nullptr;
+    const bool chi_out = MODE == MODE_FWD && a.chi != nullptr;
+
+    float2 acc[NEEDS_INV ? NACC : 1];
+#pragma unroll
+    for (int i = 0; i < (NEEDS_INV ? NACC : 1); ++i) acc[i] = make_float2(0.f, 0.f);
+    const bool compl_isl = a.band_w == nullptr && w.full_window != 0;
+    double isl = 0.0, ls = 0.0, dle = 0.0;
+    float lm = -INFINITY;
+
+    for (int t0 = sg.tau_begin; t0 < sg.tau_end; t0 += LPI) {
+        const int tau = t0 + lam;
+        const bool active = tau < sg.tau_end;
+        const int S = N - tau;
+        const float mult = tau > 0 ? 2.f : 1.f;
+        const bool main_tau = tau <= w.h_tau;
+        const float wu = (banded && active) ? bu[(31 * tau) / N] : 1.f;
+        const int64_t row_p = w.grid_off + (int64_t)(T + (active ? tau : 0)) * M;
+        const int64_t row_n = w.grid_off + (int64_t)(T - (active ? tau : 0)) * M;
+
+        // prefetch the two upstream rows (tau, -tau) while the transform runs
+        constexpr int NPF = (MODE == MODE_BWD_MAG && SPLIT) ? (2 * M / 4) / TPL : 1;
+        float4 gpre[NPF];
+        if (MODE == MODE_BWD_MAG && SPLIT) {
+#pragma unroll
+            for (int i = 0; i < NPF; ++i) {
+                const int f = t2 + i * TPL;  // float4 index over both rows
+                const int r = f >= M / 4;
+                const int64_t base = r ? row_n : row_p;
+                gpre[i] = (active && (tau > 0 || !r))
+                              ? *reinterpret_cast<const float4*>(a.grad_mag + base + 4 * (f - r * (M / 4)))
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+        float2 q0[(NEEDS_INV && !SPLIT) ? P : 1];
+
+#pragma unroll
+        for (int hh = 0; hh < (SPLIT ? 1 : 2); ++hh) {
+            const int h = SPLIT ? hsel : hh;
+            float2 v[P];
+            if (NEEDS_INV && a.load_store) {
+                const float2* ys = a.ystore + w.store_off + (int64_t)(active ? tau : 0) * M + h * MH;
+#pragma unroll
+                for (int q = 0; q < P; ++q) v[q] = active ? ys[l + q * L] : make_float2(0.f, 0.f);
+            } else {
+#pragma unroll
+                for (int r = 0; r < P; ++r) {
+                    const int m = l + r * L;
+                    float2 x = make_float2(0.f, 0.f);
+                    if (active && m < S) {
+                        x = cmulc(sv[m + tau], sv[m]);
+                        if (h) x = cmul(x, tw[m << tshift]);
+                    }
+                    v[r] = x;
+                }
+                fft_group<MH, P, -1>(v, buf, l, tw, tw_mh, sync);
+            }
+            // v[q] = Y'[2 (l + qL) + h]
+            if (MODE == MODE_FWD && a.ystore && active) {
+                float2* ys = a.ystore + w.store_off + (int64_t)tau * M + h * MH;
+#pragma unroll
+                for (int q = 0; q < P; ++q) ys[l + q * L] = v[q];
+            }
+            if constexpr (SPLIT) {
+                if (mag_out || MODE == MODE_BWD_MAG || chi_out) __syncthreads();  // transform buffers free
+                if (MODE == MODE_BWD_MAG) {
+                    float4* rb4 = reinterpret_cast<float4*>(rowbuf);
+#pragma unroll
+                    for (int i = 0; i < NPF; ++i) rb4[t2 + i * TPL] = gpre[i];
+                    __syncthreads();
+                }
+            }
+
+            // ---------------------------------------------- epilogue --
+            // p = |Y'|^2/E^2, a = sqrt(p + eps); the sidelobe test and the
+            // weight are symmetric under (tau, k) -> (-tau, -k)
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const int k = 2 * (l + q * L) + h;
+                const int kn = k ? M - k : 0;
+                const int kc = k < (M >> 1) ? k : M - k;  // |centred bin|
+                const float pw = cabs2(v[q]) * invE2;
+                const float av = sqrtf(pw + a.eps);
+                const bool sd = active && !(main_tau && kc <= w.h_k);
+                float wt = 1.f;
+                if (banded && sd) wt = wu * bv[floor_div_small(31 * kc, (M >> 1) + 1)];
+                if (HAS_MAG_OUT) {
+                    if (mag_out) {
+                        if (SPLIT) {
+                            rowbuf[k] = av;
+                            rowbuf[M + kn] = av;
+                        } else if (active) {
+                            a.mag[row_p + k] = av;
+                            if (tau > 0) a.mag[row_n + kn] = av;
+                        }
+                    }
+                    if (compl_isl) {
+                        if (active && !sd) isl -= (double)(mult * pw);  // mainlobe power
+                    } else if (sd) {
+                        isl += (double)(mult * wt * pw);
+                    }
+                }
+                if (MODE == MODE_FWD && want_lse && sd) {
+                    // online log-sum-exp, one exp per cell
+                    const float d = av - lm;
+                    const float ex = exp2f(-fabsf(d) * inv_t2);
+                    if (d > 0.f) {
+                        ls = ls * (double)ex + (double)mult;
+                        lm = av;
+                    } else {
+                        ls += (double)(mult * ex);
+                    }
+                }
+                if constexpr (NEEDS_INV) {
+                    float c = 0.f;
+                    if (MODE == MODE_BWD_MAG) {
+                        if (active) {
+                            float g;
+                            if (SPLIT) {
+                                g = rowbuf[k];
+                                if (tau > 0) g += rowbuf[M + kn];
+                            } else {
+                                g = a.grad_mag[row_p + k];
+                                if (tau > 0) g += a.grad_mag[row_n + kn];
+                            }
+                            const float ia = 1.0f / av;
+                            c = 0.5f * g * invE2 * ia;
+                            dle -= (double)(g * pw * invE * ia);
+                        }
+                    } else if (MODE == MODE_BWD_LOSS) {
+                        if (sd) {
+                            c = compl_isl ? 0.f : a.w_isl * wt * invE2;
+                            if (a.w_psl != 0.f) {
+                                const float qq = exp2f((av - glob_m) * inv_t2) * glob_inv_s;
+                                const float ia = 1.0f / av;
+                                c = fmaf(a.w_psl * qq * 0.5f * invE2, ia, c);
+                                dle -= (double)(mult * a.w_psl * qq * pw * invE * ia);
+                            }
+                            c *= mult;
+                        } else if (compl_isl && active) {
+                            c = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
+                        }
+                    } else {  // MODE_FUSED_ISL
+                        if (compl_isl) {
+                            if (active && !sd) c = -mult * a.w_isl * invE2;
+                        } else if (sd) {
+                            c = mult * a.w_isl * wt * invE2;
+                        }
+                    }
+                    v[q] = cscale(v[q], c);
+                }
+            }
+
+            if constexpr (SPLIT) {
+                if (mag_out) {
+                    // coalesced row stores: rows tau and -tau (tau = 0: one row)
+                    __syncthreads();
+                    const float4* rb4 = reinterpret_cast<const float4*>(rowbuf);
+                    if (active) {
+                        for (int f = t2; f < 2 * (M / 4); f += TPL) {
+                            const int r = f >= M / 4;
+                            if (r && tau == 0) break;
+                            float4* dst = reinterpret_cast<float4*>(a.mag + (r ? row_n : row_p)) + (f - r * (M / 4));
+                            *dst = rb4[f];
+                        }
+                    }
+                }
+                if (chi_out) {
+                    // complex AF rows from the spectrum staged in natural order
+                    __syncthreads();
+                    float2* yb = reinterpret_cast<float2*>(rowbuf);
+#pragma unroll
+                    for (int q = 0; q < P; ++q) yb[2 * (l + q * L) + h] = v[q];
+                    __syncthreads();
+                    if (active) {
+                        for (int k = t2; k < M; k += TPL) {
+                            const int ti = (int)(((int64_t)k * tau) & (M - 1));
+                            a.chi[row_p + k] = cmul(yb[k], tw[ti << tshift]);
+                            if (tau > 0) a.chi[row_n + k] = cconj(yb[k ? M - k : 0]);
+                        }
+                    }
+                }
+                if (NEEDS_INV && (mag_out || MODE == MODE_BWD_MAG || chi_out)) __syncthreads();
+            } else {
+                if (chi_out && active) {
+#pragma unroll 1
+                    for (int q = 0; q < P; ++q) {
+                        float2 y = make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int qq = 0; qq < P; ++qq)
+                            if (qq == q) y = v[qq];
+                        const int k = 2 * (l + q * L) + h;
+                        const int ti = (int)(((int64_t)k * tau) & (M - 1));
+                        a.chi[row_p + k] = cmul(y, tw[ti << tshift]);
+                        if (tau > 0) a.chi[row_n + (k ? M - k : 0)] = cconj(y);
+                    }
+                }
+            }
+
+            if constexpr (NEEDS_INV) {
+                fft_group<MH, P, +1>(v, buf, l, tw, tw_mh, sync);
+                // v[q] = IDFT_{MH}(H_h)[l + qL]; the odd half gets w_M^{-m}
+                if (h) {
+#pragma unroll
+                    for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], tw[(l + q * L) << tshift]);
+                }
+                if constexpr (SPLIT) {
+#pragma unroll
+                    for (int q = 0; q < P; ++q) buf[lds_index(l + q * L)] = v[q];
+                } else {
+                    if (hh == 0) {
+#pragma unroll
+                        for (int q = 0; q < P; ++q) q0[q] = v[q];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < P; ++q) buf[lds_index(l + q * L)] = cadd(q0[q], v[q]);
+                    }
+                }
+            }
+        }
+
+        if constexpr (NEEDS_INV) {
+            __syncthreads();
+            // lag-product adjoint for every lag of this iteration
+            for (int j = 0; j < LPI; ++j) {
+                const int tj = t0 + j;
+                if (tj >= sg.tau_end) break;
+                const int Sj = N - tj;
+                const float2* qa = lds + (SPLIT ? 2 * j : j) * BUF;
+#pragma unroll
+                for (int i = 0; i < NACC; ++i) {
+                    const int p = tid + WGS * i;
+                    if (p < N) {
+                        float2 sum = acc[i];
+                        if (p < Sj) {
+                            float2 Q = qa[lds_index(p)];
+                            if (SPLIT) Q = cadd(Q, qa[BUF + lds_index(p)]);
+                            sum = cadd(sum, cmul(cconj(Q), sv[p + tj]));
+                        }
+                        const int m = p - tj;
+                        if (m >= 0) {
+                            float2 Q = qa[lds_index(m)];
+                            if (SPLIT) Q = cadd(Q, qa[BUF + lds_index(m)]);
+                            sum = cadd(sum, cmul(Q, sv[m]));
+                        }
+                        acc[i] = sum;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ------------------------------------------- segment results -------
+    const double isl_t = block_sum<WGS, double>(isl, scratch);
+    if (MODE == MODE_FWD) {
+        wave_lse(lm, ls, inv_t2);
+        __syncthreads();
+        if ((tid & 63) == 0) {
+            scratch[2 * (tid >> 6)] = (double)lm;
+            scratch[2 * (tid >> 6) + 1] = ls;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            float m = -INFINITY;
+            double s = 0.0;
+            for (int i = 0; i < WGS / 64; ++i) lse_merge(m, s, (float)scratch[2 * i], scratch[2 * i + 1], inv_t2);
+            Part pr;
+            pr.isl = isl_t;
+            pr.lse_s = s;
+            pr.dle = 0.0;
+            pr.lse_m = m;
+            pr.pad = 0.f;
+            a.parts[sg.rec] = pr;
+        }
+    } else if (MODE == MODE_FUSED_ISL) {
+        if (tid == 0) {
+            Part pr;
+            pr.isl = isl_t;
+            pr.lse_s = 0.0;
+            pr.dle = 0.0;
+            pr.lse_m = -INFINITY;
+            pr.pad = 0.f;
+            a.parts[sg.rec] = pr;
+        }
+    }
+    if constexpr (NEEDS_INV) {
+        const double dle_t = block_sum<WGS, double>(dle, scratch);
+        if (tid == 0) {
+            if (MODE == MODE_BWD_LOSS) {
+                a.parts[sg.rec].dle = dle_t;
+            } else if (MODE == MODE_BWD_MAG) {
+                Part pr;
+                pr.isl = 0.0;
+                pr.lse_s = 0.0;
+                pr.dle = dle_t;
+                pr.lse_m = -INFINITY;
+                pr.pad = 0.f;
+                a.parts[sg.rec] = pr;
+            }
+        }
+        float2* slab = a.slabs + w.slab_off + (int64_t)(sg.rec - w.seg_begin) * N;
+#pragma unroll
+        for (int i = 0; i < NACC; ++i) {
+            const int p = tid + WGS * i;
+            if (p < N) slab[p] = acc[i];
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------- variants and kernels --
+// A variant fixes points per lane P, the half-transform split, the work-group
+// size and the occupancy target; each kernel instance covers one transform
+// size MH = M/2 = 2^LG.  Gradient accumulators per thread: NACC = MH / WGS
+// (N <= M/2 = MH), at least one.
+template <int P_, int SPLIT_, int WGS_, int WAVES_, int LO_, int HI_, int S_LDS_>
+struct Variant {
+    static constexpr int P = P_, SPLIT = SPLIT_, WGS = WGS_, WAVES = WAVES_, LO = LO_, HI = HI_, S_LDS = S_LDS_;
+    static constexpr int nacc(int lg) { return (1 << lg) / WGS > 1 ? (1 << lg) / WGS : 1; }
+    static constexpr bool fits(int lg) {
+        return lg >= LO && lg <= HI && (1 << lg) >= P &&
+               (SPLIT ? 2 * ((1 << lg) / P) <= WGS : ((1 << lg) / P) <= WGS);
+    }
+    // dynamic LDS for the transform buffers of one instance
+    static constexpr int fft_lds_bytes(int lg) {
+        return (WGS / ((1 << lg) / P)) * ((1 << lg) + ((1 << lg) >> 5)) * 8;
+    }
+};
+
+//                        P  split WGS waves LG range  s in LDS
+using V0 = Variant<16, 1, 256, 2, 6, 11, 1>;  // M 128..4096
+using V1 = Variant<16, 1, 512, 2, 12, 12, 1>; // M 8192
+using V2 = Variant<32, 0, 512, 2, 13, 14, 0>; // M 16384..32768, halves in turn
+using V3 = Variant<8, 1, 256, 2, 6, 10, 1>;   // more lanes per lag, M <= 2048
+using V4 = Variant<32, 1, 256, 1, 8, 11, 1>;  // fewer passes, M 512..4096
+
+template <int MODE, typename V, int LG>
+__global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
+    extern __shared__ float2 dyn[];
+    __shared__ double scratch[64];
+    __shared__ int s_item;
+    float2* lds = dyn;
+    float2* s_lds = V::S_LDS ? dyn + V::fft_lds_bytes(LG) / 8 : nullptr;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.ctrl[0], 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= a.n_segs) break;
+        const SegDesc sg = a.segs[a.order[item]];
+        process_segment<MODE, (1 << LG), V::P, V::SPLIT, V::WGS, V::nacc(LG)>(a, sg, lds, s_lds, V::S_LDS != 0,
+                                                                             scratch);
+    }
+    // the last work group out resets the queue for the next launch
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned done = atomicAdd(&a.ctrl[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&a.ctrl[0], 0u);
+            atomicExch(&a.ctrl[1], 0u);
+        }
+    }
+}
+
+}  // namespace graf

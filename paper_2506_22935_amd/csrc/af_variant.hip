@@ -1,0 +1,57 @@
+// One kernel variant's instantiations, one per transform size it covers
+// (compiled once per GRAF_VARIANT so the variants build in parallel).
+#include "af_segment.h"
+
+#ifndef GRAF_VARIANT
+#error "GRAF_VARIANT must be defined"
+#endif
+
+namespace graf {
+
+#define GRAF_CAT2(a, b) a##b
+#define GRAF_CAT(a, b) GRAF_CAT2(a, b)
+using VSel = GRAF_CAT(V, GRAF_VARIANT);
+
+template <int MODE, int LG>
+static void* pick_lg(int lg) {
+    if constexpr (LG > 15) {
+        return nullptr;
+    } else {
+        if (lg == LG) {
+            if constexpr (VSel::fits(LG)) return (void*)af_kernel<MODE, VSel, LG>;
+            return nullptr;
+        }
+        return pick_lg<MODE, LG + 1>(lg);
+    }
+}
+
+void* GRAF_CAT(variant_kernel_, GRAF_VARIANT)(int mode, int lg) {
+    switch (mode) {
+        case MODE_FWD: return pick_lg<MODE_FWD, 1>(lg);
+        case MODE_BWD_MAG: return pick_lg<MODE_BWD_MAG, 1>(lg);
+        case MODE_BWD_LOSS: return pick_lg<MODE_BWD_LOSS, 1>(lg);
+        case MODE_FUSED_ISL: return pick_lg<MODE_FUSED_ISL, 1>(lg);
+    }
+    return nullptr;
+}
+
+VariantInfo GRAF_CAT(variant_info_, GRAF_VARIANT)(int lg) {
+    VariantInfo vi{};
+    vi.lo = VSel::LO;
+    vi.hi = VSel::HI;
+    vi.p = VSel::P;
+    vi.split = VSel::SPLIT;
+    vi.wgs = VSel::WGS;
+    vi.s_lds = VSel::S_LDS;
+    vi.fits = 0;
+    vi.fft_lds = 0;
+    vi.nacc = 0;
+    if (lg >= 1 && lg <= 15 && VSel::fits(lg)) {
+        vi.fits = 1;
+        vi.fft_lds = VSel::fft_lds_bytes(lg);
+        vi.nacc = VSel::nacc(lg);
+    }
+    return vi;
+}
+
+}  // namespace graf

@@ -1,0 +1,90 @@
+"""The C-ABI library loads, exports every entry point its header declares and
+rejects bad plans on the host (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2506_22935_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "graf_af.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(af_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libgraf_af.so not built")
+    return L.lib()
+
+
+def test_header_declares_the_bound_names():
+    assert set(declared()) == set(L.SIGNATURES)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in L.STATUS:
+        assert lib.af_status_string(code)
+    assert lib.af_version() >= 100
+
+
+def _create(lib, waves, **opt):
+    arr = (L.AfWave * len(waves))()
+    off = 0
+    goff = 0
+    for i, (n, m, T) in enumerate(waves):
+        arr[i].n, arr[i].m, arr[i].max_lag = n, m, T
+        arr[i].h_tau, arr[i].h_k, arr[i].reserved = 1, 1, 0
+        arr[i].s_off, arr[i].grid_off = off, goff
+        off += n
+        goff += (2 * (n - 1 if T < 0 else T) + 1) * m
+    for k, v in opt.get("fields", {}).items():
+        setattr(arr[0], k, v)
+    opts = L.AfPlanOpts(eps=1e-12, store_mode=opt.get("store_mode", 0), budget_bytes=0, variant=-1,
+                        segment_iters=0)
+    h = ctypes.c_void_p()
+    rc = lib.af_plan_create(len(waves), arr, ctypes.byref(opts), ctypes.byref(h))
+    if rc == 0:
+        lib.af_plan_destroy(h)
+    return rc
+
+
+@pytest.mark.parametrize("waves,code", [
+    ([(100, 128, -1)], -2),     # M < 2N
+    ([(64, 100, -1)], -2),      # M not a power of two
+    ([(32, 64, -1)], -2),       # M below the smallest supported size
+    ([(64, 65536, -1)], -2),    # M above the largest supported size
+    ([(64, 128, 64)], -1),      # lag window beyond N - 1
+    ([(0, 128, -1)], -1),       # empty waveform
+    ([(64, 128, -2)], -1),      # bad lag window
+])
+def test_plan_validation(lib, waves, code):
+    assert _create(lib, waves) == code
+
+
+def test_plan_validation_fields(lib):
+    assert _create(lib, [(64, 128, -1)], fields={"reserved": 1}) == -1
+    assert _create(lib, [(64, 128, -1)], fields={"grid_off": 2}) == -1
+    assert _create(lib, [(64, 128, -1)], fields={"h_tau": -1}) == -1
+    assert _create(lib, [(64, 128, -1)], store_mode=3) == -1
+
+
+def test_null_arguments(lib):
+    assert lib.af_plan_create(1, None, None, None) == -1
+    assert lib.af_forward(None, None, None, None, None, None, 0, None) == -1
+    assert lib.af_backward(None, None, None, None, None, 0, None) == -1
+    assert lib.af_phase_to_signal(None, None, 5, None) == -1
+    sz = ctypes.c_size_t()
+    assert lib.af_plan_workspace_size(None, ctypes.byref(sz)) == -1

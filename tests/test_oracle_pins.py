@@ -414,3 +414,24 @@ def test_mlp_backward_matches_torch_and_fd():
     fp = np.sum(O.mlp_forward(x, Wp, bs, False)[0] * up)
     fm = np.sum(O.mlp_forward(x, Wm, bs, False)[0] * up)
     assert abs((fp - fm) / (2 * h) - dW[1][2, 3]) < 1e-7
+
+
+# --------------------------------------------------------------------------
+# FFT-step route of the oracle (used at sizes the direct sums cannot reach)
+# --------------------------------------------------------------------------
+
+def test_fft_rows_match_direct_sum():
+    n, m, T = 45, 128, 30
+    s = rand_complex(n, 30)
+    taus = [-30, -7, 0, 1, 29]
+    direct = O.chi(s, m, T)[[t + T for t in taus]]
+    assert np.max(np.abs(O.chi_rows_fft(s, m, taus) - direct)) <= 1e-11 * O.energy(s)
+
+
+def test_fft_backward_matches_direct_sum():
+    n, m, T, eps = 40, 128, 17, 1e-12
+    s = rand_complex(n, 31)
+    ga = np.random.default_rng(32).standard_normal((2 * T + 1, m))
+    ref = O.magnitude_backward(s, m, T, ga, eps)
+    got = O.magnitude_backward_fft(s, m, T, ga, eps, rows_per_block=7)
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
