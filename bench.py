@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the differentiable ambiguity-function hot path on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single]
+
+A step is one pass of the whole hot path over one batch of synthetic input
+already resident in HBM.  Default workload "single": one random-phase code,
+N=1024, all 2047 lags x M=2048 Doppler bins, loss = ISL (mainlobe |tau|<=1,
+|k|<=1) + soft-PSL (T=0.05): forward with the a grid written to HBM, loss,
+backward through the hand-written adjoint to dL/d conj(s).
+
+Prints ONE JSON line (the last line on stdout).  Progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (published, packed)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def timed(fn, reps, torch):
+    """Average ms of fn() over reps launches, HIP events on the current stream."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline_single(n, m, seed):
+    """The float64 oracle (direct sums, OpenMP) on the same single-waveform
+    problem: loss + gradient once, as cells per second."""
+    import oracle as O
+    from oracle import _native
+    from paper_2506_22935_amd import workloads as W
+    s = O.to_c64_exact(W.random_code(n, seed=seed))
+    lp = O.LossParams(w_isl=1.0, w_psl=1.0, temp=0.05, h_tau=1, h_k=1, eps=1e-12)
+    t0 = time.perf_counter()
+    O.loss_and_grad(s, m, n - 1, lp)
+    dt = time.perf_counter() - t0
+    cells = (2 * n - 1) * m
+    return dict(value=cells / dt, unit="cells/s", cores=_native.threads(), kind="oracle",
+                sample="full %d-lag x %d-bin grid, loss + gradient once (%.1f s)" % (2 * n - 1, m, dt))
+
+
+def bench_single(args, torch):
+    from paper_2506_22935_amd import af, workloads as W
+    n, m = 1024, 2048
+    cells = (2 * n - 1) * m
+    s = torch.from_numpy(W.random_code(n, seed=args.seed)).cuda()
+    lp = dict(w_isl=1.0, w_psl=1.0, temp=0.05)
+    results = {}
+    modes = {"auto": (1, 2), "store": (1,), "recompute": (2,)}[args.store]
+    variants = [args.variant] if args.variant >= 0 else [0, 3, 4]
+    for store, variant in [(st, v) for st in modes for v in variants]:
+        try:
+            plan = af.Plan([n], [m], eps=1e-12, store_mode=store, variant=variant)
+        except Exception as e:  # variant does not fit this size
+            log("variant %d: %s" % (variant, e))
+            continue
+        ws = plan.workspace
+        terms = torch.empty(1, 4, device="cuda")
+        grad = torch.empty(n, dtype=torch.complex64, device="cuda")
+        mag = torch.empty(cells, dtype=torch.float32, device="cuda")
+
+        def step():
+            for st in (0, 1, 2):
+                plan.loss_stage(st, s, terms, grad, mag, ws=ws, **lp)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ms = timed(step, args.steps, torch)
+        stage_ms = [timed(lambda st=st: plan.loss_stage(st, s, terms, grad, mag, ws=ws, **lp), args.steps, torch)
+                    for st in (0, 1, 2)]
+        log("store=%d variant=%d: %.4f ms/step, stages %s" % (store, variant, ms, ["%.4f" % x for x in stage_ms]))
+        results[(store, variant)] = (ms, stage_ms, plan)
+    store, variant = min(results, key=lambda k: results[k][0])
+    ms, stage_ms, plan = results[(store, variant)]
+    logm = int(math.log2(m))
+
+    # roofline of the dominant kernel
+    names = ["forward (FFT + a grid + loss partials)", "backward (FFT adjoint + lag gather)", "reduce"]
+    dom = max(range(3), key=lambda i: stage_ms[i])
+    if dom == 0:
+        bytes_alg = 4.0 * cells  # the a grid it writes
+        ach = bytes_alg / (stage_ms[0] * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+    else:
+        flops = 5.0 * logm * cells  # the inverse transform over every cell
+        ach = flops / (stage_ms[dom] * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None)
+    roof["kernel"] = names[dom]
+    roof["kernel_ms"] = round(stage_ms[dom], 5)
+
+    # the materialised user-loss path: a grid out, dL/da grid in (8 B per cell)
+    mplan = af.Plan([n], [m], eps=1e-12, store_mode=2, variant=variant)
+    mws = mplan.workspace
+    ga = torch.from_numpy(W.upstream_grid(2 * n - 1, m, seed=1).ravel()).cuda()
+    mag2 = torch.empty(cells, dtype=torch.float32, device="cuda")
+    g2 = torch.empty(n, dtype=torch.complex64, device="cuda")
+
+    def mstep():
+        mplan.forward(s, mag=True, ws=mws, out_mag=mag2)
+        mplan.backward(s, ga, ws=mws, out=g2)
+
+    for _ in range(args.warmup):
+        mstep()
+    mms = timed(mstep, args.steps, torch)
+    mat = dict(ms_per_step=round(mms, 5), cells_per_s=cells / (mms * 1e-3),
+               hbm_frac_8B_per_cell=round(8.0 * cells / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    log("materialised fwd+bwd: %.4f ms" % mms)
+
+    out = dict(value=cells / (ms * 1e-3), ms_per_step=ms,
+               config=dict(workload="single: N=1024 random-phase code, 2047 lags x M=2048, "
+                                    "ISL(|tau|<=1,|k|<=1)+softPSL(T=0.05) fwd+bwd, a grid written",
+                           n=n, m=m, lags=2 * n - 1, cells=cells, store=bool(store == 1), variant=variant,
+                           stage_ms=[round(x, 5) for x in stage_ms], materialised_fwd_bwd=mat),
+               roofline=roof)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline_single(n, m, args.seed)
+    return out
+
+
+def bench_copy(args, torch):
+    """Plain device copy of known size (counter calibration)."""
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    ms = timed(lambda: b.copy_(a), args.steps, torch)
+    return dict(value=2.0 * nbytes / (ms * 1e-3) / 1e9, ms_per_step=ms,
+                config=dict(workload="copy: 1 GiB device-to-device"), unit="GB/s")
+
+
+WORKLOADS = {"single": bench_single, "copy": bench_copy}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="single", choices=sorted(WORKLOADS))
+    ap.add_argument("--store", default="auto", choices=["auto", "store", "recompute"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: time the candidates)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    log("workload", args.workload, "steps", args.steps, "warmup", args.warmup)
+    res = WORKLOADS[args.workload](args, torch)
+    line = dict(metric="AF fwd+bwd cells/s", value=res["value"], unit=res.get("unit", "cells/s"), n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=res["ms_per_step"], higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic", config=res["config"])
+    for k in ("roofline", "cpu_baseline"):
+        if k in res:
+            line[k] = res[k]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

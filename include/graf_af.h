@@ -149,6 +149,14 @@ af_status af_backward(const af_plan* plan, const void* s, const float* grad_mag,
 af_status af_loss(const af_plan* plan, const void* s, const af_loss_params* loss, float* terms, float* mag,
                   void* grad_s, void* ws, size_t ws_bytes, void* stream);
 
+/* One stage of af_loss on its own, for timing and profiling.  stage 0: the
+ * forward pass (a grids and loss partials; with w_psl == 0 and grad_s set,
+ * the single fused pass instead); stage 1: the backward pass (w_psl != 0 only;
+ * reads the partials of stage 0 from ws); stage 2: the reduction into terms
+ * and grad_s.  Running stages 0, 1, 2 in order equals one af_loss call. */
+af_status af_loss_stage(const af_plan* plan, int32_t stage, const void* s, const af_loss_params* loss,
+                        float* terms, float* mag, void* grad_s, void* ws, size_t ws_bytes, void* stream);
+
 /* s[i] = exp(j phi[i]) for i < count (device arrays). */
 af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream);
 

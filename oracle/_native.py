@@ -37,8 +37,15 @@ def lib():
         h.oracle_chi.restype = ctypes.c_int
         h.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         h.oracle_adjoint.restype = ctypes.c_int
+        h.oracle_threads.argtypes = []
+        h.oracle_threads.restype = ctypes.c_int
         _handle = h
     return _handle
+
+
+def threads():
+    """OpenMP threads the C core runs on."""
+    return int(lib().oracle_threads())
 
 
 def _ptr(a):

@@ -175,6 +175,13 @@ class Plan:
                                            _ptr(ws), ws.numel(), _stream()))
         return t, g, m
 
+    def loss_stage(self, stage, s, terms, grad, mag, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, ws=None):
+        """Run one stage (0 forward, 1 backward, 2 reduce) of loss(); for timing."""
+        ws = self.workspace if ws is None else ws
+        lp = self.loss_params(w_isl, w_psl, temp, band_w)
+        L.check("af_loss_stage", L.lib().af_loss_stage(self._h, int(stage), _ptr(s), ctypes.byref(lp), _ptr(terms),
+                                                       _ptr(mag), _ptr(grad), _ptr(ws), ws.numel(), _stream()))
+
     def optim_step(self, state, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, lr=0.01, betas=(0.9, 0.999),
                    eps=1e-8, ws=None, terms=None):
         """One Adam step on the phases held in `state` (see PhaseState)."""

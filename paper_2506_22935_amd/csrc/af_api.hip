@@ -66,13 +66,15 @@ struct af_plan {
     int log2_mmax = 0;
     int max_n = 0;
     int64_t cells = 0, store_bytes = 0;
-    size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_store = 0, ws_total = 0;
+    size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_partial = 0, off_store = 0, ws_total = 0;
 
     // plan-owned device tables
     WaveDesc* d_waves = nullptr;
     SegDesc* d_segs = nullptr;
     int* d_order = nullptr;
-    int2* d_chunks = nullptr;
+    int4* d_chunks = nullptr;       // reduce blocks
+    unsigned* d_chunk_ctr = nullptr; // per reduce chunk
+    size_t cap_chunk_ctr = 0;
     float2* d_tw = nullptr;
     unsigned* d_ctrl = nullptr;
     size_t cap_segs = 0, cap_chunks = 0;
@@ -87,6 +89,8 @@ void free_tables(af_plan* p) {
     if (p->d_chunks) (void)hipFree(p->d_chunks);
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_ctrl) (void)hipFree(p->d_ctrl);
+    if (p->d_chunk_ctr) (void)hipFree(p->d_chunk_ctr);
+    p->d_chunk_ctr = nullptr;
     p->d_waves = nullptr;
     p->d_segs = nullptr;
     p->d_order = nullptr;
@@ -176,7 +180,8 @@ af_status build_schedule(af_plan* p) {
     std::vector<WaveDesc> wd(B);
     std::vector<SegDesc> segs;
     std::vector<double> seg_cost;
-    std::vector<int2> chunks;
+    std::vector<int4> rblocks;  // reduce blocks: (wave, first sample, group | groups << 16, chunk)
+    int n_rchunks = 0;
     int64_t slab_elems = 0, store_elems = 0;
     for (int b = 0; b < B; ++b) {
         const af_wave& w = p->waves[b];
@@ -209,7 +214,9 @@ af_status build_schedule(af_plan* p) {
         d.seg_count = (int)segs.size() - d.seg_begin;
         slab_elems += (int64_t)d.seg_count * w.n;
         store_elems += (int64_t)(w.max_lag + 1) * w.m;
-        for (int c = 0; c < w.n; c += 256) chunks.push_back(make_int2(b, c));
+        const int ng = (d.seg_count + graf::kSlabGroup - 1) / graf::kSlabGroup;
+        for (int c = 0; c < w.n; c += 256, ++n_rchunks)
+            for (int g = 0; g < ng; ++g) rblocks.push_back(make_int4(b, c, g | (ng << 16), n_rchunks));
     }
     // execution order: by class, longest segment first within a class
     std::vector<int> order;
@@ -230,7 +237,8 @@ af_status build_schedule(af_plan* p) {
     const size_t energy_b = align256((size_t)B * sizeof(float));
     const size_t slabs_b = align256((size_t)slab_elems * sizeof(float2));
     const size_t store_b = align256((size_t)store_elems * sizeof(float2));
-    const size_t base = parts_b + energy_b + slabs_b;
+    const size_t partial_b = align256(rblocks.size() * 256 * sizeof(float2));
+    const size_t base = parts_b + energy_b + slabs_b + partial_b;
     bool stores;
     if (p->store_mode == 1)
         stores = true;
@@ -250,11 +258,18 @@ af_status build_schedule(af_plan* p) {
         if (hipMalloc(&p->d_order, segs.size() * sizeof(int)) != hipSuccess) return hip_fail();
         p->cap_segs = segs.size();
     }
-    if (chunks.size() > p->cap_chunks) {
+    if (rblocks.size() > p->cap_chunks) {
         if (p->d_chunks) (void)hipFree(p->d_chunks);
         p->d_chunks = nullptr;
-        if (hipMalloc(&p->d_chunks, chunks.size() * sizeof(int2)) != hipSuccess) return hip_fail();
-        p->cap_chunks = chunks.size();
+        if (hipMalloc(&p->d_chunks, rblocks.size() * sizeof(int4)) != hipSuccess) return hip_fail();
+        p->cap_chunks = rblocks.size();
+    }
+    if ((size_t)n_rchunks > p->cap_chunk_ctr) {
+        if (p->d_chunk_ctr) (void)hipFree(p->d_chunk_ctr);
+        p->d_chunk_ctr = nullptr;
+        if (hipMalloc(&p->d_chunk_ctr, (size_t)n_rchunks * sizeof(unsigned)) != hipSuccess) return hip_fail();
+        if (hipMemset(p->d_chunk_ctr, 0, (size_t)n_rchunks * sizeof(unsigned)) != hipSuccess) return hip_fail();
+        p->cap_chunk_ctr = (size_t)n_rchunks;
     }
     if (!p->d_waves && hipMalloc(&p->d_waves, (size_t)B * sizeof(WaveDesc)) != hipSuccess) return hip_fail();
     if (!p->d_ctrl) {
@@ -265,17 +280,18 @@ af_status build_schedule(af_plan* p) {
     if (hipMemcpy(p->d_waves, wd.data(), (size_t)B * sizeof(WaveDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_segs, segs.data(), segs.size() * sizeof(SegDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_chunks, chunks.data(), chunks.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(p->d_chunks, rblocks.data(), rblocks.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
         return hip_fail();
 
     p->classes = cls;
     p->stores = stores;
     p->n_segs = (int)segs.size();
-    p->n_chunks = (int)chunks.size();
+    p->n_chunks = (int)rblocks.size();
     p->store_bytes = (int64_t)store_elems * (int64_t)sizeof(float2);
     p->off_parts = 0;
     p->off_energy = parts_b;
     p->off_slabs = parts_b + energy_b;
+    p->off_partial = parts_b + energy_b + slabs_b;
     p->off_store = base;
     p->ws_total = base + (stores ? store_b : 0);
     return AF_OK;
@@ -300,6 +316,7 @@ struct WsView {
     graf::Part* parts;
     float* energy;
     float2* slabs;
+    float2* partial;
     float2* store;
 };
 
@@ -309,6 +326,7 @@ WsView ws_view(const af_plan* p, void* ws) {
     v.parts = (graf::Part*)(b + p->off_parts);
     v.energy = (float*)(b + p->off_energy);
     v.slabs = (float2*)(b + p->off_slabs);
+    v.partial = (float2*)(b + p->off_partial);
     v.store = p->stores ? (float2*)(b + p->off_store) : nullptr;
     return v;
 }
@@ -339,10 +357,12 @@ ReduceArgs reduce_args(const af_plan* p, const void* s, const WsView& v) {
     std::memset(&r, 0, sizeof(r));
     r.s = (const float2*)s;
     r.waves = p->d_waves;
-    r.chunks = p->d_chunks;
-    r.n_chunks = p->n_chunks;
+    r.blocks = p->d_chunks;
+    r.n_blocks = p->n_chunks;
     r.parts = v.parts;
     r.slabs = v.slabs;
+    r.partial = v.partial;
+    r.chunk_ctr = p->d_chunk_ctr;
     r.energy = v.energy;
     r.temp = 1.f;
     r.ctrl = p->d_ctrl + (kCtrlWords - 2);
@@ -549,6 +569,49 @@ af_status af_loss(const af_plan* p, const void* s, const af_loss_params* lp, flo
     r.terms = terms;
     r.skip_slabs = grad_s ? 0 : 1;
     return graf::launch_reduce(r, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
+}
+
+af_status af_loss_stage(const af_plan* p, int32_t stage, const void* s, const af_loss_params* lp, float* terms,
+                        float* mag, void* grad_s, void* ws, size_t ws_bytes, void* stream) {
+    af_status rc = check_common(p, s, ws, ws_bytes);
+    if (rc != AF_OK) return rc;
+    if ((rc = check_loss(lp)) != AF_OK) return rc;
+    if (!aligned(mag, 16) || !aligned(grad_s, 8) || !aligned(terms, 4) || !aligned(lp->band_w, 4))
+        return AF_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const WsView v = ws_view(p, ws);
+    AfArgs a = base_args(p, s, v);
+    a.w_isl = lp->w_isl;
+    a.w_psl = lp->w_psl;
+    a.temp = lp->psl_temp;
+    a.band_w = lp->band_w;
+    a.mag = mag;
+    const bool fused = lp->w_psl == 0.f && grad_s != nullptr;
+    switch (stage) {
+        case 0:
+            if (fused) return launch(p, graf::MODE_FUSED_ISL, a, st);
+            a.ystore = grad_s ? v.store : nullptr;
+            return launch(p, graf::MODE_FWD, a, st);
+        case 1:
+            if (fused || !grad_s) return AF_OK;
+            a.mag = nullptr;
+            a.ystore = v.store;
+            a.load_store = v.store != nullptr;
+            return launch(p, graf::MODE_BWD_LOSS, a, st);
+        case 2: {
+            if (!terms && !grad_s) return AF_OK;
+            ReduceArgs r = reduce_args(p, s, v);
+            r.w_isl = lp->w_isl;
+            r.w_psl = lp->w_psl;
+            r.temp = lp->psl_temp;
+            r.uniform_w = lp->band_w == nullptr;
+            r.grad = (float2*)grad_s;
+            r.terms = terms;
+            r.skip_slabs = grad_s ? 0 : 1;
+            return graf::launch_reduce(r, st) == hipSuccess ? AF_OK : AF_ERR_HIP;
+        }
+    }
+    return AF_ERR_INVALID_ARG;
 }
 
 af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream) {

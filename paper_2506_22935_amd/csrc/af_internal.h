@@ -66,13 +66,21 @@ struct AfArgs {
     unsigned* ctrl;       // [2] work-queue ticket and exit counters
 };
 
+// The slab reduction runs in blocks of 256 samples of one waveform times a
+// group of at most kSlabGroup segments; when a chunk has several groups, each
+// block leaves its partial sums and the last block of the chunk to finish
+// adds them in group order (deterministic), then finishes the chunk.
+constexpr int kSlabGroup = 32;
+
 struct ReduceArgs {
     const float2* s;
     const WaveDesc* waves;
-    const int2* chunks;   // (wave, first sample) per block of 256 samples
-    int n_chunks;
+    const int4* blocks;   // (wave, first sample, group | groups << 16, chunk)
+    int n_blocks;
     const Part* parts;
     const float2* slabs;
+    float2* partial;      // [n_blocks][256]
+    unsigned* chunk_ctr;  // per chunk, zero between launches
     const float* energy;
     float w_isl, w_psl, temp;
     float2* grad;         // dL/d conj(s), packed like s; nullable
@@ -85,7 +93,7 @@ struct ReduceArgs {
     float* adam_v;
     float2* s_next;       // exp(j phi_new)
     int* step;            // device step counter (1-based after increment)
-    unsigned* ctrl;       // [2] exit counter for the step increment
+    unsigned* ctrl;       // [1] exit counter for the step increment
     float lr, beta1, beta2, adam_eps;
 };
 

@@ -17,88 +17,162 @@ __device__ __forceinline__ void lse_merge_r(float& m, double& s, float m2, doubl
 }
 
 // --------------------------------------------------------------- reduce --
-// One block per (waveform, 256-sample chunk): sums the waveform's slabs in
-// segment order, adds dL/dE * s, optionally writes the loss terms.
-__device__ __forceinline__ void reduce_common(const ReduceArgs& a, int& wv, int& p, float2& g, float2& sp,
-                                              float& loss, float& isl, float& soft, float& E) {
-    const int2 ch = a.chunks[blockIdx.x];
-    wv = ch.x;
-    const WaveDesc w = a.waves[wv];
-    p = ch.y + (int)threadIdx.x;
-    const float inv_t2 = kLog2eR / a.temp;
-    double isl_raw = 0.0, s = 0.0, dle = 0.0;
-    float m = -INFINITY;
-    for (int j = 0; j < w.seg_count; ++j) {
-        const Part pr = a.parts[w.seg_begin + j];
-        isl_raw += pr.isl;
-        lse_merge_r(m, s, pr.lse_m, pr.lse_s, inv_t2);
-        dle += pr.dle;
-    }
-    E = a.energy[wv];
-    // complement waveforms carry ISL - M (Moyal: the full grid holds M E^2)
-    const double isl_d = isl_raw + ((a.uniform_w && w.full_window) ? (double)w.m : 0.0);
-    isl = (float)isl_d;
-    soft = (s > 0.0) ? (float)((double)m + (double)a.temp * log(s)) : 0.f;
-    loss = (float)((double)a.w_isl * isl_d + (a.w_psl != 0.f ? (double)a.w_psl * (double)soft : 0.0));
-    // dL/dE of the ISL part is -2 w_isl (collected sum) / E in both forms
-    const float dLdE = (float)(-2.0 * (double)a.w_isl * isl_raw / (double)E + dle);
-    g = make_float2(0.f, 0.f);
-    sp = make_float2(0.f, 0.f);
-    if (p < w.n && !a.skip_slabs) {
-        const float2* sl = a.slabs + w.slab_off + p;
-        for (int j = 0; j < w.seg_count; ++j) g = cadd(g, sl[(int64_t)j * w.n]);
-        sp = a.s[w.s_off + p];
-        g.x = fmaf(dLdE, sp.x, g.x);
-        g.y = fmaf(dLdE, sp.y, g.y);
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void wave_lse_r(float& m, double& s, float inv_t2) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float m2 = __shfl_xor(m, o, 64);
+        const double s2 = __shfl_xor(s, o, 64);
+        lse_merge_r(m, s, m2, s2, inv_t2);
     }
 }
 
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
-    int wv, p;
-    float2 g, sp;
-    float loss, isl, soft, E;
-    reduce_common(a, wv, p, g, sp, loss, isl, soft, E);
-    const WaveDesc& w = a.waves[wv];
-    if (p < w.n && a.grad) a.grad[w.s_off + p] = g;
-    if (a.chunks[blockIdx.x].y == 0 && threadIdx.x == 0 && a.terms) {
-        a.terms[4 * wv + 0] = loss;
-        a.terms[4 * wv + 1] = isl;
-        a.terms[4 * wv + 2] = soft;
-        a.terms[4 * wv + 3] = E;
+struct WaveTotals {
+    double isl_raw, lse_s, dle;
+    float lse_m;
+};
+
+// Totals of a waveform's segment records, merged by the 256-thread block in
+// a fixed order (thread-strided, wavefront butterflies, waves in order).
+__device__ WaveTotals wave_totals(const ReduceArgs& a, const WaveDesc& w, double* sh) {
+    const float inv_t2 = kLog2eR / a.temp;
+    double isl = 0.0, s = 0.0, dle = 0.0;
+    float m = -INFINITY;
+    for (int j = threadIdx.x; j < w.seg_count; j += 256) {
+        const Part pr = a.parts[w.seg_begin + j];
+        isl += pr.isl;
+        dle += pr.dle;
+        lse_merge_r(m, s, pr.lse_m, pr.lse_s, inv_t2);
     }
+    isl = wave_sum_d(isl);
+    dle = wave_sum_d(dle);
+    wave_lse_r(m, s, inv_t2);
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sh[4 * wv + 0] = isl;
+        sh[4 * wv + 1] = dle;
+        sh[4 * wv + 2] = (double)m;
+        sh[4 * wv + 3] = s;
+    }
+    __syncthreads();
+    WaveTotals t{0.0, 0.0, 0.0, -INFINITY};
+    for (int i = 0; i < 4; ++i) {
+        t.isl_raw += sh[4 * i + 0];
+        t.dle += sh[4 * i + 1];
+        lse_merge_r(t.lse_m, t.lse_s, (float)sh[4 * i + 2], sh[4 * i + 3], inv_t2);
+    }
+    return t;
+}
+
+__device__ __forceinline__ float2 load_partial(const float2* p) {
+    unsigned long long bits = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    return *reinterpret_cast<float2*>(&bits);
+}
+
+// Sum of the slabs of this block's chunk (all groups), or false if another
+// block of the chunk finishes it.
+__device__ bool chunk_sum(const ReduceArgs& a, const WaveDesc& w, int p, int g, int ng, int chunk, float2& sum) {
+    __shared__ int s_last;
+    sum = make_float2(0.f, 0.f);
+    if (!a.skip_slabs && p < w.n) {
+        const int j0 = g * kSlabGroup;
+        const int j1 = min(j0 + kSlabGroup, w.seg_count);
+        const float2* sl = a.slabs + w.slab_off + p;
+#pragma unroll 8
+        for (int j = j0; j < j1; ++j) sum = cadd(sum, sl[(int64_t)j * w.n]);
+    }
+    if (ng == 1) return true;
+    if (a.skip_slabs) return g == 0;
+    a.partial[(int64_t)blockIdx.x * 256 + threadIdx.x] = sum;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&a.chunk_ctr[chunk], 1u) == (unsigned)(ng - 1);
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    sum = make_float2(0.f, 0.f);
+    const int64_t first = (int64_t)(blockIdx.x - g);
+    for (int gg = 0; gg < ng; ++gg) sum = cadd(sum, load_partial(a.partial + (first + gg) * 256 + threadIdx.x));
+    if (threadIdx.x == 0) atomicExch(&a.chunk_ctr[chunk], 0u);
+    return true;
+}
+
+// loss terms and dL/dE from the totals
+__device__ __forceinline__ void finish_terms(const ReduceArgs& a, const WaveDesc& w, const WaveTotals& t, float E,
+                                             float& dLdE, float4& terms) {
+    // complement waveforms carry ISL - M (Moyal: the full grid holds M E^2)
+    const double isl = t.isl_raw + ((a.uniform_w && w.full_window) ? (double)w.m : 0.0);
+    const float soft = (t.lse_s > 0.0) ? (float)((double)t.lse_m + (double)a.temp * log(t.lse_s)) : 0.f;
+    const double loss = (double)a.w_isl * isl + (a.w_psl != 0.f ? (double)a.w_psl * (double)soft : 0.0);
+    // dL/dE of the ISL part is -2 w_isl (collected sum) / E in both forms
+    dLdE = (float)(-2.0 * (double)a.w_isl * t.isl_raw / (double)E + t.dle);
+    terms = make_float4((float)loss, (float)isl, soft, E);
+}
+
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
+    __shared__ double sh[16];
+    const int4 d = a.blocks[blockIdx.x];
+    const WaveDesc w = a.waves[d.x];
+    const int p = d.y + (int)threadIdx.x;
+    float2 g;
+    if (!chunk_sum(a, w, p, d.z & 0xffff, d.z >> 16, d.w, g)) return;
+    const WaveTotals tt = wave_totals(a, w, sh);
+    const float E = a.energy[d.x];
+    float dLdE;
+    float4 terms;
+    finish_terms(a, w, tt, E, dLdE, terms);
+    if (p < w.n && a.grad) {
+        const float2 sp = a.s[w.s_off + p];
+        g.x = fmaf(dLdE, sp.x, g.x);
+        g.y = fmaf(dLdE, sp.y, g.y);
+        a.grad[w.s_off + p] = g;
+    }
+    if (d.y == 0 && threadIdx.x == 0 && a.terms) reinterpret_cast<float4*>(a.terms)[d.x] = terms;
 }
 
 // Reduce, then one Adam step on the phases of s = exp(j phi) (Sec. 6.2's
 // update with the Sec. 7.1.2 optimiser): dL/dphi = 2 Im(conj(s) g).
 __global__ __launch_bounds__(256) void reduce_adam_kernel(ReduceArgs a) {
+    __shared__ double sh[16];
     const int t_prev = *a.step;  // read before this block signals completion
-    int wv, p;
-    float2 g, sp;
-    float loss, isl, soft, E;
-    reduce_common(a, wv, p, g, sp, loss, isl, soft, E);
-    const WaveDesc& w = a.waves[wv];
-    if (p < w.n) {
-        const int64_t i = w.s_off + p;
-        const float dphi = 2.f * (sp.x * g.y - sp.y * g.x);
-        const float t = (float)(t_prev + 1);
-        float m = a.adam_m[i], v = a.adam_v[i];
-        m = fmaf(a.beta1, m, (1.f - a.beta1) * dphi);
-        v = fmaf(a.beta2, v, (1.f - a.beta2) * dphi * dphi);
-        const float mh = m / (1.f - powf(a.beta1, t));
-        const float vh = v / (1.f - powf(a.beta2, t));
-        const float ph = a.phi[i] - a.lr * mh / (sqrtf(vh) + a.adam_eps);
-        a.adam_m[i] = m;
-        a.adam_v[i] = v;
-        a.phi[i] = ph;
-        float sn, cs;
-        sincosf(ph, &sn, &cs);
-        a.s_next[i] = make_float2(cs, sn);
-    }
-    if (a.chunks[blockIdx.x].y == 0 && threadIdx.x == 0 && a.terms) {
-        a.terms[4 * wv + 0] = loss;
-        a.terms[4 * wv + 1] = isl;
-        a.terms[4 * wv + 2] = soft;
-        a.terms[4 * wv + 3] = E;
+    const int4 d = a.blocks[blockIdx.x];
+    const WaveDesc w = a.waves[d.x];
+    const int p = d.y + (int)threadIdx.x;
+    float2 g;
+    if (chunk_sum(a, w, p, d.z & 0xffff, d.z >> 16, d.w, g)) {
+        const WaveTotals tt = wave_totals(a, w, sh);
+        const float E = a.energy[d.x];
+        float dLdE;
+        float4 terms;
+        finish_terms(a, w, tt, E, dLdE, terms);
+        if (p < w.n) {
+            const int64_t i = w.s_off + p;
+            const float2 sp = a.s[i];
+            g.x = fmaf(dLdE, sp.x, g.x);
+            g.y = fmaf(dLdE, sp.y, g.y);
+            const float dphi = 2.f * (sp.x * g.y - sp.y * g.x);
+            const float t = (float)(t_prev + 1);
+            float m = a.adam_m[i], v = a.adam_v[i];
+            m = fmaf(a.beta1, m, (1.f - a.beta1) * dphi);
+            v = fmaf(a.beta2, v, (1.f - a.beta2) * dphi * dphi);
+            const float mh = m / (1.f - powf(a.beta1, t));
+            const float vh = v / (1.f - powf(a.beta2, t));
+            const float ph = a.phi[i] - a.lr * mh / (sqrtf(vh) + a.adam_eps);
+            a.adam_m[i] = m;
+            a.adam_v[i] = v;
+            a.phi[i] = ph;
+            float sn, cs;
+            sincosf(ph, &sn, &cs);
+            a.s_next[i] = make_float2(cs, sn);
+        }
+        if (d.y == 0 && threadIdx.x == 0 && a.terms) reinterpret_cast<float4*>(a.terms)[d.x] = terms;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -173,14 +247,14 @@ hipError_t launch_af(int mode, int variant, int lg, const AfArgs& a, int grid, i
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
-    if (a.n_chunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3(a.n_chunks), dim3(256), 0, st, a);
+    if (a.n_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3(a.n_blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_adam(const ReduceArgs& a, hipStream_t st) {
-    if (a.n_chunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_adam_kernel, dim3(a.n_chunks), dim3(256), 0, st, a);
+    if (a.n_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_adam_kernel, dim3(a.n_blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

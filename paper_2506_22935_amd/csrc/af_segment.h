@@ -148,14 +148,28 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const bool want_lse = MODE == MODE_FWD && a.w_psl != 0.f;
     float glob_m = 0.f, glob_inv_s = 0.f;
     if (MODE == MODE_BWD_LOSS && a.w_psl != 0.f) {
+        // global soft-PSL normaliser of this waveform: the work group merges
+        // the forward pass records in a fixed order (thread-strided, then
+        // wavefront butterflies, then waves in order)
         float m = -INFINITY;
         double s = 0.0;
-        for (int j = 0; j < w.seg_count; ++j) {
+        for (int j = tid; j < w.seg_count; j += WGS) {
             const Part pr = a.parts[w.seg_begin + j];
             lse_merge(m, s, pr.lse_m, pr.lse_s, inv_t2);
         }
+        wave_lse(m, s, inv_t2);
+        __syncthreads();
+        if ((tid & 63) == 0) {
+            scratch[2 * (tid >> 6)] = (double)m;
+            scratch[2 * (tid >> 6) + 1] = s;
+        }
+        __syncthreads();
+        m = -INFINITY;
+        s = 0.0;
+        for (int i = 0; i < WGS / 64; ++i) lse_merge(m, s, (float)scratch[2 * i], scratch[2 * i + 1], inv_t2);
         glob_m = m;
         glob_inv_s = (float)(1.0 / s);
+        __syncthreads();
     }
     const bool banded = a.band_w != nullptr && w.band_off >= 0;
     const float* bu = banded ? a.band_w + w.band_off : nullptr;
