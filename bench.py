@@ -140,6 +140,63 @@ def bench_single(args, torch):
     return out
 
 
+def bench_uneven(args, torch):
+    """512 random-phase codes, N log-uniform in [64, 4096], M = next pow2 >= 2N,
+    full lag grid each, ISL loss forward + backward + one Adam step on the
+    phases per step, the K steps captured in one HIP graph and replayed."""
+    import numpy as np
+    from paper_2506_22935_amd import af, workloads as W
+    ns, ms, phases = W.uneven_batch(512, seed=args.seed)
+    cells = int(sum((2 * n - 1) * m for n, m in zip(ns, ms)))
+    plan = af.Plan(ns.tolist(), ms.tolist(), eps=1e-12)
+    log("uneven: %d waveforms, %.3g cells, %d segments" % (len(ns), cells, plan.summary()["segments"]))
+    st = af.PhaseState(torch.from_numpy(np.concatenate(phases).astype(np.float32)).cuda())
+    terms = torch.empty(plan.batch, 4, device="cuda")
+    ws = plan.workspace
+    for _ in range(args.warmup):
+        plan.optim_step(st, w_isl=1.0, lr=0.01, terms=terms, ws=ws)
+    torch.cuda.synchronize()
+    isl0 = float(terms[:, 1].sum())
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(args.steps):
+                plan.optim_step(st, w_isl=1.0, lr=0.01, terms=terms, ws=ws)
+    torch.cuda.synchronize()
+    ms_total = timed(g.replay, 1, torch)
+    isl1 = float(terms[:, 1].sum())
+    ms_step = ms_total / args.steps
+    # the fused ISL pass alone (one persistent launch per size class)
+    grad = torch.empty(plan.total_samples, dtype=torch.complex64, device="cuda")
+    fused_ms = timed(lambda: plan.loss_stage(0, st.s, terms, grad, None, w_isl=1.0, ws=ws), 20, torch)
+    flops = sum(10.0 * math.log2(m) * (2 * n - 1) * m for n, m in zip(ns, ms))  # forward + inverse
+    ach = flops / (fused_ms * 1e-3) / 1e12
+    log("uneven: %.3f ms/step (graph), fused pass %.3f ms, sum ISL %.4g -> %.4g" % (ms_step, fused_ms, isl0, isl1))
+    out = dict(value=cells / (ms_step * 1e-3), ms_per_step=ms_step,
+               config=dict(workload="uneven: 512 random-phase codes, N log-uniform [64,4096], M=next pow2>=2N, "
+                                    "full lag grid, ISL fwd+bwd + Adam step, %d steps in one HIP graph" % args.steps,
+                           waveforms=len(ns), cells=cells, segments=plan.summary()["segments"],
+                           isl_sum_before=isl0, isl_sum_after=isl1),
+               roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                             frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
+                             kernel="fused ISL forward+backward (all size classes)", kernel_ms=round(fused_ms, 4)))
+    if not args.no_cpu_baseline:
+        import oracle as O
+        from oracle import _native
+        order = np.argsort(ns)[:8]
+        t0 = time.perf_counter()
+        c = 0
+        for b in order:
+            n, m = int(ns[b]), int(ms[b])
+            O.loss_and_grad(O.to_c64_exact(W.unimodular(phases[b])), m, n - 1, O.LossParams(eps=1e-12))
+            c += (2 * n - 1) * m
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=c / dt, unit="cells/s", cores=_native.threads(), kind="oracle",
+                                   sample="loss + gradient of the 8 shortest waveforms (%.1f s)" % dt)
+    return out
+
+
 def bench_copy(args, torch):
     """Plain device copy of known size (counter calibration)."""
     nbytes = 1 << 30
@@ -152,7 +209,7 @@ def bench_copy(args, torch):
                 config=dict(workload="copy: 1 GiB device-to-device"), unit="GB/s")
 
 
-WORKLOADS = {"single": bench_single, "copy": bench_copy}
+WORKLOADS = {"single": bench_single, "uneven": bench_uneven, "copy": bench_copy}
 
 
 def main():

@@ -62,19 +62,17 @@ struct af_plan {
     std::vector<int> forced;  // per class: variant forced by the autotuner (-1: default)
     int opt_variant = -1;
     bool stores = false;
-    int n_segs = 0, n_chunks = 0;
+    int n_segs = 0, n_chunks = 0, sg_log = 2;
     int log2_mmax = 0;
     int max_n = 0;
     int64_t cells = 0, store_bytes = 0;
-    size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_partial = 0, off_store = 0, ws_total = 0;
+    size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_store = 0, ws_total = 0;
 
     // plan-owned device tables
     WaveDesc* d_waves = nullptr;
     SegDesc* d_segs = nullptr;
     int* d_order = nullptr;
-    int4* d_chunks = nullptr;       // reduce blocks
-    unsigned* d_chunk_ctr = nullptr; // per reduce chunk
-    size_t cap_chunk_ctr = 0;
+    int2* d_chunks = nullptr;  // reduce blocks
     float2* d_tw = nullptr;
     unsigned* d_ctrl = nullptr;
     size_t cap_segs = 0, cap_chunks = 0;
@@ -89,8 +87,6 @@ void free_tables(af_plan* p) {
     if (p->d_chunks) (void)hipFree(p->d_chunks);
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_ctrl) (void)hipFree(p->d_ctrl);
-    if (p->d_chunk_ctr) (void)hipFree(p->d_chunk_ctr);
-    p->d_chunk_ctr = nullptr;
     p->d_waves = nullptr;
     p->d_segs = nullptr;
     p->d_order = nullptr;
@@ -180,8 +176,7 @@ af_status build_schedule(af_plan* p) {
     std::vector<WaveDesc> wd(B);
     std::vector<SegDesc> segs;
     std::vector<double> seg_cost;
-    std::vector<int4> rblocks;  // reduce blocks: (wave, first sample, group | groups << 16, chunk)
-    int n_rchunks = 0;
+    std::vector<int2> rblocks;  // reduce blocks: (wave, first sample)
     int64_t slab_elems = 0, store_elems = 0;
     for (int b = 0; b < B; ++b) {
         const af_wave& w = p->waves[b];
@@ -214,10 +209,16 @@ af_status build_schedule(af_plan* p) {
         d.seg_count = (int)segs.size() - d.seg_begin;
         slab_elems += (int64_t)d.seg_count * w.n;
         store_elems += (int64_t)(w.max_lag + 1) * w.m;
-        const int ng = (d.seg_count + graf::kSlabGroup - 1) / graf::kSlabGroup;
-        for (int c = 0; c < w.n; c += 256, ++n_rchunks)
-            for (int g = 0; g < ng; ++g) rblocks.push_back(make_int4(b, c, g | (ng << 16), n_rchunks));
+        (void)0;
     }
+    // reduce blocks: 16 slab subgroups per block when waveforms have many
+    // segments, 4 otherwise
+    int max_segs = 0;
+    for (int b = 0; b < B; ++b) max_segs = std::max(max_segs, wd[b].seg_count);
+    const int sg_log = max_segs >= 64 ? 4 : 2;
+    for (int b = 0; b < B; ++b)
+        for (int c = 0; c < wd[b].n; c += (256 >> sg_log)) rblocks.push_back(make_int2(b, c));
+
     // execution order: by class, longest segment first within a class
     std::vector<int> order;
     order.reserve(segs.size());
@@ -232,13 +233,15 @@ af_status build_schedule(af_plan* p) {
         for (int mode = 0; mode < 4; ++mode) cls[c].grid[mode] = std::min(cls[c].grid[mode], cls[c].count);
     }
 
+    std::vector<SegDesc> exec(order.size());
+    for (size_t i = 0; i < order.size(); ++i) exec[i] = segs[order[i]];
+
     // workspace layout and the store decision
     const size_t parts_b = align256(segs.size() * sizeof(graf::Part));
     const size_t energy_b = align256((size_t)B * sizeof(float));
     const size_t slabs_b = align256((size_t)slab_elems * sizeof(float2));
     const size_t store_b = align256((size_t)store_elems * sizeof(float2));
-    const size_t partial_b = align256(rblocks.size() * 256 * sizeof(float2));
-    const size_t base = parts_b + energy_b + slabs_b + partial_b;
+    const size_t base = parts_b + energy_b + slabs_b;
     bool stores;
     if (p->store_mode == 1)
         stores = true;
@@ -261,15 +264,8 @@ af_status build_schedule(af_plan* p) {
     if (rblocks.size() > p->cap_chunks) {
         if (p->d_chunks) (void)hipFree(p->d_chunks);
         p->d_chunks = nullptr;
-        if (hipMalloc(&p->d_chunks, rblocks.size() * sizeof(int4)) != hipSuccess) return hip_fail();
+        if (hipMalloc(&p->d_chunks, rblocks.size() * sizeof(int2)) != hipSuccess) return hip_fail();
         p->cap_chunks = rblocks.size();
-    }
-    if ((size_t)n_rchunks > p->cap_chunk_ctr) {
-        if (p->d_chunk_ctr) (void)hipFree(p->d_chunk_ctr);
-        p->d_chunk_ctr = nullptr;
-        if (hipMalloc(&p->d_chunk_ctr, (size_t)n_rchunks * sizeof(unsigned)) != hipSuccess) return hip_fail();
-        if (hipMemset(p->d_chunk_ctr, 0, (size_t)n_rchunks * sizeof(unsigned)) != hipSuccess) return hip_fail();
-        p->cap_chunk_ctr = (size_t)n_rchunks;
     }
     if (!p->d_waves && hipMalloc(&p->d_waves, (size_t)B * sizeof(WaveDesc)) != hipSuccess) return hip_fail();
     if (!p->d_ctrl) {
@@ -278,20 +274,20 @@ af_status build_schedule(af_plan* p) {
     }
     if (2 * C + 2 > kCtrlWords) return AF_ERR_UNSUPPORTED;
     if (hipMemcpy(p->d_waves, wd.data(), (size_t)B * sizeof(WaveDesc), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_segs, segs.data(), segs.size() * sizeof(SegDesc), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_segs, exec.data(), exec.size() * sizeof(SegDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_chunks, rblocks.data(), rblocks.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(p->d_chunks, rblocks.data(), rblocks.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
         return hip_fail();
 
     p->classes = cls;
     p->stores = stores;
     p->n_segs = (int)segs.size();
     p->n_chunks = (int)rblocks.size();
+    p->sg_log = sg_log;
     p->store_bytes = (int64_t)store_elems * (int64_t)sizeof(float2);
     p->off_parts = 0;
     p->off_energy = parts_b;
     p->off_slabs = parts_b + energy_b;
-    p->off_partial = parts_b + energy_b + slabs_b;
     p->off_store = base;
     p->ws_total = base + (stores ? store_b : 0);
     return AF_OK;
@@ -316,7 +312,6 @@ struct WsView {
     graf::Part* parts;
     float* energy;
     float2* slabs;
-    float2* partial;
     float2* store;
 };
 
@@ -326,7 +321,6 @@ WsView ws_view(const af_plan* p, void* ws) {
     v.parts = (graf::Part*)(b + p->off_parts);
     v.energy = (float*)(b + p->off_energy);
     v.slabs = (float2*)(b + p->off_slabs);
-    v.partial = (float2*)(b + p->off_partial);
     v.store = p->stores ? (float2*)(b + p->off_store) : nullptr;
     return v;
 }
@@ -337,7 +331,6 @@ AfArgs base_args(const af_plan* p, const void* s, const WsView& v) {
     a.s = (const float2*)s;
     a.waves = p->d_waves;
     a.segs = p->d_segs;
-    a.order = p->d_order;
     a.n_segs = 0;
     a.log2_mmax = p->log2_mmax;
     a.tw = p->d_tw;
@@ -348,7 +341,6 @@ AfArgs base_args(const af_plan* p, const void* s, const WsView& v) {
     a.parts = v.parts;
     a.slabs = v.slabs;
     a.energy = v.energy;
-    a.ctrl = nullptr;
     return a;
 }
 
@@ -359,10 +351,9 @@ ReduceArgs reduce_args(const af_plan* p, const void* s, const WsView& v) {
     r.waves = p->d_waves;
     r.blocks = p->d_chunks;
     r.n_blocks = p->n_chunks;
+    r.sg_log = p->sg_log;
     r.parts = v.parts;
     r.slabs = v.slabs;
-    r.partial = v.partial;
-    r.chunk_ctr = p->d_chunk_ctr;
     r.energy = v.energy;
     r.temp = 1.f;
     r.ctrl = p->d_ctrl + (kCtrlWords - 2);
@@ -375,9 +366,8 @@ af_status launch(const af_plan* p, int mode, const AfArgs& a0, hipStream_t st, i
         if (only_class >= 0 && c != only_class) continue;
         const af_plan::Class& k = p->classes[c];
         AfArgs a = a0;
-        a.order = p->d_order + k.begin;
+        a.segs = p->d_segs + k.begin;
         a.n_segs = k.count;
-        a.ctrl = p->d_ctrl + 2 * c;
         hipError_t e = graf::launch_af(mode, k.variant, k.lg, a, k.grid[mode], k.dyn_lds, st);
         if (e != hipSuccess) return AF_ERR_HIP;
     }

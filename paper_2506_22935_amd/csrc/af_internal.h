@@ -47,8 +47,7 @@ enum Mode : int {
 struct AfArgs {
     const float2* s;
     const WaveDesc* waves;
-    const SegDesc* segs;
-    const int* order;     // execution order of segment indices
+    const SegDesc* segs;  // this launch's items in execution order
     int n_segs;
     int log2_mmax;
     const float2* tw;     // exp(-j 2 pi i / MMAX), i < MMAX
@@ -63,24 +62,21 @@ struct AfArgs {
     Part* parts;          // [records]
     float2* slabs;        // [sum segs*N]
     float* energy;        // [B], written by the segment holding lag 0
-    unsigned* ctrl;       // [2] work-queue ticket and exit counters
 };
 
-// The slab reduction runs in blocks of 256 samples of one waveform times a
-// group of at most kSlabGroup segments; when a chunk has several groups, each
-// block leaves its partial sums and the last block of the chunk to finish
-// adds them in group order (deterministic), then finishes the chunk.
-constexpr int kSlabGroup = 32;
+// The slab reduction runs 256-thread blocks over (256 >> sg_log) samples of
+// one waveform; the threads split the waveform's slabs into 2^sg_log
+// interleaved subgroups and add the subgroup sums in a fixed order
+// (deterministic, no atomics).  sg_log is 2 or 4, picked by the planner.
 
 struct ReduceArgs {
     const float2* s;
     const WaveDesc* waves;
-    const int4* blocks;   // (wave, first sample, group | groups << 16, chunk)
+    const int2* blocks;   // (wave, first sample) per block
     int n_blocks;
+    int sg_log;           // log2 of the slab subgroups per block
     const Part* parts;
     const float2* slabs;
-    float2* partial;      // [n_blocks][256]
-    unsigned* chunk_ctr;  // per chunk, zero between launches
     const float* energy;
     float w_isl, w_psl, temp;
     float2* grad;         // dL/d conj(s), packed like s; nullable

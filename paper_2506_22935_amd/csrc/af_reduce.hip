@@ -70,38 +70,27 @@ __device__ WaveTotals wave_totals(const ReduceArgs& a, const WaveDesc& w, double
     return t;
 }
 
-__device__ __forceinline__ float2 load_partial(const float2* p) {
-    unsigned long long bits = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    return *reinterpret_cast<float2*>(&bits);
-}
-
-// Sum of the slabs of this block's chunk (all groups), or false if another
-// block of the chunk finishes it.
-__device__ bool chunk_sum(const ReduceArgs& a, const WaveDesc& w, int p, int g, int ng, int chunk, float2& sum) {
-    __shared__ int s_last;
-    sum = make_float2(0.f, 0.f);
+// Sum over the waveform's slabs for this block's samples: thread t adds
+// slabs t>>pb_log, (t>>pb_log) + SG, ... of sample t & (PB-1); the SG
+// subgroup sums meet in LDS and are added in subgroup order.
+__device__ __forceinline__ float2 slab_sum(const ReduceArgs& a, const WaveDesc& w, int p, float2* sh2) {
+    const int pb_log = 8 - a.sg_log;
+    const int sub = threadIdx.x >> pb_log;
+    const int SG = 1 << a.sg_log;
+    float2 sum = make_float2(0.f, 0.f);
     if (!a.skip_slabs && p < w.n) {
-        const int j0 = g * kSlabGroup;
-        const int j1 = min(j0 + kSlabGroup, w.seg_count);
         const float2* sl = a.slabs + w.slab_off + p;
 #pragma unroll 8
-        for (int j = j0; j < j1; ++j) sum = cadd(sum, sl[(int64_t)j * w.n]);
+        for (int j = sub; j < w.seg_count; j += SG) sum = cadd(sum, sl[(int64_t)j * w.n]);
     }
-    if (ng == 1) return true;
-    if (a.skip_slabs) return g == 0;
-    a.partial[(int64_t)blockIdx.x * 256 + threadIdx.x] = sum;
-    __threadfence();
+    sh2[threadIdx.x] = sum;
     __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(&a.chunk_ctr[chunk], 1u) == (unsigned)(ng - 1);
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    sum = make_float2(0.f, 0.f);
-    const int64_t first = (int64_t)(blockIdx.x - g);
-    for (int gg = 0; gg < ng; ++gg) sum = cadd(sum, load_partial(a.partial + (first + gg) * 256 + threadIdx.x));
-    if (threadIdx.x == 0) atomicExch(&a.chunk_ctr[chunk], 0u);
-    return true;
+    float2 g = make_float2(0.f, 0.f);
+    if (sub == 0) {
+        const int lane = threadIdx.x;
+        for (int k = 0; k < SG; ++k) g = cadd(g, sh2[(k << pb_log) + lane]);
+    }
+    return g;
 }
 
 // loss terms and dL/dE from the totals
@@ -118,17 +107,17 @@ __device__ __forceinline__ void finish_terms(const ReduceArgs& a, const WaveDesc
 
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
     __shared__ double sh[16];
-    const int4 d = a.blocks[blockIdx.x];
+    __shared__ float2 sh2[256];
+    const int2 d = a.blocks[blockIdx.x];
     const WaveDesc w = a.waves[d.x];
-    const int p = d.y + (int)threadIdx.x;
-    float2 g;
-    if (!chunk_sum(a, w, p, d.z & 0xffff, d.z >> 16, d.w, g)) return;
+    const int p = d.y + (int)(threadIdx.x & ((256 >> a.sg_log) - 1));
     const WaveTotals tt = wave_totals(a, w, sh);
+    float2 g = slab_sum(a, w, p, sh2);
     const float E = a.energy[d.x];
     float dLdE;
     float4 terms;
     finish_terms(a, w, tt, E, dLdE, terms);
-    if (p < w.n && a.grad) {
+    if ((int)threadIdx.x < (256 >> a.sg_log) && p < w.n && a.grad) {
         const float2 sp = a.s[w.s_off + p];
         g.x = fmaf(dLdE, sp.x, g.x);
         g.y = fmaf(dLdE, sp.y, g.y);
@@ -141,39 +130,38 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
 // update with the Sec. 7.1.2 optimiser): dL/dphi = 2 Im(conj(s) g).
 __global__ __launch_bounds__(256) void reduce_adam_kernel(ReduceArgs a) {
     __shared__ double sh[16];
+    __shared__ float2 sh2[256];
     const int t_prev = *a.step;  // read before this block signals completion
-    const int4 d = a.blocks[blockIdx.x];
+    const int2 d = a.blocks[blockIdx.x];
     const WaveDesc w = a.waves[d.x];
-    const int p = d.y + (int)threadIdx.x;
-    float2 g;
-    if (chunk_sum(a, w, p, d.z & 0xffff, d.z >> 16, d.w, g)) {
-        const WaveTotals tt = wave_totals(a, w, sh);
-        const float E = a.energy[d.x];
-        float dLdE;
-        float4 terms;
-        finish_terms(a, w, tt, E, dLdE, terms);
-        if (p < w.n) {
-            const int64_t i = w.s_off + p;
-            const float2 sp = a.s[i];
-            g.x = fmaf(dLdE, sp.x, g.x);
-            g.y = fmaf(dLdE, sp.y, g.y);
-            const float dphi = 2.f * (sp.x * g.y - sp.y * g.x);
-            const float t = (float)(t_prev + 1);
-            float m = a.adam_m[i], v = a.adam_v[i];
-            m = fmaf(a.beta1, m, (1.f - a.beta1) * dphi);
-            v = fmaf(a.beta2, v, (1.f - a.beta2) * dphi * dphi);
-            const float mh = m / (1.f - powf(a.beta1, t));
-            const float vh = v / (1.f - powf(a.beta2, t));
-            const float ph = a.phi[i] - a.lr * mh / (sqrtf(vh) + a.adam_eps);
-            a.adam_m[i] = m;
-            a.adam_v[i] = v;
-            a.phi[i] = ph;
-            float sn, cs;
-            sincosf(ph, &sn, &cs);
-            a.s_next[i] = make_float2(cs, sn);
-        }
-        if (d.y == 0 && threadIdx.x == 0 && a.terms) reinterpret_cast<float4*>(a.terms)[d.x] = terms;
+    const int p = d.y + (int)(threadIdx.x & ((256 >> a.sg_log) - 1));
+    const WaveTotals tt = wave_totals(a, w, sh);
+    float2 g = slab_sum(a, w, p, sh2);
+    const float E = a.energy[d.x];
+    float dLdE;
+    float4 terms;
+    finish_terms(a, w, tt, E, dLdE, terms);
+    if ((int)threadIdx.x < (256 >> a.sg_log) && p < w.n) {
+        const int64_t i = w.s_off + p;
+        const float2 sp = a.s[i];
+        g.x = fmaf(dLdE, sp.x, g.x);
+        g.y = fmaf(dLdE, sp.y, g.y);
+        const float dphi = 2.f * (sp.x * g.y - sp.y * g.x);
+        const float t = (float)(t_prev + 1);
+        float m = a.adam_m[i], v = a.adam_v[i];
+        m = fmaf(a.beta1, m, (1.f - a.beta1) * dphi);
+        v = fmaf(a.beta2, v, (1.f - a.beta2) * dphi * dphi);
+        const float mh = m / (1.f - powf(a.beta1, t));
+        const float vh = v / (1.f - powf(a.beta2, t));
+        const float ph = a.phi[i] - a.lr * mh / (sqrtf(vh) + a.adam_eps);
+        a.adam_m[i] = m;
+        a.adam_v[i] = v;
+        a.phi[i] = ph;
+        float sn, cs;
+        sincosf(ph, &sn, &cs);
+        a.s_next[i] = make_float2(cs, sn);
     }
+    if (d.y == 0 && threadIdx.x == 0 && a.terms) reinterpret_cast<float4*>(a.terms)[d.x] = terms;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();

@@ -97,9 +97,91 @@ __device__ __forceinline__ int floor_div_small(int a, int d) {
 // In SPLIT mode the magnitude / upstream rows of a lag are staged through the
 // lag's two transform buffers (2 * (MH + MH/32) complex >= 2 rows of M floats)
 // so that global traffic is coalesced 16-byte row accesses.
+// Per-waveform state a work group keeps across the segments it runs: the
+// energy, the soft-PSL normaliser (backward of the loss) and the samples
+// staged in LDS.
+struct WaveState {
+    int wave;
+    float E;
+    float glob_m, glob_inv_s;
+};
+
+// Stage waveform `wave` (N <= MH samples) into LDS and compute its energy;
+// with twl != nullptr also copy this size's twiddles w_M^i (i < 2 MH) from the
+// global table, all loads issued before any LDS store so that one memory
+// round trip covers both.
+template <int MODE, int WGS, int MH>
+__device__ void stage_wave(const AfArgs& a, int wave, float2* s_lds, bool s_in_lds, double* scratch, WaveState& st,
+                           float2* twl, int twsh) {
+    constexpr int NPT = (MH + WGS - 1) / WGS;
+    constexpr int TPT = (2 * MH + WGS - 1) / WGS;
+    const WaveDesc w = a.waves[wave];
+    const int tid = threadIdx.x;
+    const float2* __restrict__ sg_s = a.s + w.s_off;
+    float2 sx[NPT];
+    float2 tx[TPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int p = tid + i * WGS;
+        sx[i] = p < w.n ? sg_s[p] : make_float2(0.f, 0.f);
+    }
+    if (twl) {
+#pragma unroll
+        for (int i = 0; i < TPT; ++i) {
+            const int j = tid + i * WGS;
+            tx[i] = j < 2 * MH ? a.tw[j << twsh] : make_float2(0.f, 0.f);
+        }
+    }
+    __syncthreads();  // the previous segment is done with s_lds and scratch
+    float e = 0.f;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int p = tid + i * WGS;
+        e += cabs2(sx[i]);
+        if (s_in_lds && p < w.n) s_lds[p] = sx[i];
+    }
+    if (twl) {
+#pragma unroll
+        for (int i = 0; i < TPT; ++i) {
+            const int j = tid + i * WGS;
+            if (j < 2 * MH) twl[j] = tx[i];
+        }
+    }
+    st.wave = wave;
+    st.E = block_sum<WGS, float>(e, scratch);
+    st.glob_m = 0.f;
+    st.glob_inv_s = 0.f;
+    if (MODE == MODE_BWD_LOSS && a.w_psl != 0.f) {
+        // global soft-PSL normaliser of this waveform: the work group merges
+        // the forward pass records in a fixed order (thread-strided, then
+        // wavefront butterflies, then waves in order)
+        const float inv_t2 = kLog2e / a.temp;
+        float m = -INFINITY;
+        double s = 0.0;
+        for (int j = tid; j < w.seg_count; j += WGS) {
+            const Part pr = a.parts[w.seg_begin + j];
+            lse_merge(m, s, pr.lse_m, pr.lse_s, inv_t2);
+        }
+        wave_lse(m, s, inv_t2);
+        __syncthreads();
+        if ((tid & 63) == 0) {
+            scratch[2 * (tid >> 6)] = (double)m;
+            scratch[2 * (tid >> 6) + 1] = s;
+        }
+        __syncthreads();
+        m = -INFINITY;
+        s = 0.0;
+        for (int i = 0; i < WGS / 64; ++i) lse_merge(m, s, (float)scratch[2 * i], scratch[2 * i + 1], inv_t2);
+        st.glob_m = m;
+        st.glob_inv_s = (float)(1.0 / s);
+    }
+    __syncthreads();
+}
+
 template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC>
-__device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, float2* s_lds,
-                                                bool s_in_lds, double* scratch) {
+__device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, const float2* twl,
+                                                int twsh, const float2* s_lds, bool s_in_lds, double* scratch,
+                                                const WaveState& ws) {
     constexpr int L = MH / P;
     constexpr int G = WGS / L;
     constexpr int LPI = SPLIT ? G / 2 : G;
@@ -126,51 +208,17 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const int tshift = a.log2_mmax - w.log2m;  // w_M^i = tw[i << tshift]
     const float2* __restrict__ sg_s = a.s + w.s_off;
     const float2* __restrict__ tw = a.tw;
-    const int tw_mh = 1 << (a.log2_mmax - Plan<MH, P>::LOG_MH);
+    const int tw_mh = 2 << twsh;  // table entries per MH
     auto sync = []() { __syncthreads(); };
 
-    // energy E = sum |s|^2, fixed reduction order
-    float e = 0.f;
-    for (int p = tid; p < N; p += WGS) e += cabs2(sg_s[p]);
-    const float E = block_sum<WGS, float>(e, scratch);
+    const float E = ws.E;
     if (sg.tau_begin == 0 && tid == 0) a.energy[sg.wave] = E;
     const float invE = 1.0f / E;
     const float invE2 = invE * invE;
-
-    const float2* __restrict__ sv = sg_s;
-    if (s_in_lds) {
-        for (int p = tid; p < N; p += WGS) s_lds[p] = sg_s[p];
-        __syncthreads();
-        sv = s_lds;
-    }
-
+    const float2* __restrict__ sv = s_in_lds ? s_lds : sg_s;
     const float inv_t2 = kLog2e / a.temp;
     const bool want_lse = MODE == MODE_FWD && a.w_psl != 0.f;
-    float glob_m = 0.f, glob_inv_s = 0.f;
-    if (MODE == MODE_BWD_LOSS && a.w_psl != 0.f) {
-        // global soft-PSL normaliser of this waveform: the work group merges
-        // the forward pass records in a fixed order (thread-strided, then
-        // wavefront butterflies, then waves in order)
-        float m = -INFINITY;
-        double s = 0.0;
-        for (int j = tid; j < w.seg_count; j += WGS) {
-            const Part pr = a.parts[w.seg_begin + j];
-            lse_merge(m, s, pr.lse_m, pr.lse_s, inv_t2);
-        }
-        wave_lse(m, s, inv_t2);
-        __syncthreads();
-        if ((tid & 63) == 0) {
-            scratch[2 * (tid >> 6)] = (double)m;
-            scratch[2 * (tid >> 6) + 1] = s;
-        }
-        __syncthreads();
-        m = -INFINITY;
-        s = 0.0;
-        for (int i = 0; i < WGS / 64; ++i) lse_merge(m, s, (float)scratch[2 * i], scratch[2 * i + 1], inv_t2);
-        glob_m = m;
-        glob_inv_s = (float)(1.0 / s);
-        __syncthreads();
-    }
+    const float glob_m = ws.glob_m, glob_inv_s = ws.glob_inv_s;
     const bool banded = a.band_w != nullptr && w.band_off >= 0;
     const float* bu = banded ? a.band_w + w.band_off : nullptr;
     const float* bv = banded ? a.band_w + w.band_off + 31 : nullptr;
@@ -225,11 +273,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     float2 x = make_float2(0.f, 0.f);
                     if (active && m < S) {
                         x = cmulc(sv[m + tau], sv[m]);
-                        if (h) x = cmul(x, tw[m << tshift]);
+                        if (h) x = cmul(x, twl[m << twsh]);
                     }
                     v[r] = x;
                 }
-                fft_group<MH, P, -1>(v, buf, l, tw, tw_mh, sync);
+                fft_group<MH, P, -1>(v, buf, l, twl, tw_mh, sync);
             }
             // v[q] = Y'[2 (l + qL) + h]
             if (MODE == MODE_FWD && a.ystore && active) {
@@ -249,14 +297,17 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 
             // ---------------------------------------------- epilogue --
             // p = |Y'|^2/E^2, a = sqrt(p + eps); the sidelobe test and the
-            // weight are symmetric under (tau, k) -> (-tau, -k)
+            // weight are symmetric under (tau, k) -> (-tau, -k).  Sums over
+            // the lane's bins run in float, then fold into float64.
+            float isl_f = 0.f, dle_f = 0.f, mloc = -INFINITY;
+            float avs[(MODE == MODE_FWD) ? P : 1];
 #pragma unroll
             for (int q = 0; q < P; ++q) {
                 const int k = 2 * (l + q * L) + h;
                 const int kn = k ? M - k : 0;
                 const int kc = k < (M >> 1) ? k : M - k;  // |centred bin|
                 const float pw = cabs2(v[q]) * invE2;
-                const float av = sqrtf(pw + a.eps);
+                const float av = __builtin_amdgcn_sqrtf(pw + a.eps);
                 const bool sd = active && !(main_tau && kc <= w.h_k);
                 float wt = 1.f;
                 if (banded && sd) wt = wu * bv[floor_div_small(31 * kc, (M >> 1) + 1)];
@@ -271,21 +322,14 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         }
                     }
                     if (compl_isl) {
-                        if (active && !sd) isl -= (double)(mult * pw);  // mainlobe power
+                        if (active && !sd) isl_f -= pw;  // mainlobe power
                     } else if (sd) {
-                        isl += (double)(mult * wt * pw);
+                        isl_f = fmaf(wt, pw, isl_f);
                     }
                 }
-                if (MODE == MODE_FWD && want_lse && sd) {
-                    // online log-sum-exp, one exp per cell
-                    const float d = av - lm;
-                    const float ex = exp2f(-fabsf(d) * inv_t2);
-                    if (d > 0.f) {
-                        ls = ls * (double)ex + (double)mult;
-                        lm = av;
-                    } else {
-                        ls += (double)(mult * ex);
-                    }
+                if (MODE == MODE_FWD) {
+                    avs[q] = sd ? av : -INFINITY;
+                    mloc = fmaxf(mloc, avs[q]);
                 }
                 if constexpr (NEEDS_INV) {
                     float c = 0.f;
@@ -299,18 +343,18 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                                 g = a.grad_mag[row_p + k];
                                 if (tau > 0) g += a.grad_mag[row_n + kn];
                             }
-                            const float ia = 1.0f / av;
+                            const float ia = __builtin_amdgcn_rcpf(av);
                             c = 0.5f * g * invE2 * ia;
-                            dle -= (double)(g * pw * invE * ia);
+                            dle_f = fmaf(-g * pw * invE, ia, dle_f);
                         }
                     } else if (MODE == MODE_BWD_LOSS) {
                         if (sd) {
                             c = compl_isl ? 0.f : a.w_isl * wt * invE2;
                             if (a.w_psl != 0.f) {
                                 const float qq = exp2f((av - glob_m) * inv_t2) * glob_inv_s;
-                                const float ia = 1.0f / av;
+                                const float ia = __builtin_amdgcn_rcpf(av);
                                 c = fmaf(a.w_psl * qq * 0.5f * invE2, ia, c);
-                                dle -= (double)(mult * a.w_psl * qq * pw * invE * ia);
+                                dle_f = fmaf(-a.w_psl * qq * pw * invE, ia, dle_f);
                             }
                             c *= mult;
                         } else if (compl_isl && active) {
@@ -325,6 +369,15 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     }
                     v[q] = cscale(v[q], c);
                 }
+            }
+            isl += (double)(mult * isl_f);
+            dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f);
+            if (MODE == MODE_FWD && want_lse && mloc > -INFINITY) {
+                // this iteration's sidelobe cells, two per bin for tau > 0
+                float sl = 0.f;
+#pragma unroll
+                for (int q = 0; q < P; ++q) sl += exp2f((avs[q] - mloc) * inv_t2);
+                lse_merge(lm, ls, mloc, (double)(mult * sl), inv_t2);
             }
 
             if constexpr (SPLIT) {
@@ -374,11 +427,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             }
 
             if constexpr (NEEDS_INV) {
-                fft_group<MH, P, +1>(v, buf, l, tw, tw_mh, sync);
+                fft_group<MH, P, +1>(v, buf, l, twl, tw_mh, sync);
                 // v[q] = IDFT_{MH}(H_h)[l + qL]; the odd half gets w_M^{-m}
                 if (h) {
 #pragma unroll
-                    for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], tw[(l + q * L) << tshift]);
+                    for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl[(l + q * L) << twsh]);
                 }
                 if constexpr (SPLIT) {
 #pragma unroll
@@ -490,52 +543,51 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 // size and the occupancy target; each kernel instance covers one transform
 // size MH = M/2 = 2^LG.  Gradient accumulators per thread: NACC = MH / WGS
 // (N <= M/2 = MH), at least one.
-template <int P_, int SPLIT_, int WGS_, int WAVES_, int LO_, int HI_, int S_LDS_>
+template <int P_, int SPLIT_, int WGS_, int WAVES_, int LO_, int HI_, int S_LDS_, int TW_LDS_>
 struct Variant {
     static constexpr int P = P_, SPLIT = SPLIT_, WGS = WGS_, WAVES = WAVES_, LO = LO_, HI = HI_, S_LDS = S_LDS_;
+    static constexpr int TW_LDS = TW_LDS_;  // twiddle table copied to LDS
     static constexpr int nacc(int lg) { return (1 << lg) / WGS > 1 ? (1 << lg) / WGS : 1; }
     static constexpr bool fits(int lg) {
         return lg >= LO && lg <= HI && (1 << lg) >= P &&
                (SPLIT ? 2 * ((1 << lg) / P) <= WGS : ((1 << lg) / P) <= WGS);
     }
-    // dynamic LDS for the transform buffers of one instance
-    static constexpr int fft_lds_bytes(int lg) {
-        return (WGS / ((1 << lg) / P)) * ((1 << lg) + ((1 << lg) >> 5)) * 8;
-    }
+    // dynamic LDS of one instance: transform buffers, then the twiddle table
+    // w_M^i for i < M = 2^(lg+1)
+    static constexpr int buf_lds_bytes(int lg) { return (WGS / ((1 << lg) / P)) * ((1 << lg) + ((1 << lg) >> 5)) * 8; }
+    static constexpr int fft_lds_bytes(int lg) { return buf_lds_bytes(lg) + (TW_LDS ? (2 << lg) * 8 : 0); }
 };
 
-//                        P  split WGS waves LG range  s in LDS
-using V0 = Variant<16, 1, 256, 2, 6, 11, 1>;  // M 128..4096
-using V1 = Variant<16, 1, 512, 2, 12, 12, 1>; // M 8192
-using V2 = Variant<32, 0, 512, 2, 13, 14, 0>; // M 16384..32768, halves in turn
-using V3 = Variant<8, 1, 256, 2, 6, 10, 1>;   // more lanes per lag, M <= 2048
-using V4 = Variant<32, 1, 256, 1, 8, 11, 1>;  // fewer passes, M 512..4096
+//                 P  split WGS waves LG range  s, twiddles in LDS
+using V0 = Variant<16, 1, 256, 2, 6, 11, 1, 1>;  // M 128..4096
+using V1 = Variant<16, 1, 512, 2, 12, 12, 1, 0>; // M 8192
+using V2 = Variant<32, 0, 512, 2, 13, 14, 0, 0>; // M 16384..32768, halves in turn
+using V3 = Variant<8, 1, 256, 2, 6, 10, 1, 1>;   // more lanes per lag, M <= 2048
+using V4 = Variant<32, 1, 256, 1, 8, 11, 1, 1>;  // fewer passes, M 512..4096
 
+// Persistent kernel over one size class: work group g runs items g, g + grid,
+// g + 2 grid, ... of the class's list, which the planner sorted longest first
+// (a static, deterministic assignment).
 template <int MODE, typename V, int LG>
 __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     extern __shared__ float2 dyn[];
     __shared__ double scratch[64];
-    __shared__ int s_item;
+    constexpr int MH = 1 << LG;
     float2* lds = dyn;
     float2* s_lds = V::S_LDS ? dyn + V::fft_lds_bytes(LG) / 8 : nullptr;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.ctrl[0], 1u);
-        __syncthreads();
-        const int item = s_item;
-        __syncthreads();
-        if (item >= a.n_segs) break;
-        const SegDesc sg = a.segs[a.order[item]];
-        process_segment<MODE, (1 << LG), V::P, V::SPLIT, V::WGS, V::nacc(LG)>(a, sg, lds, s_lds, V::S_LDS != 0,
-                                                                             scratch);
-    }
-    // the last work group out resets the queue for the next launch
-    if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned done = atomicAdd(&a.ctrl[1], 1u);
-        if (done == gridDim.x - 1) {
-            atomicExch(&a.ctrl[0], 0u);
-            atomicExch(&a.ctrl[1], 0u);
-        }
+    float2* tw_lds = V::TW_LDS ? dyn + V::buf_lds_bytes(LG) / 8 : nullptr;
+    const float2* twl = V::TW_LDS ? tw_lds : a.tw;
+    const int twsh_global = a.log2_mmax - (LG + 1);
+    const int twsh = V::TW_LDS ? 0 : twsh_global;
+    WaveState st;
+    st.wave = -1;
+    for (int item = blockIdx.x; item < a.n_segs; item += gridDim.x) {
+        const SegDesc sg = a.segs[item];
+        if (sg.wave != st.wave)
+            stage_wave<MODE, V::WGS, MH>(a, sg.wave, s_lds, V::S_LDS != 0, scratch, st,
+                                         st.wave < 0 ? tw_lds : nullptr, twsh_global);
+        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG)>(a, sg, lds, twl, twsh, s_lds, V::S_LDS != 0,
+                                                                      scratch, st);
     }
 }
 

@@ -1,0 +1,142 @@
+"""Uneven batches in one plan (one persistent launch per Doppler size class),
+the optimiser step and its HIP-graph capture (GPU only).
+
+The batch is the uneven workload: 512 random-phase codes, N log-uniform in
+[64, 4096] (seed 0), M = next power of two >= 2N, full lag grid each, ISL.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2506_22935_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+EPS = 1e-12
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def af():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_22935_amd import af as afmod
+    return afmod
+
+
+@pytest.fixture(scope="module")
+def batch(af):
+    ns, ms, phases = W.uneven_batch(512, seed=0)
+    codes = [W.unimodular(p) for p in phases]
+    plan = af.Plan(ns.tolist(), ms.tolist(), eps=EPS)
+    s = torch.from_numpy(np.concatenate(codes)).cuda()
+    return dict(ns=ns, ms=ms, phases=phases, codes=codes, plan=plan, s=s)
+
+
+def isl_grad_fft(s, m):
+    """Oracle ISL (uniform weights, mainlobe 1x1) and its gradient through
+    the FFT-step route: dISL/da = 2 W a turns magnitude_backward into the
+    ISL adjoint (W chi / E^2 per cell)."""
+    n = len(s)
+    T = n - 1
+    E = O.energy(s)
+    W_ = O.isl_weights(n, m, T, 1, 1)
+    rows = O.chi_rows_fft(s, m, range(-T, T + 1))
+    a = O.magnitude(rows, E, EPS)
+    isl = float(np.sum(W_ * O.power(rows, E)))
+    g = O.magnitude_backward_fft(s, m, T, 2.0 * W_ * a, EPS)
+    return isl, g
+
+
+def test_uneven_full_batch_sampled_parity(af, batch):
+    say("uneven full batch")
+    plan, s = batch["plan"], batch["s"]
+    terms, g, _ = plan.loss(s, w_isl=1.0, w_psl=0.0)
+    torch.cuda.synchronize()
+    terms = terms.cpu().numpy()
+    g = g.cpu().numpy().astype(np.complex128)
+    ns, ms = batch["ns"], batch["ms"]
+    # direct oracle on the shortest waveforms, FFT-step oracle on a long one
+    order = np.argsort(ns)
+    picks = list(order[:4]) + [order[len(order) // 2], order[-1]]
+    for b in picks:
+        n, m = int(ns[b]), int(ms[b])
+        sr = O.to_c64_exact(batch["codes"][b])
+        if n <= 300:
+            ref = O.loss_and_grad(sr, m, n - 1, O.LossParams(eps=EPS))
+            isl, gref = ref["isl"], ref["g"]
+        else:
+            isl, gref = isl_grad_fft(sr, m)
+        gb = g[plan.s_offsets[b]:plan.s_offsets[b] + n]
+        assert abs(terms[b, 1] - isl) <= 1e-4 * isl, (b, n, terms[b, 1], isl)
+        assert np.max(np.abs(gb - gref)) <= 1e-4 * np.max(np.abs(gref)), (b, n)
+    # every waveform: the normalised loss is scale and phase invariant, so
+    # sum conj(s) g = 0 (a property that holds at any size)
+    s_np = s.cpu().numpy().astype(np.complex128)
+    for b in range(len(ns)):
+        o, n = plan.s_offsets[b], int(ns[b])
+        sb, gb = s_np[o:o + n], g[o:o + n]
+        assert abs(np.vdot(sb, gb)) <= 1e-3 * np.linalg.norm(sb) * np.linalg.norm(gb), b
+
+
+def test_graph_replay_matches_eager(af):
+    say("graph replay")
+    ns, ms, phases = W.uneven_batch(48, seed=3)
+    plan = af.Plan(ns.tolist(), ms.tolist(), eps=EPS)
+    phi0 = torch.from_numpy(np.concatenate(phases).astype(np.float32)).cuda()
+    K = 5
+    # eager reference
+    st_e = af.PhaseState(phi0.clone())
+    terms_e = torch.empty(plan.batch, 4, device="cuda")
+    for _ in range(2 * K):
+        plan.optim_step(st_e, w_isl=1.0, lr=0.01, terms=terms_e)
+    torch.cuda.synchronize()
+    # captured: K steps per graph, replayed twice with eager work in between
+    st_g = af.PhaseState(phi0.clone())
+    terms_g = torch.empty(plan.batch, 4, device="cuda")
+    ws = plan.workspace
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(K):
+                plan.optim_step(st_g, w_isl=1.0, lr=0.01, terms=terms_g, ws=ws)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    _ = (st_g.phi * 2).sum().item()  # unrelated eager work between replays
+    g.replay()
+    torch.cuda.synchronize()
+    assert int(st_g.step.item()) == 2 * K
+    assert torch.equal(st_g.phi, st_e.phi)
+    assert torch.equal(st_g.s, st_e.s)
+    assert torch.equal(terms_g, terms_e)
+
+
+def test_adam_steps_decrease_isl(af):
+    say("adam decreases isl")
+    ns, ms, phases = W.uneven_batch(16, seed=4)
+    plan = af.Plan(ns.tolist(), ms.tolist(), eps=EPS)
+    st = af.PhaseState(torch.from_numpy(np.concatenate(phases).astype(np.float32)).cuda())
+    terms = torch.empty(plan.batch, 4, device="cuda")
+    plan.optim_step(st, w_isl=1.0, lr=0.01, terms=terms)
+    first = terms[:, 1].clone()
+    for _ in range(50):
+        plan.optim_step(st, w_isl=1.0, lr=0.01, terms=terms)
+    torch.cuda.synchronize()
+    assert bool((terms[:, 1] < first).all())
+    # the device loss terms agree with the oracle at the final phases
+    phi = st.phi.cpu().numpy().astype(np.float64)
+    b = int(np.argmin(ns))
+    o, n, m = plan.s_offsets[b], int(ns[b]), int(ms[b])
+    sr = O.to_c64_exact(np.exp(1j * phi[o:o + n]))
+    plan.loss(st.s, w_isl=1.0, out_terms=terms, grad=False)
+    torch.cuda.synchronize()
+    ref = O.loss_and_grad(sr, m, n - 1, O.LossParams(eps=EPS))
+    assert abs(terms[b, 1].item() - ref["isl"]) <= 1e-4 * ref["isl"]
