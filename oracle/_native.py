@@ -37,6 +37,9 @@ def lib():
         h.oracle_chi.restype = ctypes.c_int
         h.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         h.oracle_adjoint.restype = ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int)
+        h.oracle_chi_rows.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp]
+        h.oracle_chi_rows.restype = ctypes.c_int
         h.oracle_threads.argtypes = []
         h.oracle_threads.restype = ctypes.c_int
         _handle = h
@@ -60,6 +63,18 @@ def chi(s, m, max_lag):
     rc = lib().oracle_chi(n, m, max_lag, _ptr(s.view(np.float64)), _ptr(out.view(np.float64)))
     if rc != 0:
         raise ValueError("oracle_chi rejected n=%d m=%d max_lag=%d" % (n, m, max_lag))
+    return out
+
+
+def chi_rows(s, m, taus):
+    """Direct-sum chi rows for the given lags only."""
+    s = np.ascontiguousarray(np.asarray(s, dtype=np.complex128))
+    taus = np.ascontiguousarray(np.asarray(taus, dtype=np.int32))
+    out = np.empty((len(taus), m), dtype=np.complex128)
+    rc = lib().oracle_chi_rows(s.shape[0], m, len(taus), taus.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                               _ptr(s.view(np.float64)), _ptr(out.view(np.float64)))
+    if rc != 0:
+        raise ValueError("oracle_chi_rows rejected its arguments")
     return out
 
 

@@ -109,6 +109,47 @@ int oracle_chi(int n, int m, int max_lag, const double *s, double *chi)
     return 0;
 }
 
+/* chi rows for the lags taus[0..count) only (same sums as oracle_chi),
+ * parallel over Doppler bins; out is [count][M] interleaved. */
+int oracle_chi_rows(int n, int m, int count, const int *taus, const double *s, double *out)
+{
+    if (n < 1 || m < 1 || (m & (m - 1)) != 0 || count < 0 || !taus || !s || !out) return -1;
+    for (int i = 0; i < count; ++i)
+        if (taus[i] <= -n || taus[i] >= n) return -1;
+    double *w = twiddle_table(m);
+    if (!w) return -1;
+    const int64_t mask = m - 1;
+    double *r = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!r) { free(w); return -1; }
+    for (int i = 0; i < count; ++i) {
+        const int tau = taus[i];
+        const int lo = tau > 0 ? tau : 0;
+        const int hi = tau < 0 ? n + tau : n;
+        for (int t = lo; t < hi; ++t) {
+            double ar = s[2 * t], ai = s[2 * t + 1];
+            double br = s[2 * (t - tau)], bi = -s[2 * (t - tau) + 1];
+            r[2 * t] = ar * br - ai * bi;
+            r[2 * t + 1] = ar * bi + ai * br;
+        }
+        double *row = out + (size_t)i * (size_t)m * 2;
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < m; ++k) {
+            double re = 0.0, im = 0.0;
+            for (int t = lo; t < hi; ++t) {
+                int64_t idx = ((int64_t)k * (int64_t)t) & mask;
+                double wr = w[2 * idx], wi = w[2 * idx + 1];
+                re += r[2 * t] * wr - r[2 * t + 1] * wi;
+                im += r[2 * t] * wi + r[2 * t + 1] * wr;
+            }
+            row[2 * k] = re;
+            row[2 * k + 1] = im;
+        }
+    }
+    free(r);
+    free(w);
+    return 0;
+}
+
 int oracle_adjoint(int n, int m, int max_lag, const double *s, const double *G, double *g)
 {
     if (bad_args(n, m, max_lag) || !s || !G || !g) return -1;

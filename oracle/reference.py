@@ -22,7 +22,7 @@ from scipy.special import erf
 from . import _native
 
 __all__ = [
-    "to_c64_exact", "energy", "chi", "magnitude", "power",
+    "to_c64_exact", "energy", "chi", "chi_rows", "magnitude", "power",
     "centred_bins", "mainlobe_mask", "isl_weights", "LossParams", "loss_terms",
     "loss_and_grad", "loss_grad_from_chi", "magnitude_backward", "grad_from_upstream", "phase_grad",
     "adam_step", "bf16_round", "gelu", "gelu_grad", "mlp_forward",
@@ -54,6 +54,11 @@ def chi(s, m, max_lag=None):
     s = np.asarray(s, dtype=np.complex128)
     T = s.shape[0] - 1 if max_lag is None or max_lag < 0 else int(max_lag)
     return _native.chi(s, int(m), T)
+
+
+def chi_rows(s, m, taus):
+    """Rows of chi for selected lags, by the same direct sums (C core)."""
+    return _native.chi_rows(np.asarray(s, dtype=np.complex128), int(m), taus)
 
 
 def power(c, E):
@@ -306,7 +311,8 @@ def chi_rows_fft(s, m, taus):
 def magnitude_backward_fft(s, m, max_lag, grad_mag, eps, rows_per_block=64):
     """magnitude_backward with FFT steps, streamed over lag rows: per row
     chi = FFT(r), G = g_a chi / (2 E^2 a), Q = M * IFFT(G), then the two
-    adjoint terms of the lag product and the energy term."""
+    adjoint terms of the lag product and the energy term.  grad_mag is an
+    array [2T+1, M] or a callable (row index, a row) -> that row's dL/da."""
     s = np.asarray(s, dtype=np.complex128)
     n = s.shape[0]
     T = int(max_lag)
@@ -321,7 +327,7 @@ def magnitude_backward_fft(s, m, max_lag, grad_mag, eps, rows_per_block=64):
             c = np.fft.fft(r)
             p = power(c, E)
             a = np.sqrt(p + eps)
-            ga = np.asarray(grad_mag[i], dtype=np.float64)
+            ga = np.asarray(grad_mag(i, a) if callable(grad_mag) else grad_mag[i], dtype=np.float64)
             G = ga * c / (2.0 * E * E * a)
             dLdE -= float(np.sum(ga * p / (E * a)))
             Q = np.fft.ifft(G) * m

@@ -225,9 +225,43 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const bool mag_out = HAS_MAG_OUT && a.mag != nullptr;
     const bool chi_out = MODE == MODE_FWD && a.chi != nullptr;
 
-    float2 acc[NEEDS_INV ? NACC : 1];
+    // gradient accumulators: registers, or (halves in turn, long waveforms)
+    // the segment's own slab in global memory, which only this group touches
+    constexpr bool GACC = !SPLIT;
+    float2 acc[(NEEDS_INV && !GACC) ? NACC : 1];
 #pragma unroll
-    for (int i = 0; i < (NEEDS_INV ? NACC : 1); ++i) acc[i] = make_float2(0.f, 0.f);
+    for (int i = 0; i < ((NEEDS_INV && !GACC) ? NACC : 1); ++i) acc[i] = make_float2(0.f, 0.f);
+    float2* const slab = NEEDS_INV ? a.slabs + w.slab_off + (int64_t)(sg.rec - w.seg_begin) * N : nullptr;
+    if (NEEDS_INV && GACC) {
+        for (int p = tid; p < N; p += WGS) slab[p] = make_float2(0.f, 0.f);
+    }
+    // lag-product adjoint of lag tj from Q' in LDS (qa, plus qa + BUF when the
+    // two halves sit in two buffers)
+    auto gather = [&](const float2* qa, bool two, int tj) {
+        const int Sj = N - tj;
+#pragma unroll
+        for (int i = 0; i < NACC; ++i) {
+            const int p = tid + WGS * i;
+            if (p < N) {
+                float2 sum = GACC ? slab[p] : acc[GACC ? 0 : i];
+                if (p < Sj) {
+                    float2 Q = qa[lds_index(p)];
+                    if (two) Q = cadd(Q, qa[BUF + lds_index(p)]);
+                    sum = cadd(sum, cmul(cconj(Q), sv[p + tj]));
+                }
+                const int m = p - tj;
+                if (m >= 0) {
+                    float2 Q = qa[lds_index(m)];
+                    if (two) Q = cadd(Q, qa[BUF + lds_index(m)]);
+                    sum = cadd(sum, cmul(Q, sv[m]));
+                }
+                if (GACC)
+                    slab[p] = sum;
+                else
+                    acc[GACC ? 0 : i] = sum;
+            }
+        }
+    };
     const bool compl_isl = a.band_w == nullptr && w.full_window != 0;
     double isl = 0.0, ls = 0.0, dle = 0.0;
     float lm = -INFINITY;
@@ -256,9 +290,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                               : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
-        float2 q0[(NEEDS_INV && !SPLIT) ? P : 1];
 
-#pragma unroll
+#pragma unroll 1
         for (int hh = 0; hh < (SPLIT ? 1 : 2); ++hh) {
             const int h = SPLIT ? hsel : hh;
             float2 v[P];
@@ -276,6 +309,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         if (h) x = cmul(x, twl[m << twsh]);
                     }
                     v[r] = x;
+                    // bound how many loads the scheduler keeps in flight
+                    if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
                 }
                 fft_group<MH, P, -1>(v, buf, l, twl, tw_mh, sync);
             }
@@ -433,48 +468,26 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 #pragma unroll
                     for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl[(l + q * L) << twsh]);
                 }
-                if constexpr (SPLIT) {
 #pragma unroll
-                    for (int q = 0; q < P; ++q) buf[lds_index(l + q * L)] = v[q];
-                } else {
-                    if (hh == 0) {
-#pragma unroll
-                        for (int q = 0; q < P; ++q) q0[q] = v[q];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < P; ++q) buf[lds_index(l + q * L)] = cadd(q0[q], v[q]);
+                for (int q = 0; q < P; ++q) buf[lds_index(l + q * L)] = v[q];
+                if constexpr (!SPLIT) {
+                    // halves in turn: this half's share of every lag's adjoint
+                    __syncthreads();
+                    for (int j = 0; j < LPI; ++j) {
+                        if (t0 + j >= sg.tau_end) break;
+                        gather(lds + j * BUF, false, t0 + j);
                     }
+                    __syncthreads();
                 }
             }
         }
 
-        if constexpr (NEEDS_INV) {
+        if constexpr (NEEDS_INV && SPLIT) {
             __syncthreads();
             // lag-product adjoint for every lag of this iteration
             for (int j = 0; j < LPI; ++j) {
-                const int tj = t0 + j;
-                if (tj >= sg.tau_end) break;
-                const int Sj = N - tj;
-                const float2* qa = lds + (SPLIT ? 2 * j : j) * BUF;
-#pragma unroll
-                for (int i = 0; i < NACC; ++i) {
-                    const int p = tid + WGS * i;
-                    if (p < N) {
-                        float2 sum = acc[i];
-                        if (p < Sj) {
-                            float2 Q = qa[lds_index(p)];
-                            if (SPLIT) Q = cadd(Q, qa[BUF + lds_index(p)]);
-                            sum = cadd(sum, cmul(cconj(Q), sv[p + tj]));
-                        }
-                        const int m = p - tj;
-                        if (m >= 0) {
-                            float2 Q = qa[lds_index(m)];
-                            if (SPLIT) Q = cadd(Q, qa[BUF + lds_index(m)]);
-                            sum = cadd(sum, cmul(Q, sv[m]));
-                        }
-                        acc[i] = sum;
-                    }
-                }
+                if (t0 + j >= sg.tau_end) break;
+                gather(lds + 2 * j * BUF, true, t0 + j);
             }
         }
         __syncthreads();
@@ -528,11 +541,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 a.parts[sg.rec] = pr;
             }
         }
-        float2* slab = a.slabs + w.slab_off + (int64_t)(sg.rec - w.seg_begin) * N;
+        if (!GACC) {
 #pragma unroll
-        for (int i = 0; i < NACC; ++i) {
-            const int p = tid + WGS * i;
-            if (p < N) slab[p] = acc[i];
+            for (int i = 0; i < NACC; ++i) {
+                const int p = tid + WGS * i;
+                if (p < N) slab[p] = acc[GACC ? 0 : i];
+            }
         }
     }
     __syncthreads();
@@ -561,7 +575,7 @@ struct Variant {
 //                 P  split WGS waves LG range  s, twiddles in LDS
 using V0 = Variant<16, 1, 256, 2, 6, 11, 1, 1>;  // M 128..4096
 using V1 = Variant<16, 1, 512, 2, 12, 12, 1, 0>; // M 8192
-using V2 = Variant<32, 0, 512, 2, 13, 14, 0, 0>; // M 16384..32768, halves in turn
+using V2 = Variant<16, 0, 1024, 4, 13, 14, 0, 0>; // M 16384..32768, halves in turn
 using V3 = Variant<8, 1, 256, 2, 6, 10, 1, 1>;   // more lanes per lag, M <= 2048
 using V4 = Variant<32, 1, 256, 1, 8, 11, 1, 1>;  // fewer passes, M 512..4096
 

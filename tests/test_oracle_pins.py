@@ -435,3 +435,10 @@ def test_fft_backward_matches_direct_sum():
     ref = O.magnitude_backward(s, m, T, ga, eps)
     got = O.magnitude_backward_fft(s, m, T, ga, eps, rows_per_block=7)
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_chi_rows_is_the_direct_grid():
+    n, m, T = 29, 64, 28
+    s = rand_complex(n, 33)
+    taus = [-28, -3, 0, 5, 28]
+    assert np.array_equal(O.chi_rows(s, m, taus), O.chi(s, m, T)[[t + T for t in taus]])
