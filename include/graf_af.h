@@ -170,6 +170,43 @@ af_status af_optim_step(const af_plan* plan, float* phi, float* adam_m, float* a
                         const af_loss_params* loss, const af_adam_params* adam, float* terms, void* ws,
                         size_t ws_bytes, void* stream);
 
+/* ---- proposal network (paper Sec. 6.1, Fig. 1: design parameters ->
+ * network -> waveform -> ambiguity function -> loss) ----------------------
+ * Dense layers run as BF16 MFMA GEMMs with FP32 accumulation.  All arrays are
+ * device memory, row-major, contiguous; bf16 arrays hold IEEE bfloat16.
+ *
+ * af_gemm_bf16: C[m][n] = sum_k A~[m][k] B~[n][k] with
+ *   layout 0 (X W^T): A [m][k] bf16, B [n][k] bf16
+ *   layout 1 (dZ W):  A [m][k] bf16, B [k][n] bf16
+ *   layout 2 (dZ^T A): A [k][m] bf16, B [k][n] bf16
+ * and epilogue
+ *   0: out_f32 = C
+ *   1: out_f32 = C + bias[n]
+ *   2: out_f32 = Z = C + bias[n]; out_bf16 = GELU(Z)   (exact erf GELU)
+ *   3: out_f32 = dZ = C * GELU'(aux) ; out_bf16 = dZ     (aux = Z of the layer)
+ * m and n must be multiples of 64, k a multiple of 32 (AF_ERR_UNSUPPORTED
+ * otherwise); a and b 16-byte aligned. */
+af_status af_gemm_bf16(int32_t layout, int32_t epilogue, int32_t m, int32_t n, int32_t k, const void* a,
+                       const void* b, const float* bias, const float* aux, float* out_f32, void* out_bf16,
+                       void* stream);
+
+/* out[c] = sum over r of in[r][c] (float32, fixed summation order). */
+af_status af_colsum(int32_t rows, int32_t cols, const float* in, float* out, void* stream);
+
+/* One bias-corrected Adam step (step >= 1 is the 1-based step number) on
+ * count float32 parameters; param_bf16 (nullable) receives their bfloat16
+ * copy. */
+af_status af_adam_update(int64_t count, float* param, const float* grad, float* m, float* v, int32_t step,
+                         const af_adam_params* adam, void* param_bf16, void* stream);
+
+/* out[i] = bfloat16(in[i]), round to nearest even. */
+af_status af_to_bf16(int64_t count, const float* in, void* out, void* stream);
+
+/* out[i] = dL/dphi_i = 2 Im(conj(s_i) grad_s_i) for s = exp(j phi) (complex64
+ * s and grad_s = dL/d conj(s)); out_bf16 (nullable) gets its bfloat16 copy. */
+af_status af_phase_grad(int64_t count, const void* s, const void* grad_s, float* out, void* out_bf16,
+                        void* stream);
+
 const char* af_status_string(af_status status);
 int32_t af_version(void);
 
