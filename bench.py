@@ -242,6 +242,54 @@ def bench_large(args, torch):
     return out
 
 
+def bench_proposal(args, torch):
+    """Learned proposal vs plain optimiser: 4096 sidelobe-mask descriptors,
+    N=256, M=512, weighted ISL.  The network (64 -> 3x1024 GELU -> 256, BF16
+    MFMA) is trained through the AF loss first (reported separately), then
+    time-to-target is measured: the per-descriptor weighted ISL that plain Adam
+    (lr 0.01) reaches after 2000 steps from random phases, versus network
+    proposal + plain refinement (the refinement continues as the fallback)."""
+    from paper_2506_22935_amd import proposal as P
+    n, m, B = 256, 512, 4096
+    pr = P.Proposer(n, m, seed=args.seed)
+    _, train_ms = P.timed_ms(lambda: P.train(pr, n, m, batch=512, steps=args.train_steps, seed=args.seed + 1,
+                                             log=log))
+    te = P.DescriptorBatch(n, m, B, seed=args.seed + 2)
+    res = P.evaluate(pr, te, plain_steps=2000, refine_steps=50, fallback_steps=2000, seed=args.seed + 3, log=log)
+    # MLP kernels alone: one forward + backward at batch 4096 (MFMA roofline)
+    cells = B * (2 * n - 1) * m
+    x = te.d
+    up = torch.randn(B, n, device="cuda")
+    from paper_2506_22935_amd import mlp as MLPm
+    up16 = MLPm.to_bf16(up)
+
+    def mlp_step():
+        out, cache = pr.net.forward(x)
+        pr.net.backward(up, up16, cache)
+
+    for _ in range(3):
+        mlp_step()
+    mlp_ms = timed(mlp_step, 20, torch)
+    sizes = pr.net.sizes
+    gemm_flops = sum(2.0 * B * sizes[i] * sizes[i + 1] for i in range(len(sizes) - 1))
+    mlp_flops = 3.0 * gemm_flops - 2.0 * B * sizes[0] * sizes[1]  # forward, dW, dX (no dX for the input)
+    mlp_tf = mlp_flops / (mlp_ms * 1e-3) / 1e12
+    speedup = res["median_plain_ms"] / res["median_learned_ms"] if res["median_learned_ms"] > 0 else None
+    keep = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items()
+            if not isinstance(v, torch.Tensor)}
+    out = dict(value=speedup, unit="x (median time-to-target, plain / learned)", ms_per_step=res["step_ms"],
+               metric="time-to-target weighted ISL, learned vs plain",
+               config=dict(workload="proposal: 4096 descriptors, N=256, M=512, weighted ISL; plain Adam 2000 steps "
+                                    "vs network + refinement",
+                           train_steps=args.train_steps, train_ms=round(train_ms, 1), optimiser_step_ms=res["step_ms"],
+                           optimiser_cells_per_s=cells / (res["step_ms"] * 1e-3), evaluation=keep,
+                           mlp_fwd_bwd_ms=round(mlp_ms, 4)),
+               roofline=dict(bound="mfma", achieved=round(mlp_tf, 2), peak=2500.0, unit="TFLOP/s",
+                             frac=round(mlp_tf / 2500.0, 4), traffic=None,
+                             kernel="proposal network forward + backward (BF16 MFMA GEMMs), batch 4096"))
+    return out
+
+
 def bench_copy(args, torch):
     """Plain device copy of known size (counter calibration)."""
     nbytes = 1 << 30
@@ -254,7 +302,8 @@ def bench_copy(args, torch):
                 config=dict(workload="copy: 1 GiB device-to-device"), unit="GB/s")
 
 
-WORKLOADS = {"single": bench_single, "uneven": bench_uneven, "large": bench_large, "copy": bench_copy}
+WORKLOADS = {"single": bench_single, "uneven": bench_uneven, "large": bench_large, "proposal": bench_proposal,
+             "copy": bench_copy}
 
 
 def main():
@@ -267,6 +316,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: time the candidates)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=3000, help="proposal workload: network training steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path; "
@@ -278,7 +328,8 @@ def main():
         sys.exit(2)
     log("workload", args.workload, "steps", args.steps, "warmup", args.warmup)
     res = WORKLOADS[args.workload](args, torch)
-    line = dict(metric="AF fwd+bwd cells/s", value=res["value"], unit=res.get("unit", "cells/s"), n_gpus=1,
+    line = dict(metric=res.get("metric", "AF fwd+bwd cells/s"), value=res["value"], unit=res.get("unit", "cells/s"),
+                n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=res["ms_per_step"], higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f32", data="synthetic", config=res["config"])
     for k in ("roofline", "cpu_baseline"):
