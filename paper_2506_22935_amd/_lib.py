@@ -7,7 +7,9 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libgraf_af.so")
+# GRAF_AF_LIB points at another build of the same library (e.g. an
+# instrumented one); the default is the in-tree build.
+LIB_PATH = os.environ.get("GRAF_AF_LIB") or os.path.join(_PKG, "libgraf_af.so")
 
 AF_OK = 0
 STATUS = {0: "AF_OK", -1: "AF_ERR_INVALID_ARG", -2: "AF_ERR_UNSUPPORTED", -3: "AF_ERR_BUDGET",

@@ -56,10 +56,12 @@ struct af_plan {
         int grid[4] = {0, 0, 0, 0};
         int dyn_lds = 0;
         int max_n = 0;
+        int single_wave = -1;  // the waveform index when the class has one
         double cost = 0.0;
     };
     std::vector<Class> classes;
     std::vector<int> forced;  // per class: variant forced by the autotuner (-1: default)
+    std::vector<WaveDesc> wave_desc;  // host copy of the device descriptors
     int opt_variant = -1;
     bool stores = false;
     int n_segs = 0, n_chunks = 0, sg_log = 2;
@@ -279,6 +281,16 @@ af_status build_schedule(af_plan* p) {
         hipMemcpy(p->d_chunks, rblocks.data(), rblocks.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
         return hip_fail();
 
+    for (int c = 0; c < C; ++c) {
+        int count = 0, last = -1;
+        for (int b = 0; b < B; ++b)
+            if (cls_of_wave[b] == c) {
+                ++count;
+                last = b;
+            }
+        cls[c].single_wave = count == 1 ? last : -1;
+    }
+    p->wave_desc = wd;
     p->classes = cls;
     p->stores = stores;
     p->n_segs = (int)segs.size();
@@ -368,6 +380,11 @@ af_status launch(const af_plan* p, int mode, const AfArgs& a0, hipStream_t st, i
         AfArgs a = a0;
         a.segs = p->d_segs + k.begin;
         a.n_segs = k.count;
+        a.single = k.single_wave >= 0 ? 1 : 0;
+        if (a.single) {
+            a.w0 = p->wave_desc[k.single_wave];
+            a.w0_index = k.single_wave;
+        }
         hipError_t e = graf::launch_af(mode, k.variant, k.lg, a, k.grid[mode], k.dyn_lds, st);
         if (e != hipSuccess) return AF_ERR_HIP;
     }

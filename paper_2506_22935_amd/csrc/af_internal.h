@@ -45,6 +45,9 @@ enum Mode : int {
 };
 
 struct AfArgs {
+    WaveDesc w0;          // the waveform of a one-waveform class (single != 0)
+    int single;
+    int w0_index;
     const float2* s;
     const WaveDesc* waves;
     const SegDesc* segs;  // this launch's items in execution order

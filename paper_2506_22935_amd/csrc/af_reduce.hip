@@ -77,11 +77,19 @@ __device__ __forceinline__ float2 slab_sum(const ReduceArgs& a, const WaveDesc& 
     const int pb_log = 8 - a.sg_log;
     const int sub = threadIdx.x >> pb_log;
     const int SG = 1 << a.sg_log;
+    constexpr int U = 8;  // slab loads in flight per thread
     float2 sum = make_float2(0.f, 0.f);
     if (!a.skip_slabs && p < w.n) {
         const float2* sl = a.slabs + w.slab_off + p;
-#pragma unroll 8
-        for (int j = sub; j < w.seg_count; j += SG) sum = cadd(sum, sl[(int64_t)j * w.n]);
+        int j = sub;
+        for (; j + (U - 1) * SG < w.seg_count; j += U * SG) {
+            float2 x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = sl[(int64_t)(j + u * SG) * w.n];
+#pragma unroll
+            for (int u = 0; u < U; ++u) sum = cadd(sum, x[u]);
+        }
+        for (; j < w.seg_count; j += SG) sum = cadd(sum, sl[(int64_t)j * w.n]);
     }
     sh2[threadIdx.x] = sum;
     __syncthreads();

@@ -108,28 +108,45 @@ struct WaveState {
 
 // Stage waveform `wave` (N <= MH samples) into LDS and compute its energy;
 // with twl != nullptr also copy this size's twiddles w_M^i (i < 2 MH) from the
-// global table, all loads issued before any LDS store so that one memory
-// round trip covers both.
+// global table; for the loss backward also merge the forward pass records
+// into the soft-PSL normaliser.  Every global load is issued before the first
+// barrier, so one memory round trip covers all of them.
 template <int MODE, int WGS, int MH>
-__device__ void stage_wave(const AfArgs& a, int wave, float2* s_lds, bool s_in_lds, double* scratch, WaveState& st,
-                           float2* twl, int twsh) {
+__device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2* s_lds, bool s_in_lds,
+                           double* scratch, WaveState& st, float2* twl, int twsh) {
     constexpr int NPT = (MH + WGS - 1) / WGS;
     constexpr int TPT = (2 * MH + WGS - 1) / WGS;
-    const WaveDesc w = a.waves[wave];
+    constexpr int PPT = 4;  // records per thread merged from registers
+    constexpr bool MERGE = MODE == MODE_BWD_LOSS;
     const int tid = threadIdx.x;
-    const float2* __restrict__ sg_s = a.s + w.s_off;
-    float2 sx[NPT];
     float2 tx[TPT];
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int p = tid + i * WGS;
-        sx[i] = p < w.n ? sg_s[p] : make_float2(0.f, 0.f);
-    }
     if (twl) {
 #pragma unroll
         for (int i = 0; i < TPT; ++i) {
             const int j = tid + i * WGS;
             tx[i] = j < 2 * MH ? a.tw[j << twsh] : make_float2(0.f, 0.f);
+        }
+    }
+    const float2* __restrict__ sg_s = a.s + w.s_off;
+    float2 sx[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int p = tid + i * WGS;
+        sx[i] = p < w.n ? sg_s[p] : make_float2(0.f, 0.f);
+    }
+    const bool merge = MERGE && a.w_psl != 0.f;
+    float pm[MERGE ? PPT : 1];
+    double ps[MERGE ? PPT : 1];
+    if (merge) {
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const int j = tid + i * WGS;
+            pm[i] = -INFINITY;
+            ps[i] = 0.0;
+            if (j < w.seg_count) {
+                pm[i] = a.parts[w.seg_begin + j].lse_m;
+                ps[i] = a.parts[w.seg_begin + j].lse_s;
+            }
         }
     }
     __syncthreads();  // the previous segment is done with s_lds and scratch
@@ -148,30 +165,38 @@ __device__ void stage_wave(const AfArgs& a, int wave, float2* s_lds, bool s_in_l
         }
     }
     st.wave = wave;
-    st.E = block_sum<WGS, float>(e, scratch);
     st.glob_m = 0.f;
     st.glob_inv_s = 0.f;
-    if (MODE == MODE_BWD_LOSS && a.w_psl != 0.f) {
-        // global soft-PSL normaliser of this waveform: the work group merges
-        // the forward pass records in a fixed order (thread-strided, then
-        // wavefront butterflies, then waves in order)
+    if (!merge) {
+        st.E = block_sum<WGS, float>(e, scratch);
+    } else {
+        // energy and the global soft-PSL normaliser in one fixed-order
+        // reduction: thread-strided records, wavefront butterflies, waves in order
         const float inv_t2 = kLog2e / a.temp;
         float m = -INFINITY;
         double s = 0.0;
-        for (int j = tid; j < w.seg_count; j += WGS) {
+#pragma unroll
+        for (int i = 0; i < (MERGE ? PPT : 1); ++i) lse_merge(m, s, pm[i], ps[i], inv_t2);
+        for (int j = tid + PPT * WGS; j < w.seg_count; j += WGS) {
             const Part pr = a.parts[w.seg_begin + j];
             lse_merge(m, s, pr.lse_m, pr.lse_s, inv_t2);
         }
         wave_lse(m, s, inv_t2);
-        __syncthreads();
+        e = wave_sum(e);
         if ((tid & 63) == 0) {
-            scratch[2 * (tid >> 6)] = (double)m;
-            scratch[2 * (tid >> 6) + 1] = s;
+            scratch[3 * (tid >> 6)] = (double)m;
+            scratch[3 * (tid >> 6) + 1] = s;
+            scratch[3 * (tid >> 6) + 2] = (double)e;
         }
         __syncthreads();
         m = -INFINITY;
         s = 0.0;
-        for (int i = 0; i < WGS / 64; ++i) lse_merge(m, s, (float)scratch[2 * i], scratch[2 * i + 1], inv_t2);
+        float et = 0.f;
+        for (int i = 0; i < WGS / 64; ++i) {
+            lse_merge(m, s, (float)scratch[3 * i], scratch[3 * i + 1], inv_t2);
+            et += (float)scratch[3 * i + 2];
+        }
+        st.E = et;
         st.glob_m = m;
         st.glob_inv_s = (float)(1.0 / s);
     }
@@ -202,7 +227,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     float2* buf = lds + grp * BUF;
     float* rowbuf = reinterpret_cast<float*>(lds + (SPLIT ? 2 * lam : lam) * BUF);
 
-    const WaveDesc w = a.waves[sg.wave];
+    const WaveDesc w = a.single ? a.w0 : a.waves[sg.wave];
     const int N = w.n, T = w.T;
     constexpr int M = M_;
     const int tshift = a.log2_mmax - w.log2m;  // w_M^i = tw[i << tshift]
@@ -494,53 +519,36 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
 
     // ------------------------------------------- segment results -------
-    const double isl_t = block_sum<WGS, double>(isl, scratch);
-    if (MODE == MODE_FWD) {
-        wave_lse(lm, ls, inv_t2);
-        __syncthreads();
-        if ((tid & 63) == 0) {
-            scratch[2 * (tid >> 6)] = (double)lm;
-            scratch[2 * (tid >> 6) + 1] = ls;
+    // one fixed-order reduction of (ISL, soft-PSL pair, dL/dE) over the group
+    if (MODE == MODE_FWD) wave_lse(lm, ls, inv_t2);
+    isl = wave_sum(isl);
+    dle = wave_sum(dle);
+    __syncthreads();
+    if ((tid & 63) == 0) {
+        scratch[4 * (tid >> 6) + 0] = isl;
+        scratch[4 * (tid >> 6) + 1] = (double)lm;
+        scratch[4 * (tid >> 6) + 2] = ls;
+        scratch[4 * (tid >> 6) + 3] = dle;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        Part pr;
+        pr.isl = 0.0;
+        pr.lse_s = 0.0;
+        pr.dle = 0.0;
+        pr.lse_m = -INFINITY;
+        pr.pad = 0.f;
+        for (int i = 0; i < WGS / 64; ++i) {
+            pr.isl += scratch[4 * i + 0];
+            if (MODE == MODE_FWD) lse_merge(pr.lse_m, pr.lse_s, (float)scratch[4 * i + 1], scratch[4 * i + 2], inv_t2);
+            pr.dle += scratch[4 * i + 3];
         }
-        __syncthreads();
-        if (tid == 0) {
-            float m = -INFINITY;
-            double s = 0.0;
-            for (int i = 0; i < WGS / 64; ++i) lse_merge(m, s, (float)scratch[2 * i], scratch[2 * i + 1], inv_t2);
-            Part pr;
-            pr.isl = isl_t;
-            pr.lse_s = s;
-            pr.dle = 0.0;
-            pr.lse_m = m;
-            pr.pad = 0.f;
+        if (MODE == MODE_BWD_LOSS)
+            a.parts[sg.rec].dle = pr.dle;
+        else
             a.parts[sg.rec] = pr;
-        }
-    } else if (MODE == MODE_FUSED_ISL) {
-        if (tid == 0) {
-            Part pr;
-            pr.isl = isl_t;
-            pr.lse_s = 0.0;
-            pr.dle = 0.0;
-            pr.lse_m = -INFINITY;
-            pr.pad = 0.f;
-            a.parts[sg.rec] = pr;
-        }
     }
     if constexpr (NEEDS_INV) {
-        const double dle_t = block_sum<WGS, double>(dle, scratch);
-        if (tid == 0) {
-            if (MODE == MODE_BWD_LOSS) {
-                a.parts[sg.rec].dle = dle_t;
-            } else if (MODE == MODE_BWD_MAG) {
-                Part pr;
-                pr.isl = 0.0;
-                pr.lse_s = 0.0;
-                pr.dle = dle_t;
-                pr.lse_m = -INFINITY;
-                pr.pad = 0.f;
-                a.parts[sg.rec] = pr;
-            }
-        }
         if (!GACC) {
 #pragma unroll
             for (int i = 0; i < NACC; ++i) {
@@ -595,11 +603,19 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     const int twsh = V::TW_LDS ? 0 : twsh_global;
     WaveState st;
     st.wave = -1;
+    if (a.single && blockIdx.x < a.n_segs) {
+        // one waveform: stage it before the first item so that the item, the
+        // samples and the twiddles travel in the same memory round trip
+        stage_wave<MODE, V::WGS, MH>(a, a.w0, a.w0_index, s_lds, V::S_LDS != 0, scratch, st, tw_lds, twsh_global);
+    }
     for (int item = blockIdx.x; item < a.n_segs; item += gridDim.x) {
         const SegDesc sg = a.segs[item];
-        if (sg.wave != st.wave)
-            stage_wave<MODE, V::WGS, MH>(a, sg.wave, s_lds, V::S_LDS != 0, scratch, st,
+        if (sg.wave != st.wave) {
+            // a class with one waveform carries its descriptor in the arguments
+            const WaveDesc w = a.single ? a.w0 : a.waves[sg.wave];
+            stage_wave<MODE, V::WGS, MH>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st,
                                          st.wave < 0 ? tw_lds : nullptr, twsh_global);
+        }
         process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG)>(a, sg, lds, twl, twsh, s_lds, V::S_LDS != 0,
                                                                       scratch, st);
     }
