@@ -101,7 +101,7 @@ void free_tables(af_plan* p) {
 bool variant_fits(int v, int lg, int max_n) {
     const VariantInfo vi = graf::variant_info(v, lg);
     if (!vi.fits) return false;
-    const int lds = vi.fft_lds + (vi.s_lds ? 8 * max_n : 0);
+    const int lds = vi.fft_lds + (vi.s_lds ? 8 * (2 << lg) : 0);  // samples zero-padded to M
     return lds <= kMaxLds;
 }
 
@@ -151,7 +151,7 @@ af_status build_schedule(af_plan* p) {
         if (v < 0 || !variant_fits(v, k.lg, k.max_n)) return AF_ERR_UNSUPPORTED;
         k.variant = v;
         const VariantInfo vi = graf::variant_info(v, k.lg);
-        k.dyn_lds = vi.fft_lds + (vi.s_lds ? 8 * k.max_n : 0);
+        k.dyn_lds = vi.fft_lds + (vi.s_lds ? 8 * (2 << k.lg) : 0);  // samples zero-padded to M
         for (int mode = 0; mode < 4; ++mode) {
             const int r = graf::variant_max_resident(mode, v, k.lg, k.dyn_lds);
             if (r <= 0) return AF_ERR_UNSUPPORTED;

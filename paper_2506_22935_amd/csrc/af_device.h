@@ -148,6 +148,10 @@ struct Dft<4, SIGN> {
 // ----------------------------------------------------------- LDS layout --
 // One padding slot per 32 complex entries spreads stride-R stores over banks.
 __device__ __forceinline__ int lds_index(int i) { return i + (i >> 5); }
+// lds_index(b + c) = lds_index(b) + lds_index(c) whenever (b mod 32) +
+// (c mod 32) < 32: accesses at compile-time offsets c from one per-lane base
+// then need one address register and immediate offsets.
+constexpr int lds_off(int c) { return c + (c >> 5); }
 template <int N>
 struct LdsSize {
     static constexpr int value = N + (N >> 5);
@@ -195,9 +199,30 @@ __device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, con
         }
         Dft<R, SIGN>::run(u);
         if constexpr (!LAST) {
-            const int base = (j / NS) * NS * R + k;
+            // base mod 32 + (r NS) mod 32 < 32 holds when NS = 1 (base is a
+            // multiple of R), when NS R >= 32 (base mod 32 = k < NS and r NS
+            // mod 32 <= 32 - NS) and when NS >= 32
+            static_assert(NS == 1 || NS * R >= 32, "write offsets would carry");
+            const int bi = lds_index((j / NS) * NS * R + k);
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lds_index(base + r * NS)] = u[r];
+            for (int r = 0; r < R; ++r) lds[bi + lds_off(r * NS)] = u[r];
+        }
+    }
+}
+
+// Gather the next pass's inputs: slot [b*R + r] = y[l + L*b + r*MH/R].
+template <int MH, int P, int R>
+__device__ __forceinline__ void read_group(float2* v, const float2* lds, int l) {
+    constexpr int L = MH / P;
+#pragma unroll
+    for (int b = 0; b < P / R; ++b) {
+        if constexpr ((MH / R) % 32 == 0) {
+            const int bi = lds_index(l + L * b);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b * R + r] = lds[bi + lds_off(r * (MH / R))];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b * R + r] = lds[lds_index(l + L * b + r * (MH / R))];
         }
     }
 }
@@ -224,30 +249,21 @@ __device__ __forceinline__ void fft_group(float2* v, float2* lds, int l, const f
         sync();
         constexpr int NS1 = P;
         constexpr int R1 = NPASS == 2 ? RL : P;
-#pragma unroll
-        for (int b = 0; b < P / R1; ++b)
-#pragma unroll
-            for (int r = 0; r < R1; ++r) v[b * R1 + r] = lds[lds_index(l + L * b + r * (MH / R1))];
+        read_group<MH, P, R1>(v, lds, l);
         sync();
         stockham_pass<MH, P, R1, NS1, SIGN, NPASS == 2>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS1 * R1));
         if constexpr (NPASS >= 3) {
             sync();
             constexpr int NS2 = P * P;
             constexpr int R2 = NPASS == 3 ? RL : P;
-#pragma unroll
-            for (int b = 0; b < P / R2; ++b)
-#pragma unroll
-                for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[lds_index(l + L * b + r * (MH / R2))];
+        read_group<MH, P, R2>(v, lds, l);
             sync();
             stockham_pass<MH, P, R2, NS2, SIGN, NPASS == 3>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS2 * R2));
             if constexpr (NPASS >= 4) {
                 sync();
                 constexpr int NS3 = P * P * P;
                 constexpr int R3 = RL;
-#pragma unroll
-                for (int b = 0; b < P / R3; ++b)
-#pragma unroll
-                    for (int r = 0; r < R3; ++r) v[b * R3 + r] = lds[lds_index(l + L * b + r * (MH / R3))];
+                read_group<MH, P, R3>(v, lds, l);
                 sync();
                 stockham_pass<MH, P, R3, NS3, SIGN, true>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS3 * R3));
             }

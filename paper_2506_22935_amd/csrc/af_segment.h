@@ -31,9 +31,23 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace graf {
 
 constexpr float kLog2e = 1.4426950408889634f;
+
+// Soft-PSL sums use the shift a_ref = sqrt(1 + eps), an upper bound of every
+// a (|chi| <= E by Cauchy-Schwarz, so p <= 1).  When a_ref log2(e) / T < 100
+// no term exp((a - a_ref)/T), a >= 0, leaves the normal float range, and the
+// fixed shift replaces the running maximum: plain sums, no rescaling.  Smaller
+// temperatures fall back to per-iteration maxima merged pairwise.
+__device__ __forceinline__ float lse_ref(float eps) { return __builtin_amdgcn_sqrtf(1.f + eps); }
+__device__ __forceinline__ bool lse_fixed_shift(float eps, float inv_t2) { return lse_ref(eps) * inv_t2 < 100.f; }
+
+// 2^x without the denormal-range fix-up (results below 2^-126 flush to zero,
+// which only drops terms far below the float resolution of the sums)
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // ----------------------------------------------------------- reductions --
 __device__ __forceinline__ float wave_sum(float v) {
@@ -152,10 +166,15 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
     __syncthreads();  // the previous segment is done with s_lds and scratch
     float e = 0.f;
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const int p = tid + i * WGS;
-        e += cabs2(sx[i]);
-        if (s_in_lds && p < w.n) s_lds[p] = sx[i];
+    for (int i = 0; i < NPT; ++i) e += cabs2(sx[i]);
+    if (s_in_lds) {
+        // 2 MH entries, zero from N on: every lag product index m + tau
+        // (m < MH, tau <= N) reads a sample or a zero
+#pragma unroll
+        for (int i = 0; i < 2 * NPT; ++i) {
+            const int p = tid + i * WGS;
+            if (p < 2 * MH) s_lds[p] = (i < NPT && p < w.n) ? sx[i < NPT ? i : 0] : make_float2(0.f, 0.f);
+        }
     }
     if (twl) {
 #pragma unroll
@@ -173,15 +192,25 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
         // energy and the global soft-PSL normaliser in one fixed-order
         // reduction: thread-strided records, wavefront butterflies, waves in order
         const float inv_t2 = kLog2e / a.temp;
+        const bool fixed = lse_fixed_shift(a.eps, inv_t2);
         float m = -INFINITY;
         double s = 0.0;
+        if (fixed) {
+            // every record carries the shift a_ref
+            m = lse_ref(a.eps);
 #pragma unroll
-        for (int i = 0; i < (MERGE ? PPT : 1); ++i) lse_merge(m, s, pm[i], ps[i], inv_t2);
-        for (int j = tid + PPT * WGS; j < w.seg_count; j += WGS) {
-            const Part pr = a.parts[w.seg_begin + j];
-            lse_merge(m, s, pr.lse_m, pr.lse_s, inv_t2);
+            for (int i = 0; i < (MERGE ? PPT : 1); ++i) s += ps[i];
+            for (int j = tid + PPT * WGS; j < w.seg_count; j += WGS) s += a.parts[w.seg_begin + j].lse_s;
+            s = wave_sum(s);
+        } else {
+#pragma unroll
+            for (int i = 0; i < (MERGE ? PPT : 1); ++i) lse_merge(m, s, pm[i], ps[i], inv_t2);
+            for (int j = tid + PPT * WGS; j < w.seg_count; j += WGS) {
+                const Part pr = a.parts[w.seg_begin + j];
+                lse_merge(m, s, pr.lse_m, pr.lse_s, inv_t2);
+            }
+            wave_lse(m, s, inv_t2);
         }
-        wave_lse(m, s, inv_t2);
         e = wave_sum(e);
         if ((tid & 63) == 0) {
             scratch[3 * (tid >> 6)] = (double)m;
@@ -189,16 +218,38 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
             scratch[3 * (tid >> 6) + 2] = (double)e;
         }
         __syncthreads();
-        m = -INFINITY;
+        m = fixed ? lse_ref(a.eps) : -INFINITY;
         s = 0.0;
         float et = 0.f;
         for (int i = 0; i < WGS / 64; ++i) {
-            lse_merge(m, s, (float)scratch[3 * i], scratch[3 * i + 1], inv_t2);
+            if (fixed)
+                s += scratch[3 * i + 1];
+            else
+                lse_merge(m, s, (float)scratch[3 * i], scratch[3 * i + 1], inv_t2);
             et += (float)scratch[3 * i + 2];
         }
         st.E = et;
         st.glob_m = m;
         st.glob_inv_s = (float)(1.0 / s);
+    }
+    __syncthreads();
+}
+
+// Copy this size's twiddles w_M^i (i < 2 MH) from the global table to LDS
+// (classes with several waveforms, before their first item).
+template <int WGS, int MH>
+__device__ void stage_twiddles(const AfArgs& a, float2* twl, int twsh) {
+    constexpr int TPT = (2 * MH + WGS - 1) / WGS;
+    float2 tx[TPT];
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+        const int j = threadIdx.x + i * WGS;
+        tx[i] = j < 2 * MH ? a.tw[j << twsh] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+        const int j = threadIdx.x + i * WGS;
+        if (j < 2 * MH) twl[j] = tx[i];
     }
     __syncthreads();
 }
@@ -222,7 +273,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const int grp = tid / L;
     const int l = tid - grp * L;
     const int lam = SPLIT ? (grp >> 1) : grp;
-    const int hsel = SPLIT ? (grp & 1) : 0;
+    const int hsel = SPLIT ? ((L % 64 == 0) ? __builtin_amdgcn_readfirstlane(grp & 1) : (grp & 1)) : 0;
     const int t2 = tid - lam * TPL;  // thread index among the lag's threads
     float2* buf = lds + grp * BUF;
     float* rowbuf = reinterpret_cast<float*>(lds + (SPLIT ? 2 * lam : lam) * BUF);
@@ -234,7 +285,17 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const float2* __restrict__ sg_s = a.s + w.s_off;
     const float2* __restrict__ tw = a.tw;
     const int tw_mh = 2 << twsh;  // table entries per MH
-    auto sync = []() { __syncthreads(); };
+    // transform passes exchange data only inside the lane group: when the
+    // group is exactly one wavefront, ordering its own LDS accesses suffices
+    auto sync = []() {
+        if constexpr (L == 64) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    };
 
     const float E = ws.E;
     if (sg.tau_begin == 0 && tid == 0) a.energy[sg.wave] = E;
@@ -243,6 +304,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const float2* __restrict__ sv = s_in_lds ? s_lds : sg_s;
     const float inv_t2 = kLog2e / a.temp;
     const bool want_lse = MODE == MODE_FWD && a.w_psl != 0.f;
+    const bool lse_fixed = lse_fixed_shift(a.eps, inv_t2);
+    const float aref_t2 = lse_ref(a.eps) * inv_t2;
     const float glob_m = ws.glob_m, glob_inv_s = ws.glob_inv_s;
     const bool banded = a.band_w != nullptr && w.band_off >= 0;
     const float* bu = banded ? a.band_w + w.band_off : nullptr;
@@ -289,10 +352,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     };
     const bool compl_isl = a.band_w == nullptr && w.full_window != 0;
     double isl = 0.0, ls = 0.0, dle = 0.0;
-    float lm = -INFINITY;
+    float lm = (want_lse && lse_fixed) ? lse_ref(a.eps) : -INFINITY;
 
     for (int t0 = sg.tau_begin; t0 < sg.tau_end; t0 += LPI) {
-        const int tau = t0 + lam;
+        // lane groups of whole wavefronts: the lag is wave-uniform
+        const int tau = (L % 64 == 0) ? __builtin_amdgcn_readfirstlane(t0 + lam) : t0 + lam;
         const bool active = tau < sg.tau_end;
         const int S = N - tau;
         const float mult = tau > 0 ? 2.f : 1.f;
@@ -325,17 +389,31 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 #pragma unroll
                 for (int q = 0; q < P; ++q) v[q] = active ? ys[l + q * L] : make_float2(0.f, 0.f);
             } else {
+                if (s_in_lds) {
+                    // zero-padded samples: r'[m] = 0 for m >= N - tau comes
+                    // out of the product itself; an inactive lag reads zeros
+                    const int tz = active ? tau : N;
 #pragma unroll
-                for (int r = 0; r < P; ++r) {
-                    const int m = l + r * L;
-                    float2 x = make_float2(0.f, 0.f);
-                    if (active && m < S) {
-                        x = cmulc(sv[m + tau], sv[m]);
+                    for (int r = 0; r < P; ++r) {
+                        const int m = l + r * L;
+                        float2 x = cmulc(sv[m + tz], sv[m]);
                         if (h) x = cmul(x, twl[m << twsh]);
+                        v[r] = x;
+                        if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
                     }
-                    v[r] = x;
-                    // bound how many loads the scheduler keeps in flight
-                    if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < P; ++r) {
+                        const int m = l + r * L;
+                        float2 x = make_float2(0.f, 0.f);
+                        if (active && m < S) {
+                            x = cmulc(sv[m + tau], sv[m]);
+                            if (h) x = cmul(x, twl[m << twsh]);
+                        }
+                        v[r] = x;
+                        // bound how many loads the scheduler keeps in flight
+                        if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
                 fft_group<MH, P, -1>(v, buf, l, twl, tw_mh, sync);
             }
@@ -359,84 +437,124 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // p = |Y'|^2/E^2, a = sqrt(p + eps); the sidelobe test and the
             // weight are symmetric under (tau, k) -> (-tau, -k).  Sums over
             // the lane's bins run in float, then fold into float64.
-            float isl_f = 0.f, dle_f = 0.f, mloc = -INFINITY;
+            float isl_f = 0.f, dle_f = 0.f, mloc = -INFINITY, sl_f = 0.f;
             float avs[(MODE == MODE_FWD) ? P : 1];
+            // One straight-line copy per loss configuration (shift rule,
+            // banded weights, mainlobe complement, soft-PSL on/off): every
+            // condition left inside is per lane and becomes a select.
+            auto epilogue = [&](auto fixed_c, auto banded_c, auto compl_c, auto psl_c) {
+                constexpr bool FIXED = decltype(fixed_c)::value;
+                constexpr bool BANDED = decltype(banded_c)::value;
+                constexpr bool COMPL = decltype(compl_c)::value;
+                constexpr bool PSL = decltype(psl_c)::value;
+                const float c_main = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
 #pragma unroll
-            for (int q = 0; q < P; ++q) {
-                const int k = 2 * (l + q * L) + h;
-                const int kn = k ? M - k : 0;
-                const int kc = k < (M >> 1) ? k : M - k;  // |centred bin|
-                const float pw = cabs2(v[q]) * invE2;
-                const float av = __builtin_amdgcn_sqrtf(pw + a.eps);
-                const bool sd = active && !(main_tau && kc <= w.h_k);
-                float wt = 1.f;
-                if (banded && sd) wt = wu * bv[floor_div_small(31 * kc, (M >> 1) + 1)];
-                if (HAS_MAG_OUT) {
-                    if (mag_out) {
-                        if (SPLIT) {
-                            rowbuf[k] = av;
-                            rowbuf[M + kn] = av;
-                        } else if (active) {
-                            a.mag[row_p + k] = av;
-                            if (tau > 0) a.mag[row_n + kn] = av;
+                for (int q = 0; q < P; ++q) {
+                    const int k = 2 * (l + q * L) + h;
+                    const int kn = k ? M - k : 0;
+                    const int kc = k < (M >> 1) ? k : M - k;  // |centred bin|
+                    const float pw = cabs2(v[q]) * invE2;
+                    const float av = __builtin_amdgcn_sqrtf(pw + a.eps);
+                    const bool main_cell = active && main_tau && kc <= w.h_k;
+                    const bool sd = active && !main_cell;
+                    float wt = 1.f;
+                    if constexpr (BANDED) {
+                        // the band index is in [0, 30] for every bin
+                        wt = wu * bv[floor_div_small(31 * kc, (M >> 1) + 1)];
+                    }
+                    if (HAS_MAG_OUT) {
+                        if (mag_out) {
+                            if (SPLIT) {
+                                rowbuf[k] = av;
+                                rowbuf[M + kn] = av;
+                            } else if (active) {
+                                a.mag[row_p + k] = av;
+                                if (tau > 0) a.mag[row_n + kn] = av;
+                            }
+                        }
+                        if constexpr (COMPL)
+                            isl_f -= main_cell ? pw : 0.f;  // mainlobe power
+                        else
+                            isl_f = fmaf(sd ? wt : 0.f, pw, isl_f);
+                    }
+                    if constexpr (MODE == MODE_FWD && PSL) {
+                        if constexpr (FIXED) {
+                            sl_f += sd ? fast_exp2(fmaf(av, inv_t2, -aref_t2)) : 0.f;
+                        } else {
+                            avs[q] = sd ? av : -INFINITY;
+                            mloc = fmaxf(mloc, avs[q]);
                         }
                     }
-                    if (compl_isl) {
-                        if (active && !sd) isl_f -= pw;  // mainlobe power
-                    } else if (sd) {
-                        isl_f = fmaf(wt, pw, isl_f);
-                    }
-                }
-                if (MODE == MODE_FWD) {
-                    avs[q] = sd ? av : -INFINITY;
-                    mloc = fmaxf(mloc, avs[q]);
-                }
-                if constexpr (NEEDS_INV) {
-                    float c = 0.f;
-                    if (MODE == MODE_BWD_MAG) {
-                        if (active) {
+                    if constexpr (NEEDS_INV) {
+                        float c = 0.f;
+                        if constexpr (MODE == MODE_BWD_MAG) {
                             float g;
                             if (SPLIT) {
                                 g = rowbuf[k];
                                 if (tau > 0) g += rowbuf[M + kn];
                             } else {
-                                g = a.grad_mag[row_p + k];
-                                if (tau > 0) g += a.grad_mag[row_n + kn];
+                                g = active ? a.grad_mag[row_p + k] : 0.f;
+                                if (active && tau > 0) g += a.grad_mag[row_n + kn];
                             }
+                            g = active ? g : 0.f;
                             const float ia = __builtin_amdgcn_rcpf(av);
                             c = 0.5f * g * invE2 * ia;
                             dle_f = fmaf(-g * pw * invE, ia, dle_f);
-                        }
-                    } else if (MODE == MODE_BWD_LOSS) {
-                        if (sd) {
-                            c = compl_isl ? 0.f : a.w_isl * wt * invE2;
-                            if (a.w_psl != 0.f) {
-                                const float qq = exp2f((av - glob_m) * inv_t2) * glob_inv_s;
+                        } else if constexpr (MODE == MODE_BWD_LOSS) {
+                            float cs = COMPL ? 0.f : a.w_isl * wt * invE2;
+                            if constexpr (PSL) {
+                                const float qq = fast_exp2((av - glob_m) * inv_t2) * glob_inv_s;
                                 const float ia = __builtin_amdgcn_rcpf(av);
-                                c = fmaf(a.w_psl * qq * 0.5f * invE2, ia, c);
-                                dle_f = fmaf(-a.w_psl * qq * pw * invE, ia, dle_f);
+                                cs = fmaf(a.w_psl * qq * 0.5f * invE2, ia, cs);
+                                dle_f = fmaf(sd ? -a.w_psl * qq * pw * invE : 0.f, ia, dle_f);
                             }
-                            c *= mult;
-                        } else if (compl_isl && active) {
-                            c = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
+                            c = sd ? mult * cs : ((COMPL && main_cell) ? c_main : 0.f);
+                        } else {  // MODE_FUSED_ISL
+                            if constexpr (COMPL)
+                                c = main_cell ? c_main : 0.f;
+                            else
+                                c = sd ? mult * a.w_isl * wt * invE2 : 0.f;
                         }
-                    } else {  // MODE_FUSED_ISL
-                        if (compl_isl) {
-                            if (active && !sd) c = -mult * a.w_isl * invE2;
-                        } else if (sd) {
-                            c = mult * a.w_isl * wt * invE2;
-                        }
+                        v[q] = cscale(v[q], c);
                     }
-                    v[q] = cscale(v[q], c);
                 }
+            };
+            using T_ = std::integral_constant<bool, true>;
+            using F_ = std::integral_constant<bool, false>;
+            auto by_loss = [&](auto fixed_c, auto psl_c) {
+                if (banded)
+                    epilogue(fixed_c, T_{}, F_{}, psl_c);
+                else if (compl_isl)
+                    epilogue(fixed_c, F_{}, T_{}, psl_c);
+                else
+                    epilogue(fixed_c, F_{}, F_{}, psl_c);
+            };
+            if constexpr (MODE == MODE_FWD) {
+                if (!want_lse)
+                    by_loss(T_{}, F_{});
+                else if (lse_fixed)
+                    by_loss(T_{}, T_{});
+                else
+                    by_loss(F_{}, T_{});
+            } else if constexpr (MODE == MODE_BWD_LOSS) {
+                if (a.w_psl != 0.f)
+                    by_loss(T_{}, T_{});
+                else
+                    by_loss(T_{}, F_{});
+            } else if constexpr (MODE == MODE_BWD_MAG) {
+                epilogue(T_{}, F_{}, F_{}, F_{});
+            } else {
+                by_loss(T_{}, F_{});
             }
             isl += (double)(mult * isl_f);
             dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f);
-            if (MODE == MODE_FWD && want_lse && mloc > -INFINITY) {
+            if (MODE == MODE_FWD && want_lse && lse_fixed) {
+                ls += (double)(mult * sl_f);
+            } else if (MODE == MODE_FWD && want_lse && mloc > -INFINITY) {
                 // this iteration's sidelobe cells, two per bin for tau > 0
                 float sl = 0.f;
 #pragma unroll
-                for (int q = 0; q < P; ++q) sl += exp2f((avs[q] - mloc) * inv_t2);
+                for (int q = 0; q < P; ++q) sl += fast_exp2((avs[q] - mloc) * inv_t2);
                 lse_merge(lm, ls, mloc, (double)(mult * sl), inv_t2);
             }
 
@@ -493,8 +611,14 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 #pragma unroll
                     for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl[(l + q * L) << twsh]);
                 }
+                if constexpr (L % 32 == 0) {
+                    const int bi = lds_index(l);
 #pragma unroll
-                for (int q = 0; q < P; ++q) buf[lds_index(l + q * L)] = v[q];
+                    for (int q = 0; q < P; ++q) buf[bi + lds_off(q * L)] = v[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < P; ++q) buf[lds_index(l + q * L)] = v[q];
+                }
                 if constexpr (!SPLIT) {
                     // halves in turn: this half's share of every lag's adjoint
                     __syncthreads();
@@ -520,7 +644,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 
     // ------------------------------------------- segment results -------
     // one fixed-order reduction of (ISL, soft-PSL pair, dL/dE) over the group
-    if (MODE == MODE_FWD) wave_lse(lm, ls, inv_t2);
+    if (MODE == MODE_FWD) {
+        if (lse_fixed)
+            ls = wave_sum(ls);
+        else
+            wave_lse(lm, ls, inv_t2);
+    }
     isl = wave_sum(isl);
     dle = wave_sum(dle);
     __syncthreads();
@@ -603,18 +732,27 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     const int twsh = V::TW_LDS ? 0 : twsh_global;
     WaveState st;
     st.wave = -1;
-    if (a.single && blockIdx.x < a.n_segs) {
-        // one waveform: stage it before the first item so that the item, the
-        // samples and the twiddles travel in the same memory round trip
-        stage_wave<MODE, V::WGS, MH>(a, a.w0, a.w0_index, s_lds, V::S_LDS != 0, scratch, st, tw_lds, twsh_global);
+    // the first item's descriptor travels with the staging loads; each later
+    // one is fetched while the previous item runs
+    SegDesc next;
+    if (blockIdx.x < a.n_segs) next = a.segs[blockIdx.x];
+    if (blockIdx.x < a.n_segs) {
+        if (a.single) {
+            // one waveform: its samples, the twiddles and the first item's
+            // descriptor travel in the same memory round trip
+            stage_wave<MODE, V::WGS, MH>(a, a.w0, a.w0_index, s_lds, V::S_LDS != 0, scratch, st, tw_lds,
+                                         twsh_global);
+        } else if (tw_lds) {
+            stage_twiddles<V::WGS, MH>(a, tw_lds, twsh_global);
+        }
     }
     for (int item = blockIdx.x; item < a.n_segs; item += gridDim.x) {
-        const SegDesc sg = a.segs[item];
+        const SegDesc sg = next;
+        if (item + (int)gridDim.x < a.n_segs) next = a.segs[item + gridDim.x];
         if (sg.wave != st.wave) {
             // a class with one waveform carries its descriptor in the arguments
             const WaveDesc w = a.single ? a.w0 : a.waves[sg.wave];
-            stage_wave<MODE, V::WGS, MH>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st,
-                                         st.wave < 0 ? tw_lds : nullptr, twsh_global);
+            stage_wave<MODE, V::WGS, MH>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st, nullptr, 0);
         }
         process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG)>(a, sg, lds, twl, twsh, s_lds, V::S_LDS != 0,
                                                                       scratch, st);
