@@ -42,34 +42,44 @@ def timed(fn, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline_single(n, m, seed):
+def cpu_baseline_single(n, m, seed, budget_s=10.0):
     """The float64 oracle (direct sums, OpenMP) on the same single-waveform
-    problem: loss + gradient once, as cells per second."""
+    problem: loss + gradient repeated for about budget_s seconds, as cells
+    per second."""
     import oracle as O
     from oracle import _native
     from paper_2506_22935_amd import workloads as W
     s = O.to_c64_exact(W.random_code(n, seed=seed))
     lp = O.LossParams(w_isl=1.0, w_psl=1.0, temp=0.05, h_tau=1, h_k=1, eps=1e-12)
-    t0 = time.perf_counter()
-    O.loss_and_grad(s, m, n - 1, lp)
-    dt = time.perf_counter() - t0
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        O.loss_and_grad(s, m, n - 1, lp)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
     cells = (2 * n - 1) * m
-    return dict(value=cells / dt, unit="cells/s", cores=_native.threads(), kind="oracle",
-                sample="full %d-lag x %d-bin grid, loss + gradient once (%.1f s)" % (2 * n - 1, m, dt))
+    return dict(value=reps * cells / dt, unit="cells/s", cores=_native.threads(), kind="oracle",
+                sample="full %d-lag x %d-bin grid, loss + gradient %d times (%.1f s)" % (2 * n - 1, m, reps, dt))
+
+
+def fft_flops(n_transforms, m):
+    """Algorithmic flops of n_transforms complex M-point transforms (5 M log2 M each)."""
+    return 5.0 * m * math.log2(m) * n_transforms
 
 
 def bench_single(args, torch):
     from paper_2506_22935_amd import af, workloads as W
     n, m = 1024, 2048
+    T = n - 1
     cells = (2 * n - 1) * m
     s = torch.from_numpy(W.random_code(n, seed=args.seed)).cuda()
     lp = dict(w_isl=1.0, w_psl=1.0, temp=0.05)
     results = {}
-    modes = {"auto": (1, 2), "store": (1,), "recompute": (2,)}[args.store]
     variants = [args.variant] if args.variant >= 0 else [0, 3, 4]
-    for store, variant in [(st, v) for st in modes for v in variants]:
+    for variant in variants:
         try:
-            plan = af.Plan([n], [m], eps=1e-12, store_mode=store, variant=variant)
+            plan = af.Plan([n], [m], eps=1e-12, store_mode=2, variant=variant)
         except Exception as e:  # variant does not fit this size
             log("variant %d: %s" % (variant, e))
             continue
@@ -87,52 +97,53 @@ def bench_single(args, torch):
         torch.cuda.synchronize()
         ms = timed(step, args.steps, torch)
         stage_ms = [timed(lambda st=st: plan.loss_stage(st, s, terms, grad, mag, ws=ws, **lp), args.steps, torch)
-                    for st in (0, 1, 2)]
-        log("store=%d variant=%d: %.4f ms/step, stages %s" % (store, variant, ms, ["%.4f" % x for x in stage_ms]))
-        results[(store, variant)] = (ms, stage_ms, plan)
-    store, variant = min(results, key=lambda k: results[k][0])
-    ms, stage_ms, plan = results[(store, variant)]
-    logm = int(math.log2(m))
+                    for st in (0, 2)]
+        log("variant=%d: %.4f ms/step, fused pass %.4f ms, reduce %.4f ms" % (variant, ms, stage_ms[0], stage_ms[1]))
+        results[variant] = (ms, stage_ms, plan)
+    variant = min(results, key=lambda k: results[k][0])
+    ms, stage_ms, plan = results[variant]
 
-    # roofline of the dominant kernel
-    names = ["forward (FFT + a grid + loss partials)", "backward (FFT adjoint + lag gather)", "reduce"]
-    dom = max(range(3), key=lambda i: stage_ms[i])
-    if dom == 0:
-        bytes_alg = 4.0 * cells  # the a grid it writes
-        ach = bytes_alg / (stage_ms[0] * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
-    else:
-        flops = 5.0 * logm * cells  # the inverse transform over every cell
-        ach = flops / (stage_ms[dom] * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None)
-    roof["kernel"] = names[dom]
-    roof["kernel_ms"] = round(stage_ms[dom], 5)
+    # roofline of the dominant kernel, the fused loss pass: one forward and
+    # one inverse M-point transform per lag pair (T + 1 of them) over the
+    # kernel's average duration; bound by vector ALU issue
+    flops = 2.0 * fft_flops(T + 1, m)
+    ach = flops / (stage_ms[0] * 1e-3) / 1e12
+    roof = dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
+                kernel="fused loss pass (forward + backward transforms, a grid, loss partials)",
+                kernel_ms=round(stage_ms[0], 5), flops_per_launch=flops)
+
+    # the a grid the step writes, against HBM
+    hbm_step = 4.0 * cells / (ms * 1e-3) / 1e9
 
     # the materialised user-loss path: a grid out, dL/da grid in (8 B per cell)
-    mplan = af.Plan([n], [m], eps=1e-12, store_mode=2, variant=variant)
-    mws = mplan.workspace
-    ga = torch.from_numpy(W.upstream_grid(2 * n - 1, m, seed=1).ravel()).cuda()
-    mag2 = torch.empty(cells, dtype=torch.float32, device="cuda")
-    g2 = torch.empty(n, dtype=torch.complex64, device="cuda")
+    mat = {}
+    for store in (1, 2):
+        mplan = af.Plan([n], [m], eps=1e-12, store_mode=store, variant=variant)
+        mws = mplan.workspace
+        ga = torch.from_numpy(W.upstream_grid(2 * n - 1, m, seed=1).ravel()).cuda()
+        mag2 = torch.empty(cells, dtype=torch.float32, device="cuda")
+        g2 = torch.empty(n, dtype=torch.complex64, device="cuda")
 
-    def mstep():
-        mplan.forward(s, mag=True, ws=mws, out_mag=mag2)
-        mplan.backward(s, ga, ws=mws, out=g2)
+        def mstep():
+            mplan.forward(s, mag=True, ws=mws, out_mag=mag2)
+            mplan.backward(s, ga, ws=mws, out=g2)
 
-    for _ in range(args.warmup):
-        mstep()
-    mms = timed(mstep, args.steps, torch)
-    mat = dict(ms_per_step=round(mms, 5), cells_per_s=cells / (mms * 1e-3),
-               hbm_frac_8B_per_cell=round(8.0 * cells / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
-    log("materialised fwd+bwd: %.4f ms" % mms)
+        for _ in range(args.warmup):
+            mstep()
+        mms = timed(mstep, args.steps, torch)
+        mat["store" if store == 1 else "recompute"] = dict(
+            ms_per_step=round(mms, 5), cells_per_s=cells / (mms * 1e-3),
+            hbm_frac_8B_per_cell=round(8.0 * cells / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+        log("materialised fwd+bwd (store=%d): %.4f ms" % (store, mms))
 
     out = dict(value=cells / (ms * 1e-3), ms_per_step=ms,
                config=dict(workload="single: N=1024 random-phase code, 2047 lags x M=2048, "
                                     "ISL(|tau|<=1,|k|<=1)+softPSL(T=0.05) fwd+bwd, a grid written",
-                           n=n, m=m, lags=2 * n - 1, cells=cells, store=bool(store == 1), variant=variant,
-                           stage_ms=[round(x, 5) for x in stage_ms], materialised_fwd_bwd=mat),
+                           n=n, m=m, lags=2 * n - 1, cells=cells, variant=variant, path="fused loss pass + reduce",
+                           stage_ms=dict(fused_pass=round(stage_ms[0], 5), reduce=round(stage_ms[1], 5)),
+                           a_grid_hbm_gbs=round(hbm_step, 1), a_grid_hbm_frac=round(hbm_step / HBM_PEAK_GBS, 4),
+                           materialised_fwd_bwd=mat),
                roofline=roof)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -170,7 +181,8 @@ def bench_uneven(args, torch):
     # the fused ISL pass alone (one persistent launch per size class)
     grad = torch.empty(plan.total_samples, dtype=torch.complex64, device="cuda")
     fused_ms = timed(lambda: plan.loss_stage(0, st.s, terms, grad, None, w_isl=1.0, ws=ws), 20, torch)
-    flops = sum(10.0 * math.log2(m) * (2 * n - 1) * m for n, m in zip(ns, ms))  # forward + inverse
+    # one forward and one inverse M-point transform per lag pair (N of them)
+    flops = sum(2.0 * fft_flops(int(n), int(m)) for n, m in zip(ns, ms))
     ach = flops / (fused_ms * 1e-3) / 1e12
     log("uneven: %.3f ms/step (graph), fused pass %.3f ms, sum ISL %.4g -> %.4g" % (ms_step, fused_ms, isl0, isl1))
     out = dict(value=cells / (ms_step * 1e-3), ms_per_step=ms_step,
@@ -182,19 +194,37 @@ def bench_uneven(args, torch):
                              frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
                              kernel="fused ISL forward+backward (all size classes)", kernel_ms=round(fused_ms, 4)))
     if not args.no_cpu_baseline:
-        import oracle as O
-        from oracle import _native
-        order = np.argsort(ns)[:8]
-        t0 = time.perf_counter()
-        c = 0
-        for b in order:
-            n, m = int(ns[b]), int(ms[b])
-            O.loss_and_grad(O.to_c64_exact(W.unimodular(phases[b])), m, n - 1, O.LossParams(eps=1e-12))
-            c += (2 * n - 1) * m
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = dict(value=c / dt, unit="cells/s", cores=_native.threads(), kind="oracle",
-                                   sample="loss + gradient of the 8 shortest waveforms (%.1f s)" % dt)
+        out["cpu_baseline"] = cpu_baseline_uneven(ns, ms, phases, args.seed)
     return out
+
+
+def cpu_baseline_uneven(ns, ms, phases, seed, budget_s=12.0):
+    """The oracle on a time-bounded sample of the batch: waveforms in a seeded
+    random order, skipping any whose predicted cost (the direct sums scale as
+    N^2 M) would overrun the budget."""
+    import numpy as np
+    import oracle as O
+    from oracle import _native
+    from paper_2506_22935_amd import workloads as W
+    order = np.random.default_rng(seed + 99).permutation(len(ns))
+    done_cells, done_t, rate, picked = 0, 0.0, None, []
+    for b in order:
+        n, m = int(ns[b]), int(ms[b])
+        work = float(n) * n * m
+        if rate is not None and done_t + rate * work > budget_s:
+            continue
+        t0 = time.perf_counter()
+        O.loss_and_grad(O.to_c64_exact(W.unimodular(phases[b])), m, n - 1, O.LossParams(eps=1e-12))
+        dt = time.perf_counter() - t0
+        done_t += dt
+        done_cells += (2 * n - 1) * m
+        picked.append(n)
+        rate = done_t / sum(float(x) * x * W.next_pow2(2 * x) for x in picked)
+        if done_t >= budget_s:
+            break
+    return dict(value=done_cells / done_t, unit="cells/s", cores=_native.threads(), kind="oracle",
+                sample="loss + gradient of %d waveforms (N %d..%d) in seeded random order, %.1f s"
+                       % (len(picked), min(picked), max(picked), done_t))
 
 
 def bench_large(args, torch):

@@ -81,6 +81,8 @@ typedef struct {
     int64_t budget_bytes;      /* workspace budget; <= 0 means unlimited */
     int32_t variant;           /* -1: library default; >= 0 forces a kernel variant */
     int32_t segment_iters;     /* lag iterations per work item; 0: planner's choice */
+    int32_t loss_passes;       /* 0: af_loss / af_optim_step use one fused pass where the
+                                  loss allows it; 1: always a forward then a backward pass */
 } af_plan_opts;
 
 typedef struct af_plan af_plan;
@@ -144,16 +146,21 @@ af_status af_backward(const af_plan* plan, const void* s, const float* grad_mag,
 /* Built-in loss forward and backward.  terms: device float[batch][4] receiving
  * (L, ISL, softPSL, E) per waveform (nullable).  mag (nullable): the a grids.
  * grad_s (nullable: loss only): dL/d conj(s).  With w_psl == 0 one fused pass
- * does everything; with w_psl != 0 a forward pass finds the soft-PSL
- * normaliser first. */
+ * does everything.  With w_psl != 0, one fused pass also does when band_w is
+ * NULL, every waveform has the full lag window (or w_isl == 0), psl_temp >=
+ * sqrt(1 + eps) log2(e) / 100 and the kernel variant splits the two half
+ * transforms: the soft-PSL gradient leaves that pass without its global
+ * normaliser, which the reduction applies.  Otherwise a forward pass finds the
+ * normaliser first and a backward pass follows. */
 af_status af_loss(const af_plan* plan, const void* s, const af_loss_params* loss, float* terms, float* mag,
                   void* grad_s, void* ws, size_t ws_bytes, void* stream);
 
 /* One stage of af_loss on its own, for timing and profiling.  stage 0: the
- * forward pass (a grids and loss partials; with w_psl == 0 and grad_s set,
- * the single fused pass instead); stage 1: the backward pass (w_psl != 0 only;
- * reads the partials of stage 0 from ws); stage 2: the reduction into terms
- * and grad_s.  Running stages 0, 1, 2 in order equals one af_loss call. */
+ * forward pass (a grids and loss partials; with grad_s set and a loss that
+ * allows it, the single fused pass instead); stage 1: the backward pass (only
+ * when stage 0 was not fused; reads the partials of stage 0 from ws); stage
+ * 2: the reduction into terms and grad_s.  Running stages 0, 1, 2 in order
+ * equals one af_loss call. */
 af_status af_loss_stage(const af_plan* plan, int32_t stage, const void* s, const af_loss_params* loss,
                         float* terms, float* mag, void* grad_s, void* ws, size_t ws_bytes, void* stream);
 

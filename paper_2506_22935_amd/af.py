@@ -37,7 +37,7 @@ class Plan:
     """
 
     def __init__(self, lengths, ms, max_lags=None, h_tau=1, h_k=1, eps=1e-12, store_mode=0,
-                 budget_bytes=0, variant=-1, segment_iters=0):
+                 budget_bytes=0, variant=-1, segment_iters=0, loss_passes=0):
         lengths = [int(n) for n in lengths]
         ms = [int(m) for m in ms]
         B = len(lengths)
@@ -63,7 +63,8 @@ class Plan:
         self.batch, self.lengths, self.ms, self.max_lags = B, lengths, ms, max_lags
         self.total_samples, self.total_cells = s_off, g_off
         opts = L.AfPlanOpts(eps=float(eps), store_mode=int(store_mode), budget_bytes=int(budget_bytes),
-                            variant=int(variant), segment_iters=int(segment_iters))
+                            variant=int(variant), segment_iters=int(segment_iters),
+                            loss_passes=int(loss_passes))
         h = ctypes.c_void_p()
         L.check("af_plan_create", L.lib().af_plan_create(B, waves, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h

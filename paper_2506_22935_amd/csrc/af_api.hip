@@ -46,6 +46,7 @@ struct af_plan {
     int store_mode = 0;
     int64_t budget = 0;
     int seg_iters_opt = 0;
+    int loss_passes_opt = 0;
 
     // schedule: one class per distinct M, each with its own kernel variant,
     // slice of the execution order, grid and work-queue counters
@@ -53,7 +54,7 @@ struct af_plan {
         int lg = 0;          // log2(M/2)
         int variant = -1;
         int begin = 0, count = 0;  // slice of the execution order
-        int grid[4] = {0, 0, 0, 0};
+        int grid[graf::kNumModes] = {};
         int dyn_lds = 0;
         int max_n = 0;
         int single_wave = -1;  // the waveform index when the class has one
@@ -68,13 +69,12 @@ struct af_plan {
     int log2_mmax = 0;
     int max_n = 0;
     int64_t cells = 0, store_bytes = 0;
-    size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_store = 0, ws_total = 0;
+    size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_slabs2 = 0, off_store = 0, ws_total = 0;
 
     // plan-owned device tables
     WaveDesc* d_waves = nullptr;
     SegDesc* d_segs = nullptr;
-    int* d_order = nullptr;
-    int2* d_chunks = nullptr;  // reduce blocks
+    graf::RBlock* d_chunks = nullptr;  // reduce blocks
     float2* d_tw = nullptr;
     unsigned* d_ctrl = nullptr;
     size_t cap_segs = 0, cap_chunks = 0;
@@ -85,13 +85,11 @@ namespace {
 void free_tables(af_plan* p) {
     if (p->d_waves) (void)hipFree(p->d_waves);
     if (p->d_segs) (void)hipFree(p->d_segs);
-    if (p->d_order) (void)hipFree(p->d_order);
     if (p->d_chunks) (void)hipFree(p->d_chunks);
     if (p->d_tw) (void)hipFree(p->d_tw);
     if (p->d_ctrl) (void)hipFree(p->d_ctrl);
     p->d_waves = nullptr;
     p->d_segs = nullptr;
-    p->d_order = nullptr;
     p->d_chunks = nullptr;
     p->d_tw = nullptr;
     p->d_ctrl = nullptr;
@@ -152,7 +150,7 @@ af_status build_schedule(af_plan* p) {
         k.variant = v;
         const VariantInfo vi = graf::variant_info(v, k.lg);
         k.dyn_lds = vi.fft_lds + (vi.s_lds ? 8 * (2 << k.lg) : 0);  // samples zero-padded to M
-        for (int mode = 0; mode < 4; ++mode) {
+        for (int mode = 0; mode < graf::kNumModes; ++mode) {
             const int r = graf::variant_max_resident(mode, v, k.lg, k.dyn_lds);
             if (r <= 0) return AF_ERR_UNSUPPORTED;
             k.grid[mode] = r * p->cus;  // capped by the segment count below
@@ -178,8 +176,8 @@ af_status build_schedule(af_plan* p) {
     std::vector<WaveDesc> wd(B);
     std::vector<SegDesc> segs;
     std::vector<double> seg_cost;
-    std::vector<int2> rblocks;  // reduce blocks: (wave, first sample)
-    int64_t slab_elems = 0, store_elems = 0;
+    std::vector<int2> rpos;  // reduce blocks: (wave, first sample)
+    int64_t slab_elems = 0, slab2_elems = 0, store_elems = 0;
     for (int b = 0; b < B; ++b) {
         const af_wave& w = p->waves[b];
         int per = p->seg_iters_opt > 0 ? p->seg_iters_opt
@@ -210,6 +208,12 @@ af_status build_schedule(af_plan* p) {
         }
         d.seg_count = (int)segs.size() - d.seg_begin;
         slab_elems += (int64_t)d.seg_count * w.n;
+        // segments holding mainlobe lags (second slabs of the fused loss pass)
+        d.isl_segs = 0;
+        for (int i = d.seg_begin; i < (int)segs.size(); ++i)
+            if (segs[i].tau_begin <= w.h_tau) ++d.isl_segs;
+        d.slab2_off = slab2_elems;
+        slab2_elems += (int64_t)d.isl_segs * w.n;
         store_elems += (int64_t)(w.max_lag + 1) * w.m;
         (void)0;
     }
@@ -219,7 +223,7 @@ af_status build_schedule(af_plan* p) {
     for (int b = 0; b < B; ++b) max_segs = std::max(max_segs, wd[b].seg_count);
     const int sg_log = max_segs >= 64 ? 4 : 2;
     for (int b = 0; b < B; ++b)
-        for (int c = 0; c < wd[b].n; c += (256 >> sg_log)) rblocks.push_back(make_int2(b, c));
+        for (int c = 0; c < wd[b].n; c += (256 >> sg_log)) rpos.push_back(make_int2(b, c));
 
     // execution order: by class, longest segment first within a class
     std::vector<int> order;
@@ -242,8 +246,9 @@ af_status build_schedule(af_plan* p) {
     const size_t parts_b = align256(segs.size() * sizeof(graf::Part));
     const size_t energy_b = align256((size_t)B * sizeof(float));
     const size_t slabs_b = align256((size_t)slab_elems * sizeof(float2));
+    const size_t slabs2_b = align256((size_t)slab2_elems * sizeof(float2));
     const size_t store_b = align256((size_t)store_elems * sizeof(float2));
-    const size_t base = parts_b + energy_b + slabs_b;
+    const size_t base = parts_b + energy_b + slabs_b + slabs2_b;
     bool stores;
     if (p->store_mode == 1)
         stores = true;
@@ -256,17 +261,21 @@ af_status build_schedule(af_plan* p) {
     // upload
     if (segs.size() > p->cap_segs) {
         if (p->d_segs) (void)hipFree(p->d_segs);
-        if (p->d_order) (void)hipFree(p->d_order);
         p->d_segs = nullptr;
-        p->d_order = nullptr;
         if (hipMalloc(&p->d_segs, segs.size() * sizeof(SegDesc)) != hipSuccess) return hip_fail();
-        if (hipMalloc(&p->d_order, segs.size() * sizeof(int)) != hipSuccess) return hip_fail();
         p->cap_segs = segs.size();
+    }
+    // reduce blocks carry their waveform's final descriptor
+    std::vector<graf::RBlock> rblocks(rpos.size());
+    for (size_t i = 0; i < rpos.size(); ++i) {
+        rblocks[i].w = wd[rpos[i].x];
+        rblocks[i].wave = rpos[i].x;
+        rblocks[i].p0 = rpos[i].y;
     }
     if (rblocks.size() > p->cap_chunks) {
         if (p->d_chunks) (void)hipFree(p->d_chunks);
         p->d_chunks = nullptr;
-        if (hipMalloc(&p->d_chunks, rblocks.size() * sizeof(int2)) != hipSuccess) return hip_fail();
+        if (hipMalloc(&p->d_chunks, rblocks.size() * sizeof(graf::RBlock)) != hipSuccess) return hip_fail();
         p->cap_chunks = rblocks.size();
     }
     if (!p->d_waves && hipMalloc(&p->d_waves, (size_t)B * sizeof(WaveDesc)) != hipSuccess) return hip_fail();
@@ -277,8 +286,8 @@ af_status build_schedule(af_plan* p) {
     if (2 * C + 2 > kCtrlWords) return AF_ERR_UNSUPPORTED;
     if (hipMemcpy(p->d_waves, wd.data(), (size_t)B * sizeof(WaveDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_segs, exec.data(), exec.size() * sizeof(SegDesc), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_chunks, rblocks.data(), rblocks.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(p->d_chunks, rblocks.data(), rblocks.size() * sizeof(graf::RBlock), hipMemcpyHostToDevice) !=
+            hipSuccess)
         return hip_fail();
 
     for (int c = 0; c < C; ++c) {
@@ -300,6 +309,7 @@ af_status build_schedule(af_plan* p) {
     p->off_parts = 0;
     p->off_energy = parts_b;
     p->off_slabs = parts_b + energy_b;
+    p->off_slabs2 = parts_b + energy_b + slabs_b;
     p->off_store = base;
     p->ws_total = base + (stores ? store_b : 0);
     return AF_OK;
@@ -308,6 +318,7 @@ af_status build_schedule(af_plan* p) {
 af_status validate_plan_inputs(int32_t batch, const af_wave* waves, const af_plan_opts* opts) {
     if (batch <= 0 || !waves || !opts) return AF_ERR_INVALID_ARG;
     if (!(opts->eps >= 0.f) || opts->store_mode < 0 || opts->store_mode > 2) return AF_ERR_INVALID_ARG;
+    if (opts->loss_passes < 0 || opts->loss_passes > 1) return AF_ERR_INVALID_ARG;
     for (int b = 0; b < batch; ++b) {
         const af_wave& w = waves[b];
         if (w.n < 1 || w.s_off < 0 || w.grid_off < 0 || w.h_tau < 0 || w.h_k < 0 || w.reserved != 0)
@@ -324,6 +335,7 @@ struct WsView {
     graf::Part* parts;
     float* energy;
     float2* slabs;
+    float2* slabs2;
     float2* store;
 };
 
@@ -333,6 +345,7 @@ WsView ws_view(const af_plan* p, void* ws) {
     v.parts = (graf::Part*)(b + p->off_parts);
     v.energy = (float*)(b + p->off_energy);
     v.slabs = (float2*)(b + p->off_slabs);
+    v.slabs2 = (float2*)(b + p->off_slabs2);
     v.store = p->stores ? (float2*)(b + p->off_store) : nullptr;
     return v;
 }
@@ -352,6 +365,7 @@ AfArgs base_args(const af_plan* p, const void* s, const WsView& v) {
     a.temp = 1.f;
     a.parts = v.parts;
     a.slabs = v.slabs;
+    a.slabs2 = v.slabs2;
     a.energy = v.energy;
     return a;
 }
@@ -360,12 +374,16 @@ ReduceArgs reduce_args(const af_plan* p, const void* s, const WsView& v) {
     ReduceArgs r;
     std::memset(&r, 0, sizeof(r));
     r.s = (const float2*)s;
-    r.waves = p->d_waves;
     r.blocks = p->d_chunks;
+    if (p->batch == 1) {
+        r.single = 1;
+        r.w0 = p->wave_desc[0];
+    }
     r.n_blocks = p->n_chunks;
     r.sg_log = p->sg_log;
     r.parts = v.parts;
     r.slabs = v.slabs;
+    r.slabs2 = v.slabs2;
     r.energy = v.energy;
     r.temp = 1.f;
     r.ctrl = p->d_ctrl + (kCtrlWords - 2);
@@ -407,6 +425,23 @@ af_status check_loss(const af_loss_params* lp) {
 }
 
 // loss forward/backward into slabs and parts (no reduce)
+// Can ISL + soft-PSL forward and backward run as one pass (MODE_LOSS)?  The
+// soft-PSL gradient then leaves the pass without its normaliser 1/S: this
+// needs the fixed shift of the soft-PSL sums (the same rule the kernels use),
+// uniform ISL weights with full lag windows (the ISL gradient then lives on
+// the mainlobe cells) and variants that split the two half transforms.
+bool fused_loss_ok(const af_plan* p, const af_loss_params* lp) {
+    if (p->loss_passes_opt == 1 || lp->w_psl == 0.f || lp->band_w != nullptr) return false;
+    const float inv_t2 = 1.4426950408889634f / lp->psl_temp;
+    if (!(std::sqrt(1.f + p->eps) * inv_t2 < 100.f)) return false;
+    for (const af_plan::Class& k : p->classes)
+        if (!graf::variant_info(k.variant, k.lg).split) return false;
+    if (lp->w_isl != 0.f)
+        for (const WaveDesc& d : p->wave_desc)
+            if (!d.full_window) return false;
+    return true;
+}
+
 af_status loss_passes(const af_plan* p, const void* s, const af_loss_params* lp, float* mag, bool want_grad,
                       const WsView& v, hipStream_t st, int only_class = -1) {
     AfArgs a = base_args(p, s, v);
@@ -417,6 +452,7 @@ af_status loss_passes(const af_plan* p, const void* s, const af_loss_params* lp,
     a.mag = mag;
     if (!want_grad) return launch(p, graf::MODE_FWD, a, st, only_class);
     if (lp->w_psl == 0.f) return launch(p, graf::MODE_FUSED_ISL, a, st, only_class);
+    if (fused_loss_ok(p, lp)) return launch(p, graf::MODE_LOSS, a, st, only_class);
     a.ystore = v.store;
     af_status rc = launch(p, graf::MODE_FWD, a, st, only_class);
     if (rc != AF_OK) return rc;
@@ -473,6 +509,7 @@ af_status af_plan_create(int32_t batch, const af_wave* waves, const af_plan_opts
     p->store_mode = opts->store_mode;
     p->budget = opts->budget_bytes;
     p->seg_iters_opt = opts->segment_iters;
+    p->loss_passes_opt = opts->loss_passes;
     p->log2_mmax = ilog2(mmax);
 
     // twiddles exp(-j 2 pi i / MMAX), computed in double, rounded once
@@ -575,6 +612,7 @@ af_status af_loss(const af_plan* p, const void* s, const af_loss_params* lp, flo
     r.grad = (float2*)grad_s;
     r.terms = terms;
     r.skip_slabs = grad_s ? 0 : 1;
+    r.psl_scaled = grad_s != nullptr && fused_loss_ok(p, lp);
     return graf::launch_reduce(r, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
 }
 
@@ -594,13 +632,15 @@ af_status af_loss_stage(const af_plan* p, int32_t stage, const void* s, const af
     a.band_w = lp->band_w;
     a.mag = mag;
     const bool fused = lp->w_psl == 0.f && grad_s != nullptr;
+    const bool fused_loss = grad_s != nullptr && fused_loss_ok(p, lp);
     switch (stage) {
         case 0:
             if (fused) return launch(p, graf::MODE_FUSED_ISL, a, st);
+            if (fused_loss) return launch(p, graf::MODE_LOSS, a, st);
             a.ystore = grad_s ? v.store : nullptr;
             return launch(p, graf::MODE_FWD, a, st);
         case 1:
-            if (fused || !grad_s) return AF_OK;
+            if (fused || fused_loss || !grad_s) return AF_OK;
             a.mag = nullptr;
             a.ystore = v.store;
             a.load_store = v.store != nullptr;
@@ -615,6 +655,7 @@ af_status af_loss_stage(const af_plan* p, int32_t stage, const void* s, const af
             r.grad = (float2*)grad_s;
             r.terms = terms;
             r.skip_slabs = grad_s ? 0 : 1;
+            r.psl_scaled = grad_s != nullptr && fused_loss_ok(p, lp);
             return graf::launch_reduce(r, st) == hipSuccess ? AF_OK : AF_ERR_HIP;
         }
     }
@@ -651,6 +692,7 @@ af_status af_optim_step(const af_plan* p, float* phi, float* adam_m, float* adam
     r.adam_v = adam_v;
     r.s_next = (float2*)s;
     r.step = step;
+    r.psl_scaled = fused_loss_ok(p, lp);
     r.lr = ad->lr;
     r.beta1 = ad->beta1;
     r.beta2 = ad->beta2;

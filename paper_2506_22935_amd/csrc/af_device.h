@@ -28,6 +28,69 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float cabs2(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
 
+// ------------------------------------------------ wavefront reductions --
+// Lane exchange through DPP: quad permutations and row rotations act inside
+// rows of 16 lanes; the four row sums are then read out lane by lane.  The
+// additions run in a fixed order, and every lane receives the same total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowRor4 = 0x124;
+constexpr int kDppRowRor8 = 0x128;
+
+__device__ __forceinline__ float wave_allsum(float v) {
+    v += dpp_f<kDppQuadXor1>(v);
+    v += dpp_f<kDppQuadXor2>(v);
+    v += dpp_f<kDppRowRor4>(v);
+    v += dpp_f<kDppRowRor8>(v);
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+__device__ __forceinline__ double wave_allsum(double v) {
+    v += dpp_d<kDppQuadXor1>(v);
+    v += dpp_d<kDppQuadXor2>(v);
+    v += dpp_d<kDppRowRor4>(v);
+    v += dpp_d<kDppRowRor8>(v);
+    auto lane = [&](int src) {
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), src),
+                                __builtin_amdgcn_readlane(__double2loint(v), src));
+    };
+    return (lane(0) + lane(16)) + (lane(32) + lane(48));
+}
+
+__device__ __forceinline__ float wave_allmax(float v) {
+    v = fmaxf(v, dpp_f<kDppQuadXor1>(v));
+    v = fmaxf(v, dpp_f<kDppQuadXor2>(v));
+    v = fmaxf(v, dpp_f<kDppRowRor4>(v));
+    v = fmaxf(v, dpp_f<kDppRowRor8>(v));
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
+}
+
+// Log-sum-exp pairs (m, s) = (max, sum of exp2((x - m) k)) over a wavefront:
+// the common maximum first, then one rescale per lane and a plain sum.
+__device__ __forceinline__ void wave_lse_pair(float& m, double& s, float k) {
+    const float mw = wave_allmax(m);
+    s = (m == -INFINITY) ? 0.0 : s * (double)exp2f((m - mw) * k);
+    s = wave_allsum(s);
+    m = mw;
+}
+
 // ------------------------------------------------- compile-time twiddles --
 // cos / sin of 2*pi*k/R in double precision, reduced to the first octant and
 // evaluated with a Taylor series (error far below float rounding).

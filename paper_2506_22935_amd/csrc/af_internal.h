@@ -18,6 +18,8 @@ struct WaveDesc {
     int band_off;             // first of its 62 shaping weights, or -1
     int full_window;          // T = N - 1: with uniform ISL weights the ISL is
                               // taken as M - (mainlobe power), Moyal's identity
+    int isl_segs;             // its segments that hold mainlobe lags (tau <= h_tau)
+    int64_t slab2_off;        // first complex64 of their second slabs
 };
 
 // One work item: lags [tau_begin, tau_end) (tau >= 0) of one waveform.
@@ -41,8 +43,12 @@ enum Mode : int {
     MODE_FWD = 0,       // spectra -> magnitude / AF / stored spectra / loss parts
     MODE_BWD_MAG = 1,   // upstream dL/da grid -> gradient slabs
     MODE_BWD_LOSS = 2,  // ISL + soft-PSL loss -> gradient slabs (needs MODE_FWD parts)
-    MODE_FUSED_ISL = 3  // ISL loss forward and backward in one pass
+    MODE_FUSED_ISL = 3, // ISL loss forward and backward in one pass
+    MODE_LOSS = 4       // ISL (mainlobe complement) + soft-PSL (fixed shift) loss,
+                        // forward and backward in one pass; the soft-PSL
+                        // gradient is left unnormalised for the reduction
 };
+constexpr int kNumModes = 5;
 
 struct AfArgs {
     WaveDesc w0;          // the waveform of a one-waveform class (single != 0)
@@ -64,6 +70,7 @@ struct AfArgs {
     const float* grad_mag;  // [grid] (MODE_BWD_MAG)
     Part* parts;          // [records]
     float2* slabs;        // [sum segs*N]
+    float2* slabs2;       // [sum isl_segs*N] ISL part of MODE_LOSS
     float* energy;        // [B], written by the segment holding lag 0
 };
 
@@ -72,11 +79,23 @@ struct AfArgs {
 // interleaved subgroups and add the subgroup sums in a fixed order
 // (deterministic, no atomics).  sg_log is 2 or 4, picked by the planner.
 
+// One block of the gradient reduction: samples [p0, p0 + 256 >> sg_log) of
+// waveform `wave`, with that waveform's descriptor alongside so that a block
+// needs one load before its data loads.
+struct RBlock {
+    WaveDesc w;
+    int wave, p0;
+};
+
 struct ReduceArgs {
     const float2* s;
-    const WaveDesc* waves;
-    const int2* blocks;   // (wave, first sample) per block
+    const RBlock* blocks;
     int n_blocks;
+    WaveDesc w0;          // one-waveform plans: blocks are implicit (single != 0)
+    int single;
+    int psl_scaled;       // slabs and dL/dE records carry the soft-PSL part
+                          // without 1/S (MODE_LOSS); the ISL part is in slabs2
+    const float2* slabs2;
     int sg_log;           // log2 of the slab subgroups per block
     const Part* parts;
     const float2* slabs;

@@ -10,6 +10,10 @@ namespace graf {
 constexpr float kLog2eR = 1.4426950408889634f;
 
 __device__ __forceinline__ void lse_merge_r(float& m, double& s, float m2, double s2, float inv_t2) {
+    if (m2 == m) {  // same shift: a plain sum
+        s += s2;
+        return;
+    }
     float mn = fmaxf(m, m2);
     if (mn == -INFINITY) return;
     s = s * (double)exp2f((m - mn) * inv_t2) + s2 * (double)exp2f((m2 - mn) * inv_t2);
@@ -17,20 +21,9 @@ __device__ __forceinline__ void lse_merge_r(float& m, double& s, float m2, doubl
 }
 
 // --------------------------------------------------------------- reduce --
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_sum_d(double v) { return wave_allsum(v); }
 
-__device__ __forceinline__ void wave_lse_r(float& m, double& s, float inv_t2) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const float m2 = __shfl_xor(m, o, 64);
-        const double s2 = __shfl_xor(s, o, 64);
-        lse_merge_r(m, s, m2, s2, inv_t2);
-    }
-}
+__device__ __forceinline__ void wave_lse_r(float& m, double& s, float inv_t2) { wave_lse_pair(m, s, inv_t2); }
 
 struct WaveTotals {
     double isl_raw, lse_s, dle;
@@ -73,23 +66,35 @@ __device__ WaveTotals wave_totals(const ReduceArgs& a, const WaveDesc& w, double
 // Sum over the waveform's slabs for this block's samples: thread t adds
 // slabs t>>pb_log, (t>>pb_log) + SG, ... of sample t & (PB-1); the SG
 // subgroup sums meet in LDS and are added in subgroup order.
-__device__ __forceinline__ float2 slab_sum(const ReduceArgs& a, const WaveDesc& w, int p, float2* sh2) {
+// The first U slabs of every thread are loaded before the segment records are
+// merged (slab_first), so both memory round trips overlap; slab_sum adds them
+// and any further slabs in the same order.
+constexpr int kSlabU = 32;
+struct SlabFirst {
+    float2 x[kSlabU];
+};
+__device__ __forceinline__ void slab_first(const ReduceArgs& a, const WaveDesc& w, int p, SlabFirst& f) {
+    const int sub = threadIdx.x >> (8 - a.sg_log);
+    const int SG = 1 << a.sg_log;
+    const bool ok = !a.skip_slabs && p < w.n;
+    const float2* sl = a.slabs + w.slab_off + p;
+#pragma unroll
+    for (int u = 0; u < kSlabU; ++u) {
+        const int j = sub + u * SG;
+        f.x[u] = (ok && j < w.seg_count) ? sl[(int64_t)j * w.n] : make_float2(0.f, 0.f);
+    }
+}
+__device__ __forceinline__ float2 slab_sum(const ReduceArgs& a, const WaveDesc& w, int p, const SlabFirst& f,
+                                           float2* sh2) {
     const int pb_log = 8 - a.sg_log;
     const int sub = threadIdx.x >> pb_log;
     const int SG = 1 << a.sg_log;
-    constexpr int U = 8;  // slab loads in flight per thread
     float2 sum = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < kSlabU; ++u) sum = cadd(sum, f.x[u]);
     if (!a.skip_slabs && p < w.n) {
         const float2* sl = a.slabs + w.slab_off + p;
-        int j = sub;
-        for (; j + (U - 1) * SG < w.seg_count; j += U * SG) {
-            float2 x[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) x[u] = sl[(int64_t)(j + u * SG) * w.n];
-#pragma unroll
-            for (int u = 0; u < U; ++u) sum = cadd(sum, x[u]);
-        }
-        for (; j < w.seg_count; j += SG) sum = cadd(sum, sl[(int64_t)j * w.n]);
+        for (int j = sub + kSlabU * SG; j < w.seg_count; j += SG) sum = cadd(sum, sl[(int64_t)j * w.n]);
     }
     sh2[threadIdx.x] = sum;
     __syncthreads();
@@ -101,37 +106,74 @@ __device__ __forceinline__ float2 slab_sum(const ReduceArgs& a, const WaveDesc& 
     return g;
 }
 
-// loss terms and dL/dE from the totals
-__device__ __forceinline__ void finish_terms(const ReduceArgs& a, const WaveDesc& w, const WaveTotals& t, float E,
-                                             float& dLdE, float4& terms) {
+// dL/dE from the totals: the ISL part is -2 w_isl (collected sum) / E in
+// both forms
+__device__ __forceinline__ float total_dlde(const ReduceArgs& a, const WaveTotals& t, float E) {
+    return (float)(-2.0 * (double)a.w_isl * t.isl_raw / (double)E + t.dle);
+}
+// the loss terms (one thread per waveform writes them)
+__device__ __forceinline__ float4 loss_terms(const ReduceArgs& a, const WaveDesc& w, const WaveTotals& t, float E) {
     // complement waveforms carry ISL - M (Moyal: the full grid holds M E^2)
     const double isl = t.isl_raw + ((a.uniform_w && w.full_window) ? (double)w.m : 0.0);
     const float soft = (t.lse_s > 0.0) ? (float)((double)t.lse_m + (double)a.temp * log(t.lse_s)) : 0.f;
     const double loss = (double)a.w_isl * isl + (a.w_psl != 0.f ? (double)a.w_psl * (double)soft : 0.0);
-    // dL/dE of the ISL part is -2 w_isl (collected sum) / E in both forms
-    dLdE = (float)(-2.0 * (double)a.w_isl * t.isl_raw / (double)E + t.dle);
-    terms = make_float4((float)loss, (float)isl, soft, E);
+    return make_float4((float)loss, (float)isl, soft, E);
+}
+
+// Sum of a waveform's second slabs (fused loss pass: the ISL part of the
+// segments that hold mainlobe lags) at sample p, in segment order.
+__device__ __forceinline__ float2 second_slabs(const ReduceArgs& a, const WaveDesc& w, int p) {
+    float2 sum = make_float2(0.f, 0.f);
+    const float2* sl = a.slabs2 + w.slab2_off + p;
+    for (int j = 0; j < w.isl_segs; ++j) sum = cadd(sum, sl[(int64_t)j * w.n]);
+    return sum;
+}
+
+__device__ __forceinline__ RBlock reduce_block(const ReduceArgs& a) {
+    RBlock b;
+    if (a.single) {
+        b.w = a.w0;
+        b.wave = 0;
+        b.p0 = (int)blockIdx.x * (256 >> a.sg_log);
+    } else {
+        b = a.blocks[blockIdx.x];
+    }
+    return b;
 }
 
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
     __shared__ double sh[16];
     __shared__ float2 sh2[256];
-    const int2 d = a.blocks[blockIdx.x];
-    const WaveDesc w = a.waves[d.x];
-    const int p = d.y + (int)(threadIdx.x & ((256 >> a.sg_log) - 1));
+    const RBlock b = reduce_block(a);
+    const WaveDesc& w = b.w;
+    const int p = b.p0 + (int)(threadIdx.x & ((256 >> a.sg_log) - 1));
+    const bool mine = (int)threadIdx.x < (256 >> a.sg_log) && p < w.n;
+    // every load this block needs goes out before the first reduction
+    const float E = a.energy[b.wave];
+    const float2 sp = mine ? a.s[w.s_off + p] : make_float2(0.f, 0.f);
+    SlabFirst f;
+    slab_first(a, w, p, f);
+    const bool isl2 = a.psl_scaled && a.uniform_w && w.full_window && a.w_isl != 0.f && mine;
+    const float2 s2 = isl2 ? second_slabs(a, w, p) : make_float2(0.f, 0.f);
     const WaveTotals tt = wave_totals(a, w, sh);
-    float2 g = slab_sum(a, w, p, sh2);
-    const float E = a.energy[d.x];
+    float2 g = slab_sum(a, w, p, f, sh2);
     float dLdE;
-    float4 terms;
-    finish_terms(a, w, tt, E, dLdE, terms);
-    if ((int)threadIdx.x < (256 >> a.sg_log) && p < w.n && a.grad) {
-        const float2 sp = a.s[w.s_off + p];
+    if (a.psl_scaled) {
+        // fused loss pass: main slabs and dL/dE records carry the soft-PSL
+        // part without 1/S; the mainlobe ISL part sits in the second slabs
+        const double inv_s = tt.lse_s > 0.0 ? 1.0 / tt.lse_s : 0.0;
+        g.x = fmaf((float)inv_s, g.x, s2.x);
+        g.y = fmaf((float)inv_s, g.y, s2.y);
+        dLdE = (float)(-2.0 * (double)a.w_isl * tt.isl_raw / (double)E + tt.dle * inv_s);
+    } else {
+        dLdE = total_dlde(a, tt, E);
+    }
+    if (mine && a.grad) {
         g.x = fmaf(dLdE, sp.x, g.x);
         g.y = fmaf(dLdE, sp.y, g.y);
         a.grad[w.s_off + p] = g;
     }
-    if (d.y == 0 && threadIdx.x == 0 && a.terms) reinterpret_cast<float4*>(a.terms)[d.x] = terms;
+    if (b.p0 == 0 && threadIdx.x == 0 && a.terms) reinterpret_cast<float4*>(a.terms)[b.wave] = loss_terms(a, w, tt, E);
 }
 
 // Reduce, then one Adam step on the phases of s = exp(j phi) (Sec. 6.2's
@@ -140,28 +182,48 @@ __global__ __launch_bounds__(256) void reduce_adam_kernel(ReduceArgs a) {
     __shared__ double sh[16];
     __shared__ float2 sh2[256];
     const int t_prev = *a.step;  // read before this block signals completion
-    const int2 d = a.blocks[blockIdx.x];
-    const WaveDesc w = a.waves[d.x];
-    const int p = d.y + (int)(threadIdx.x & ((256 >> a.sg_log) - 1));
+    const RBlock b = reduce_block(a);
+    const WaveDesc& w = b.w;
+    const int p = b.p0 + (int)(threadIdx.x & ((256 >> a.sg_log) - 1));
+    const bool mine = (int)threadIdx.x < (256 >> a.sg_log) && p < w.n;
+    const int64_t i = w.s_off + (mine ? p : 0);
+    // every load this block needs goes out before the first reduction
+    const float E = a.energy[b.wave];
+    float2 sp = make_float2(0.f, 0.f);
+    float m = 0.f, v = 0.f, ph0 = 0.f;
+    if (mine) {
+        sp = a.s[i];
+        m = a.adam_m[i];
+        v = a.adam_v[i];
+        ph0 = a.phi[i];
+    }
+    SlabFirst f;
+    slab_first(a, w, p, f);
+    const bool isl2 = a.psl_scaled && a.uniform_w && w.full_window && a.w_isl != 0.f && mine;
+    const float2 s2 = isl2 ? second_slabs(a, w, p) : make_float2(0.f, 0.f);
     const WaveTotals tt = wave_totals(a, w, sh);
-    float2 g = slab_sum(a, w, p, sh2);
-    const float E = a.energy[d.x];
+    float2 g = slab_sum(a, w, p, f, sh2);
     float dLdE;
-    float4 terms;
-    finish_terms(a, w, tt, E, dLdE, terms);
-    if ((int)threadIdx.x < (256 >> a.sg_log) && p < w.n) {
-        const int64_t i = w.s_off + p;
-        const float2 sp = a.s[i];
+    if (a.psl_scaled) {
+        // fused loss pass: main slabs and dL/dE records carry the soft-PSL
+        // part without 1/S; the mainlobe ISL part sits in the second slabs
+        const double inv_s = tt.lse_s > 0.0 ? 1.0 / tt.lse_s : 0.0;
+        g.x = fmaf((float)inv_s, g.x, s2.x);
+        g.y = fmaf((float)inv_s, g.y, s2.y);
+        dLdE = (float)(-2.0 * (double)a.w_isl * tt.isl_raw / (double)E + tt.dle * inv_s);
+    } else {
+        dLdE = total_dlde(a, tt, E);
+    }
+    if (mine) {
         g.x = fmaf(dLdE, sp.x, g.x);
         g.y = fmaf(dLdE, sp.y, g.y);
         const float dphi = 2.f * (sp.x * g.y - sp.y * g.x);
         const float t = (float)(t_prev + 1);
-        float m = a.adam_m[i], v = a.adam_v[i];
         m = fmaf(a.beta1, m, (1.f - a.beta1) * dphi);
         v = fmaf(a.beta2, v, (1.f - a.beta2) * dphi * dphi);
         const float mh = m / (1.f - powf(a.beta1, t));
         const float vh = v / (1.f - powf(a.beta2, t));
-        const float ph = a.phi[i] - a.lr * mh / (sqrtf(vh) + a.adam_eps);
+        const float ph = ph0 - a.lr * mh / (sqrtf(vh) + a.adam_eps);
         a.adam_m[i] = m;
         a.adam_v[i] = v;
         a.phi[i] = ph;
@@ -169,7 +231,7 @@ __global__ __launch_bounds__(256) void reduce_adam_kernel(ReduceArgs a) {
         sincosf(ph, &sn, &cs);
         a.s_next[i] = make_float2(cs, sn);
     }
-    if (d.y == 0 && threadIdx.x == 0 && a.terms) reinterpret_cast<float4*>(a.terms)[d.x] = terms;
+    if (b.p0 == 0 && threadIdx.x == 0 && a.terms) reinterpret_cast<float4*>(a.terms)[b.wave] = loss_terms(a, w, tt, E);
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();

@@ -50,33 +50,22 @@ __device__ __forceinline__ bool lse_fixed_shift(float eps, float inv_t2) { retur
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // ----------------------------------------------------------- reductions --
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ __forceinline__ float wave_sum(float v) { return wave_allsum(v); }
+__device__ __forceinline__ double wave_sum(double v) { return wave_allsum(v); }
 
 // log-sum-exp pair (max, sum of exp((x - max)/T)) merge; inv_t2 = log2(e)/T
 __device__ __forceinline__ void lse_merge(float& m, double& s, float m2, double s2, float inv_t2) {
+    if (m2 == m) {  // same shift (always so with the fixed shift): a plain sum
+        s += s2;
+        return;
+    }
     float mn = fmaxf(m, m2);
     if (mn == -INFINITY) return;
     s = s * (double)exp2f((m - mn) * inv_t2) + s2 * (double)exp2f((m2 - mn) * inv_t2);
     m = mn;
 }
 
-__device__ __forceinline__ void wave_lse(float& m, double& s, float inv_t2) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        float m2 = __shfl_xor(m, o, 64);
-        double s2 = __shfl_xor(s, o, 64);
-        lse_merge(m, s, m2, s2, inv_t2);
-    }
-}
+__device__ __forceinline__ void wave_lse(float& m, double& s, float inv_t2) { wave_lse_pair(m, s, inv_t2); }
 
 // Sum over the work group in a fixed order: wavefront butterflies, then the
 // per-wave results in wave order.  Every thread receives the total.
@@ -265,7 +254,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     constexpr int TPL = SPLIT ? 2 * L : L;  // threads per lag
     constexpr int M_ = 2 * MH;
     constexpr bool NEEDS_INV = MODE != MODE_FWD;
-    constexpr bool HAS_MAG_OUT = MODE == MODE_FWD || MODE == MODE_FUSED_ISL;
+    constexpr bool HAS_MAG_OUT = MODE == MODE_FWD || MODE == MODE_FUSED_ISL || MODE == MODE_LOSS;
+    constexpr bool FWD_SUMS = MODE == MODE_FWD || MODE == MODE_LOSS;  // soft-PSL partials
     static_assert(L >= 1 && G >= (SPLIT ? 2 : 1), "group does not fit the work group");
     static_assert(!SPLIT || (2 * BUF * 2 >= 2 * M_), "row staging does not fit");
 
@@ -303,7 +293,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const float invE2 = invE * invE;
     const float2* __restrict__ sv = s_in_lds ? s_lds : sg_s;
     const float inv_t2 = kLog2e / a.temp;
-    const bool want_lse = MODE == MODE_FWD && a.w_psl != 0.f;
+    const bool want_lse = FWD_SUMS && a.w_psl != 0.f;
     const bool lse_fixed = lse_fixed_shift(a.eps, inv_t2);
     const float aref_t2 = lse_ref(a.eps) * inv_t2;
     const float glob_m = ws.glob_m, glob_inv_s = ws.glob_inv_s;
@@ -325,13 +315,14 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
     // lag-product adjoint of lag tj from Q' in LDS (qa, plus qa + BUF when the
     // two halves sit in two buffers)
-    auto gather = [&](const float2* qa, bool two, int tj) {
+    // (gdst != nullptr: accumulate into gdst[p] instead)
+    auto gather = [&](const float2* qa, bool two, int tj, float2* gdst) {
         const int Sj = N - tj;
 #pragma unroll
         for (int i = 0; i < NACC; ++i) {
             const int p = tid + WGS * i;
             if (p < N) {
-                float2 sum = GACC ? slab[p] : acc[GACC ? 0 : i];
+                float2 sum = gdst ? gdst[p] : (GACC ? slab[p] : acc[GACC ? 0 : i]);
                 if (p < Sj) {
                     float2 Q = qa[lds_index(p)];
                     if (two) Q = cadd(Q, qa[BUF + lds_index(p)]);
@@ -343,7 +334,9 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     if (two) Q = cadd(Q, qa[BUF + lds_index(m)]);
                     sum = cadd(sum, cmul(Q, sv[m]));
                 }
-                if (GACC)
+                if (gdst)
+                    gdst[p] = sum;
+                else if (GACC)
                     slab[p] = sum;
                 else
                     acc[GACC ? 0 : i] = sum;
@@ -351,14 +344,69 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         }
     };
     const bool compl_isl = a.band_w == nullptr && w.full_window != 0;
+    // MODE_LOSS: the ISL gradient lives on the mainlobe cells (complement
+    // form); segments holding mainlobe lags collect it in their second slab
+    const bool isl_seg = MODE == MODE_LOSS && compl_isl && a.w_isl != 0.f && sg.tau_begin <= w.h_tau;
+    float2* const slab2 = isl_seg ? a.slabs2 + w.slab2_off + (int64_t)(sg.rec - w.seg_begin) * N : nullptr;
+    if (isl_seg) {
+        for (int p = tid; p < N; p += WGS) slab2[p] = make_float2(0.f, 0.f);
+    }
     double isl = 0.0, ls = 0.0, dle = 0.0;
-    float lm = (want_lse && lse_fixed) ? lse_ref(a.eps) : -INFINITY;
+    float lm = (want_lse && (lse_fixed || MODE == MODE_LOSS)) ? lse_ref(a.eps) : -INFINITY;
+
+    // Y' of lag tau, half h, in the exit layout v[q] = Y'[2 (l + qL) + h]
+    auto lag_spectrum = [&](float2* v, int h, int tau, bool active) {
+        const int S = N - tau;
+        if (s_in_lds) {
+            // zero-padded samples: r'[m] = 0 for m >= N - tau comes out of
+            // the product itself; an inactive lag reads zeros
+            const int tz = active ? tau : N;
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                const int m = l + r * L;
+                float2 x = cmulc(sv[m + tz], sv[m]);
+                if (h) x = cmul(x, twl[m << twsh]);
+                v[r] = x;
+                if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                const int m = l + r * L;
+                float2 x = make_float2(0.f, 0.f);
+                if (active && m < S) {
+                    x = cmulc(sv[m + tau], sv[m]);
+                    if (h) x = cmul(x, twl[m << twsh]);
+                }
+                v[r] = x;
+                // bound how many loads the scheduler keeps in flight
+                if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        fft_group<MH, P, -1>(v, buf, l, twl, tw_mh, sync);
+    };
+    // Q' of half h: inverse transform, w_M^{-m} on the odd half, stored to
+    // this group's buffer in natural order
+    auto inverse_to_lds = [&](float2* v, int h) {
+        fft_group<MH, P, +1>(v, buf, l, twl, tw_mh, sync);
+        if (h) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl[(l + q * L) << twsh]);
+        }
+        if constexpr (L % 32 == 0) {
+            const int bi = lds_index(l);
+#pragma unroll
+            for (int q = 0; q < P; ++q) buf[bi + lds_off(q * L)] = v[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < P; ++q) buf[lds_index(l + q * L)] = v[q];
+        }
+    };
 
     for (int t0 = sg.tau_begin; t0 < sg.tau_end; t0 += LPI) {
         // lane groups of whole wavefronts: the lag is wave-uniform
         const int tau = (L % 64 == 0) ? __builtin_amdgcn_readfirstlane(t0 + lam) : t0 + lam;
         const bool active = tau < sg.tau_end;
-        const int S = N - tau;
         const float mult = tau > 0 ? 2.f : 1.f;
         const bool main_tau = tau <= w.h_tau;
         const float wu = (banded && active) ? bu[(31 * tau) / N] : 1.f;
@@ -389,33 +437,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 #pragma unroll
                 for (int q = 0; q < P; ++q) v[q] = active ? ys[l + q * L] : make_float2(0.f, 0.f);
             } else {
-                if (s_in_lds) {
-                    // zero-padded samples: r'[m] = 0 for m >= N - tau comes
-                    // out of the product itself; an inactive lag reads zeros
-                    const int tz = active ? tau : N;
-#pragma unroll
-                    for (int r = 0; r < P; ++r) {
-                        const int m = l + r * L;
-                        float2 x = cmulc(sv[m + tz], sv[m]);
-                        if (h) x = cmul(x, twl[m << twsh]);
-                        v[r] = x;
-                        if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-                    }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < P; ++r) {
-                        const int m = l + r * L;
-                        float2 x = make_float2(0.f, 0.f);
-                        if (active && m < S) {
-                            x = cmulc(sv[m + tau], sv[m]);
-                            if (h) x = cmul(x, twl[m << twsh]);
-                        }
-                        v[r] = x;
-                        // bound how many loads the scheduler keeps in flight
-                        if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-                    }
-                }
-                fft_group<MH, P, -1>(v, buf, l, twl, tw_mh, sync);
+                lag_spectrum(v, h, tau, active);
             }
             // v[q] = Y'[2 (l + qL) + h]
             if (MODE == MODE_FWD && a.ystore && active) {
@@ -477,9 +499,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         else
                             isl_f = fmaf(sd ? wt : 0.f, pw, isl_f);
                     }
-                    if constexpr (MODE == MODE_FWD && PSL) {
+                    // exp((a - a_ref)/T): the fixed-shift soft-PSL term
+                    const float e = (FWD_SUMS && PSL && FIXED) ? fast_exp2(fmaf(av, inv_t2, -aref_t2)) : 0.f;
+                    if constexpr (FWD_SUMS && PSL) {
                         if constexpr (FIXED) {
-                            sl_f += sd ? fast_exp2(fmaf(av, inv_t2, -aref_t2)) : 0.f;
+                            sl_f += sd ? e : 0.f;
                         } else {
                             avs[q] = sd ? av : -INFINITY;
                             mloc = fmaxf(mloc, avs[q]);
@@ -509,6 +533,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                                 dle_f = fmaf(sd ? -a.w_psl * qq * pw * invE : 0.f, ia, dle_f);
                             }
                             c = sd ? mult * cs : ((COMPL && main_cell) ? c_main : 0.f);
+                        } else if constexpr (MODE == MODE_LOSS) {
+                            // soft-PSL part without the normaliser 1/S
+                            const float ia = __builtin_amdgcn_rcpf(av);
+                            c = sd ? mult * a.w_psl * e * 0.5f * invE2 * ia : 0.f;
+                            dle_f = fmaf(sd ? -a.w_psl * e * pw * invE : 0.f, ia, dle_f);
                         } else {  // MODE_FUSED_ISL
                             if constexpr (COMPL)
                                 c = main_cell ? c_main : 0.f;
@@ -543,12 +572,17 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     by_loss(T_{}, F_{});
             } else if constexpr (MODE == MODE_BWD_MAG) {
                 epilogue(T_{}, F_{}, F_{}, F_{});
+            } else if constexpr (MODE == MODE_LOSS) {
+                if (compl_isl)
+                    epilogue(T_{}, F_{}, T_{}, T_{});
+                else
+                    epilogue(T_{}, F_{}, F_{}, T_{});
             } else {
                 by_loss(T_{}, F_{});
             }
             isl += (double)(mult * isl_f);
             dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f);
-            if (MODE == MODE_FWD && want_lse && lse_fixed) {
+            if (FWD_SUMS && want_lse && (lse_fixed || MODE == MODE_LOSS)) {
                 ls += (double)(mult * sl_f);
             } else if (MODE == MODE_FWD && want_lse && mloc > -INFINITY) {
                 // this iteration's sidelobe cells, two per bin for tau > 0
@@ -605,26 +639,13 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             }
 
             if constexpr (NEEDS_INV) {
-                fft_group<MH, P, +1>(v, buf, l, twl, tw_mh, sync);
-                // v[q] = IDFT_{MH}(H_h)[l + qL]; the odd half gets w_M^{-m}
-                if (h) {
-#pragma unroll
-                    for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl[(l + q * L) << twsh]);
-                }
-                if constexpr (L % 32 == 0) {
-                    const int bi = lds_index(l);
-#pragma unroll
-                    for (int q = 0; q < P; ++q) buf[bi + lds_off(q * L)] = v[q];
-                } else {
-#pragma unroll
-                    for (int q = 0; q < P; ++q) buf[lds_index(l + q * L)] = v[q];
-                }
+                inverse_to_lds(v, h);
                 if constexpr (!SPLIT) {
                     // halves in turn: this half's share of every lag's adjoint
                     __syncthreads();
                     for (int j = 0; j < LPI; ++j) {
                         if (t0 + j >= sg.tau_end) break;
-                        gather(lds + j * BUF, false, t0 + j);
+                        gather(lds + j * BUF, false, t0 + j, nullptr);
                     }
                     __syncthreads();
                 }
@@ -636,22 +657,46 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // lag-product adjoint for every lag of this iteration
             for (int j = 0; j < LPI; ++j) {
                 if (t0 + j >= sg.tau_end) break;
-                gather(lds + 2 * j * BUF, true, t0 + j);
+                gather(lds + 2 * j * BUF, true, t0 + j, nullptr);
             }
         }
         __syncthreads();
+        if constexpr (MODE == MODE_LOSS && SPLIT) {
+            if (isl_seg && t0 <= w.h_tau) {
+                // ISL part of the mainlobe lags: the spectrum again, times
+                // d(M - mainlobe power)/d conj(chi) = -w_isl/E^2 on mainlobe
+                // cells (both signs of tau for tau > 0), into the second slab
+                float2 v[P];
+                lag_spectrum(v, hsel, tau, active);
+                const float c_main = -mult * a.w_isl * invE2;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int k = 2 * (l + q * L) + hsel;
+                    const int kc = k < (M >> 1) ? k : M - k;
+                    const bool main_cell = active && main_tau && kc <= w.h_k;
+                    v[q] = cscale(v[q], main_cell ? c_main : 0.f);
+                }
+                inverse_to_lds(v, hsel);
+                __syncthreads();
+                for (int j = 0; j < LPI; ++j) {
+                    if (t0 + j >= sg.tau_end) break;
+                    gather(lds + 2 * j * BUF, true, t0 + j, slab2);
+                }
+                __syncthreads();
+            }
+        }
     }
 
     // ------------------------------------------- segment results -------
     // one fixed-order reduction of (ISL, soft-PSL pair, dL/dE) over the group
-    if (MODE == MODE_FWD) {
-        if (lse_fixed)
+    if (FWD_SUMS) {
+        if (lse_fixed || MODE == MODE_LOSS)
             ls = wave_sum(ls);
         else
             wave_lse(lm, ls, inv_t2);
     }
     isl = wave_sum(isl);
-    dle = wave_sum(dle);
+    if (MODE != MODE_FWD) dle = wave_sum(dle);
     __syncthreads();
     if ((tid & 63) == 0) {
         scratch[4 * (tid >> 6) + 0] = isl;
@@ -669,7 +714,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         pr.pad = 0.f;
         for (int i = 0; i < WGS / 64; ++i) {
             pr.isl += scratch[4 * i + 0];
-            if (MODE == MODE_FWD) lse_merge(pr.lse_m, pr.lse_s, (float)scratch[4 * i + 1], scratch[4 * i + 2], inv_t2);
+            if (FWD_SUMS) lse_merge(pr.lse_m, pr.lse_s, (float)scratch[4 * i + 1], scratch[4 * i + 2], inv_t2);
             pr.dle += scratch[4 * i + 3];
         }
         if (MODE == MODE_BWD_LOSS)

@@ -31,6 +31,7 @@ void* GRAF_CAT(variant_kernel_, GRAF_VARIANT)(int mode, int lg) {
         case MODE_BWD_MAG: return pick_lg<MODE_BWD_MAG, 1>(lg);
         case MODE_BWD_LOSS: return pick_lg<MODE_BWD_LOSS, 1>(lg);
         case MODE_FUSED_ISL: return pick_lg<MODE_FUSED_ISL, 1>(lg);
+        case MODE_LOSS: return pick_lg<MODE_LOSS, 1>(lg);
     }
     return nullptr;
 }

@@ -186,10 +186,13 @@ def softpsl_fp32_floor(s, m, T, lp, seed=0):
 
 @pytest.mark.parametrize("n,m", [(64, 128), (1024, 2048), (333, 1024)])
 @pytest.mark.parametrize("lp", LOSSES)
-def test_loss_and_grad(af, n, m, lp):
-    say("loss", n, m, lp)
+@pytest.mark.parametrize("passes", [0, 1])  # 0: one fused pass where allowed, 1: forward + backward
+def test_loss_and_grad(af, n, m, lp, passes):
+    if passes == 1 and not lp["w_psl"]:
+        pytest.skip("w_psl == 0 always runs the single fused ISL pass")
+    say("loss", n, m, lp, passes)
     s = W.random_code(n, seed=7 * n)
-    plan = af.Plan([n], [m], h_tau=1, h_k=1, eps=EPS)
+    plan = af.Plan([n], [m], h_tau=1, h_k=1, eps=EPS, loss_passes=passes)
     terms, g, _ = plan.loss(to_dev(s), grad=True, **lp)
     torch.cuda.synchronize()
     ref = O.loss_and_grad(ref_c64(s), m, n - 1, O.LossParams(h_tau=1, h_k=1, eps=EPS, **lp))
@@ -202,6 +205,62 @@ def test_loss_and_grad(af, n, m, lp):
     err = np.max(np.abs(g.cpu().numpy().astype(np.complex128) - ref["g"]))
     bar = max(TOL_G * np.max(np.abs(ref["g"])), 2.0 * floor)
     assert err <= bar, "loss grad err %.3e vs bar %.3e (floor %.3e)" % (err, bar, floor)
+
+
+def loss_vs_oracle(af, plan, codes, ms, Ts, lp, what):
+    """plan.loss against the oracle for every waveform of a packed batch."""
+    s = packed(codes)
+    terms, g, _ = plan.loss(s, grad=True, **lp)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.complex128)
+    t = terms.cpu().numpy()
+    for b, (code, m, T) in enumerate(zip(codes, ms, Ts)):
+        n = len(code)
+        sr = ref_c64(code)
+        ref = O.loss_and_grad(sr, m, T, O.LossParams(h_tau=1, h_k=1, eps=EPS, **lp))
+        assert abs(t[b, 0] - ref["loss"]) <= 1e-4 * abs(ref["loss"]) + 1e-6, "%s loss %d" % (what, b)
+        if lp["w_psl"]:
+            assert abs(t[b, 2] - ref["softpsl"]) <= 1e-5 * max(1.0, abs(ref["softpsl"])), "%s softpsl %d" % (what, b)
+        floor = softpsl_fp32_floor(sr, m, T, lp)
+        gb = g[plan.s_offsets[b]:plan.s_offsets[b] + n]
+        err = np.max(np.abs(gb - ref["g"]))
+        bar = max(TOL_G * np.max(np.abs(ref["g"])), 2.0 * floor)
+        assert err <= bar, "%s grad %d: err %.3e bar %.3e" % (what, b, err, bar)
+
+
+@pytest.mark.parametrize("passes", [0, 1])
+def test_isl_softpsl_uneven_batch(af, passes):
+    # ISL + soft-PSL over waveforms of several lengths and sizes: the fused
+    # pass (second slabs on the mainlobe lags of every waveform) and the
+    # forward + backward passes
+    say("isl+softpsl uneven", passes)
+    ns = [64, 100, 255, 256, 511, 700, 1023, 90]
+    ms = [W.next_pow2(2 * n) for n in ns]
+    ms[-1] = 4 * ms[-1]
+    codes = [W.random_code(n, seed=300 + i) for i, n in enumerate(ns)]
+    plan = af.Plan(ns, ms, eps=EPS, loss_passes=passes)
+    loss_vs_oracle(af, plan, codes, ms, [n - 1 for n in ns], dict(w_isl=1.0, w_psl=0.5, temp=0.05), "uneven")
+
+
+def test_softpsl_partial_window_fused(af):
+    # soft-PSL alone over a partial lag window: eligible for the fused pass
+    # (no ISL part), the grids hold 2T + 1 rows
+    say("softpsl partial window")
+    ns, Ts = [300, 512], [40, 200]
+    ms = [1024, 1024]
+    codes = [W.random_code(n, seed=400 + i) for i, n in enumerate(ns)]
+    plan = af.Plan(ns, ms, max_lags=Ts, eps=EPS)
+    loss_vs_oracle(af, plan, codes, ms, Ts, dict(w_isl=0.0, w_psl=1.0, temp=0.1), "partial")
+
+
+def test_small_temperature_uses_running_maximum(af):
+    # T = 0.01 is below the fixed-shift rule: forward + backward passes with
+    # per-iteration maxima
+    say("small temperature")
+    n, m = 128, 256
+    codes = [W.random_code(n, seed=501)]
+    plan = af.Plan([n], [m], eps=EPS)
+    loss_vs_oracle(af, plan, codes, [m], [n - 1], dict(w_isl=1.0, w_psl=1.0, temp=0.01), "small T")
 
 
 def test_weighted_isl_batch(af):
