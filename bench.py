@@ -63,6 +63,44 @@ def cpu_baseline_single(n, m, seed, budget_s=10.0):
                 sample="full %d-lag x %d-bin grid, loss + gradient %d times (%.1f s)" % (2 * n - 1, m, reps, dt))
 
 
+def source_digest():
+    """SHA-256 over the kernel sources and the public header: a profile's
+    counter figures describe the kernels only while this is unchanged."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2506_22935_amd", "csrc", "*.h")) +
+                   glob.glob(os.path.join(ROOT, "paper_2506_22935_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "include", "*.h")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(summary, variant):
+    """HBM bytes per launch of the dominant kernel from a committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    summary is missing, was taken for another variant, or the kernels changed
+    since."""
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("    ") and ":" in line:
+                k, v = line.strip().split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != source_digest() or kv.get("variant") != str(variant):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def fft_flops(n_transforms, m):
     """Algorithmic flops of n_transforms complex M-point transforms (5 M log2 M each)."""
     return 5.0 * m * math.log2(m) * n_transforms
@@ -76,7 +114,7 @@ def bench_single(args, torch):
     s = torch.from_numpy(W.random_code(n, seed=args.seed)).cuda()
     lp = dict(w_isl=1.0, w_psl=1.0, temp=0.05)
     results = {}
-    variants = [args.variant] if args.variant >= 0 else [0, 3, 4]
+    variants = [0, 3, 4] if args.sweep else [args.variant]
     for variant in variants:
         try:
             plan = af.Plan([n], [m], eps=1e-12, store_mode=2, variant=variant)
@@ -109,7 +147,8 @@ def bench_single(args, torch):
     flops = 2.0 * fft_flops(T + 1, m)
     ach = flops / (stage_ms[0] * 1e-3) / 1e12
     roof = dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
+                frac=round(ach / FP32_PEAK_TFLOPS, 4),
+                traffic=profiled_traffic("af_loss_fused_n1024_m2048.md", plan.summary()["variant"]),
                 kernel="fused loss pass (forward + backward transforms, a grid, loss partials)",
                 kernel_ms=round(stage_ms[0], 5), flops_per_launch=flops)
 
@@ -140,7 +179,8 @@ def bench_single(args, torch):
     out = dict(value=cells / (ms * 1e-3), ms_per_step=ms,
                config=dict(workload="single: N=1024 random-phase code, 2047 lags x M=2048, "
                                     "ISL(|tau|<=1,|k|<=1)+softPSL(T=0.05) fwd+bwd, a grid written",
-                           n=n, m=m, lags=2 * n - 1, cells=cells, variant=variant, path="fused loss pass + reduce",
+                           n=n, m=m, lags=2 * n - 1, cells=cells, variant=plan.summary()["variant"],
+                           path="fused loss pass + reduce",
                            stage_ms=dict(fused_pass=round(stage_ms[0], 5), reduce=round(stage_ms[1], 5)),
                            a_grid_hbm_gbs=round(hbm_step, 1), a_grid_hbm_frac=round(hbm_step / HBM_PEAK_GBS, 4),
                            materialised_fwd_bwd=mat),
@@ -344,7 +384,8 @@ def main():
     ap.add_argument("--workload", default="single", choices=sorted(WORKLOADS))
     ap.add_argument("--store", default="auto", choices=["auto", "store", "recompute"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: time the candidates)")
+    ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: the library's default)")
+    ap.add_argument("--sweep", action="store_true", help="single workload: time variants 0, 3, 4, report the best")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--train-steps", type=int, default=3000, help="proposal workload: network training steps")
     args = ap.parse_args()

@@ -315,14 +315,16 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
     // lag-product adjoint of lag tj from Q' in LDS (qa, plus qa + BUF when the
     // two halves sit in two buffers)
-    // (gdst != nullptr: accumulate into gdst[p] instead)
-    auto gather = [&](const float2* qa, bool two, int tj, float2* gdst) {
+    // (to_dst true: accumulate into gdst[p] instead; a compile-time choice so
+    // that the register accumulators stay in registers)
+    auto gather = [&](const float2* qa, bool two, int tj, auto to_dst, float2* gdst) {
+        constexpr bool TO_DST = decltype(to_dst)::value;
         const int Sj = N - tj;
 #pragma unroll
         for (int i = 0; i < NACC; ++i) {
             const int p = tid + WGS * i;
             if (p < N) {
-                float2 sum = gdst ? gdst[p] : (GACC ? slab[p] : acc[GACC ? 0 : i]);
+                float2 sum = TO_DST ? gdst[p] : (GACC ? slab[p] : acc[(GACC || TO_DST) ? 0 : i]);
                 if (p < Sj) {
                     float2 Q = qa[lds_index(p)];
                     if (two) Q = cadd(Q, qa[BUF + lds_index(p)]);
@@ -334,12 +336,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     if (two) Q = cadd(Q, qa[BUF + lds_index(m)]);
                     sum = cadd(sum, cmul(Q, sv[m]));
                 }
-                if (gdst)
+                if (TO_DST)
                     gdst[p] = sum;
                 else if (GACC)
                     slab[p] = sum;
                 else
-                    acc[GACC ? 0 : i] = sum;
+                    acc[(GACC || TO_DST) ? 0 : i] = sum;
             }
         }
     };
@@ -645,7 +647,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     __syncthreads();
                     for (int j = 0; j < LPI; ++j) {
                         if (t0 + j >= sg.tau_end) break;
-                        gather(lds + j * BUF, false, t0 + j, nullptr);
+                        gather(lds + j * BUF, false, t0 + j, std::false_type{}, nullptr);
                     }
                     __syncthreads();
                 }
@@ -657,7 +659,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // lag-product adjoint for every lag of this iteration
             for (int j = 0; j < LPI; ++j) {
                 if (t0 + j >= sg.tau_end) break;
-                gather(lds + 2 * j * BUF, true, t0 + j, nullptr);
+                gather(lds + 2 * j * BUF, true, t0 + j, std::false_type{}, nullptr);
             }
         }
         __syncthreads();
@@ -680,7 +682,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 __syncthreads();
                 for (int j = 0; j < LPI; ++j) {
                     if (t0 + j >= sg.tau_end) break;
-                    gather(lds + 2 * j * BUF, true, t0 + j, slab2);
+                    gather(lds + 2 * j * BUF, true, t0 + j, std::true_type{}, slab2);
                 }
                 __syncthreads();
             }
