@@ -263,6 +263,19 @@ def test_small_temperature_uses_running_maximum(af):
     loss_vs_oracle(af, plan, codes, [m], [n - 1], dict(w_isl=1.0, w_psl=1.0, temp=0.01), "small T")
 
 
+def test_autotune_picks_a_fitting_variant(af):
+    # two size classes; the tuner times every variant that fits each class
+    # and the plan keeps computing the same loss and gradient afterwards
+    say("autotune")
+    ns, ms = [256, 256, 700], [512, 512, 2048]
+    codes = [W.random_code(n, seed=600 + i) for i, n in enumerate(ns)]
+    plan = af.Plan(ns, ms, eps=EPS)
+    v, best = plan.autotune(packed(codes))
+    assert v in (0, 3, 4) and best > 0.0  # M = 2048 fits variants 0, 3 and 4
+    assert plan.summary()["variant"] == v
+    loss_vs_oracle(af, plan, codes, ms, [n - 1 for n in ns], dict(w_isl=1.0, w_psl=0.0, temp=0.05), "autotuned")
+
+
 def test_weighted_isl_batch(af):
     # descriptor-weighted ISL on a slice of the proposal workload (N=256, M=512)
     say("weighted isl batch")
