@@ -353,6 +353,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     if (isl_seg) {
         for (int p = tid; p < N; p += WGS) slab2[p] = make_float2(0.f, 0.f);
     }
+    // With few mainlobe bins, Q of the ISL part is evaluated directly from
+    // H on those bins (2 h_k + 1 per lag, kept in scratch) instead of a
+    // second transform pair.
+    const int n_mb = 2 * w.h_k + 1;
+    const bool direct_isl = isl_seg && LPI * n_mb <= 64;
+    float2* const mlb = reinterpret_cast<float2*>(scratch);
     double isl = 0.0, ls = 0.0, dle = 0.0;
     float lm = (want_lse && (lse_fixed || MODE == MODE_LOSS)) ? lse_ref(a.eps) : -INFINITY;
 
@@ -536,6 +542,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                             }
                             c = sd ? mult * cs : ((COMPL && main_cell) ? c_main : 0.f);
                         } else if constexpr (MODE == MODE_LOSS) {
+                            if (direct_isl && main_cell) {
+                                // H of the ISL part on this mainlobe bin
+                                const int ks = k < (M >> 1) ? k : k - M;
+                                mlb[lam * n_mb + ks + w.h_k] = cscale(v[q], -mult * a.w_isl * invE2);
+                            }
                             // soft-PSL part without the normaliser 1/S
                             const float ia = __builtin_amdgcn_rcpf(av);
                             c = sd ? mult * a.w_psl * e * 0.5f * invE2 * ia : 0.f;
@@ -664,7 +675,30 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         }
         __syncthreads();
         if constexpr (MODE == MODE_LOSS && SPLIT) {
-            if (isl_seg && t0 <= w.h_tau) {
+            if (direct_isl && t0 <= w.h_tau) {
+                // ISL part of the mainlobe lags: Q[m] = sum over the mainlobe
+                // bins of H[k] exp(+j 2 pi k m / M), into each lag's buffer
+                for (int j = 0; j < LPI; ++j) {
+                    const int tj = t0 + j;
+                    if (tj >= sg.tau_end || tj > w.h_tau) break;
+                    float2* qb = lds + 2 * j * BUF;
+                    const float2* hb = mlb + j * n_mb;
+                    for (int m = tid; m < N - tj; m += WGS) {
+                        float2 qv = make_float2(0.f, 0.f);
+                        for (int b = 0; b < n_mb; ++b) {
+                            const int ti = ((b - w.h_k) * m) & (M - 1);
+                            qv = cadd(qv, cmulc(hb[b], twl[ti << twsh]));
+                        }
+                        qb[lds_index(m)] = qv;
+                    }
+                }
+                __syncthreads();
+                for (int j = 0; j < LPI; ++j) {
+                    if (t0 + j >= sg.tau_end || t0 + j > w.h_tau) break;
+                    gather(lds + 2 * j * BUF, false, t0 + j, std::true_type{}, slab2);
+                }
+                __syncthreads();
+            } else if (isl_seg && t0 <= w.h_tau) {
                 // ISL part of the mainlobe lags: the spectrum again, times
                 // d(M - mainlobe power)/d conj(chi) = -w_isl/E^2 on mainlobe
                 // cells (both signs of tau for tau > 0), into the second slab
