@@ -236,7 +236,7 @@ af_status build_schedule(af_plan* p) {
                          [&](int a, int b) { return seg_cost[a] > seg_cost[b]; });
         cls[c].count = (int)order.size() - cls[c].begin;
         for (int i = cls[c].begin; i < (int)order.size(); ++i) cls[c].cost += seg_cost[order[i]];
-        for (int mode = 0; mode < 4; ++mode) cls[c].grid[mode] = std::min(cls[c].grid[mode], cls[c].count);
+        for (int mode = 0; mode < graf::kNumModes; ++mode) cls[c].grid[mode] = std::min(cls[c].grid[mode], cls[c].count);
     }
 
     std::vector<SegDesc> exec(order.size());

@@ -276,6 +276,56 @@ def test_autotune_picks_a_fitting_variant(af):
     loss_vs_oracle(af, plan, codes, ms, [n - 1 for n in ns], dict(w_isl=1.0, w_psl=0.0, temp=0.05), "autotuned")
 
 
+def test_fused_loss_graph_replay_matches_eager(af):
+    # ISL + soft-PSL Adam steps on one waveform through the fused loss pass
+    # and the reduce-plus-Adam kernel, captured in a HIP graph (device step
+    # counter, exit counter): every replay must equal the eager steps
+    say("fused loss graph replay")
+    n, m, K = 1024, 2048, 4
+    plan = af.Plan([n], [m], eps=EPS)
+    phi0 = torch.from_numpy(W.random_phases(n, seed=21).astype(np.float32)).cuda()
+    st_e = af.PhaseState(phi0.clone())
+    terms_e = torch.empty(1, 4, device="cuda")
+    eager = []
+    for _ in range(3 * K):
+        plan.optim_step(st_e, w_isl=1.0, w_psl=1.0, lr=0.01, terms=terms_e)
+        eager.append((st_e.phi.clone(), terms_e.clone()))
+    torch.cuda.synchronize()
+    st_g = af.PhaseState(phi0.clone())
+    terms_g = torch.empty(1, 4, device="cuda")
+    ws = plan.workspace
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(K):
+                plan.optim_step(st_g, w_isl=1.0, w_psl=1.0, lr=0.01, terms=terms_g, ws=ws)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        phi_e, terms_ref = eager[(rep + 1) * K - 1]
+        assert int(st_g.step.item()) == (rep + 1) * K
+        assert torch.equal(st_g.phi, phi_e), "replay %d" % rep
+        assert torch.equal(terms_g, terms_ref), "replay %d" % rep
+        _ = (st_g.phi * 2).sum().item()  # unrelated eager work between replays
+
+
+def test_fused_pass_matches_two_passes(af):
+    # the same loss and gradient from the fused pass (auto) and from forced
+    # forward + backward passes
+    say("fused vs two passes")
+    n, m = 1024, 2048
+    s = to_dev(W.random_code(n, seed=31))
+    a = af.Plan([n], [m], eps=EPS).loss(s, w_isl=1.0, w_psl=1.0, temp=0.05)
+    b = af.Plan([n], [m], eps=EPS, loss_passes=1).loss(s, w_isl=1.0, w_psl=1.0, temp=0.05)
+    torch.cuda.synchronize()
+    ga, gb = a[1].cpu().numpy(), b[1].cpu().numpy()
+    assert np.max(np.abs(ga - gb)) <= 1e-4 * np.max(np.abs(gb))
+    assert np.allclose(a[0].cpu().numpy(), b[0].cpu().numpy(), rtol=1e-5, atol=1e-6)
+
+
 def test_weighted_isl_batch(af):
     # descriptor-weighted ISL on a slice of the proposal workload (N=256, M=512)
     say("weighted isl batch")
