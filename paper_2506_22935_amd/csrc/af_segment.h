@@ -350,14 +350,14 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     // form); segments holding mainlobe lags collect it in their second slab
     const bool isl_seg = MODE == MODE_LOSS && compl_isl && a.w_isl != 0.f && sg.tau_begin <= w.h_tau;
     float2* const slab2 = isl_seg ? a.slabs2 + w.slab2_off + (int64_t)(sg.rec - w.seg_begin) * N : nullptr;
-    if (isl_seg) {
-        for (int p = tid; p < N; p += WGS) slab2[p] = make_float2(0.f, 0.f);
-    }
     // With few mainlobe bins, Q of the ISL part is evaluated directly from
     // H on those bins (2 h_k + 1 per lag, kept in scratch) instead of a
-    // second transform pair.
+    // second transform pair; its first iteration then initialises the slab.
     const int n_mb = 2 * w.h_k + 1;
     const bool direct_isl = isl_seg && LPI * n_mb <= 64;
+    if (isl_seg && !direct_isl) {
+        for (int p = tid; p < N; p += WGS) slab2[p] = make_float2(0.f, 0.f);
+    }
     float2* const mlb = reinterpret_cast<float2*>(scratch);
     double isl = 0.0, ls = 0.0, dle = 0.0;
     float lm = (want_lse && (lse_fixed || MODE == MODE_LOSS)) ? lse_ref(a.eps) : -INFINITY;
@@ -484,7 +484,13 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     const int kn = k ? M - k : 0;
                     const int kc = k < (M >> 1) ? k : M - k;  // |centred bin|
                     const float pw = cabs2(v[q]) * invE2;
-                    const float av = __builtin_amdgcn_sqrtf(pw + a.eps);
+                    // a = sqrt(x) and 1/a = rsqrt(x): modes that need both take
+                    // one reciprocal square root and a multiply
+                    constexpr bool NEED_IA = MODE == MODE_BWD_MAG || MODE == MODE_LOSS ||
+                                             (MODE == MODE_BWD_LOSS && PSL);
+                    const float xa = pw + a.eps;
+                    const float ia = NEED_IA ? __builtin_amdgcn_rsqf(xa) : 0.f;
+                    const float av = NEED_IA ? xa * ia : __builtin_amdgcn_sqrtf(xa);
                     const bool main_cell = active && main_tau && kc <= w.h_k;
                     const bool sd = active && !main_cell;
                     float wt = 1.f;
@@ -529,15 +535,13 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                                 if (active && tau > 0) g += a.grad_mag[row_n + kn];
                             }
                             g = active ? g : 0.f;
-                            const float ia = __builtin_amdgcn_rcpf(av);
                             c = 0.5f * g * invE2 * ia;
                             dle_f = fmaf(-g * pw * invE, ia, dle_f);
                         } else if constexpr (MODE == MODE_BWD_LOSS) {
                             float cs = COMPL ? 0.f : a.w_isl * wt * invE2;
                             if constexpr (PSL) {
                                 const float qq = fast_exp2((av - glob_m) * inv_t2) * glob_inv_s;
-                                const float ia = __builtin_amdgcn_rcpf(av);
-                                cs = fmaf(a.w_psl * qq * 0.5f * invE2, ia, cs);
+                                    cs = fmaf(a.w_psl * qq * 0.5f * invE2, ia, cs);
                                 dle_f = fmaf(sd ? -a.w_psl * qq * pw * invE : 0.f, ia, dle_f);
                             }
                             c = sd ? mult * cs : ((COMPL && main_cell) ? c_main : 0.f);
@@ -548,7 +552,6 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                                 mlb[lam * n_mb + ks + w.h_k] = cscale(v[q], -mult * a.w_isl * invE2);
                             }
                             // soft-PSL part without the normaliser 1/S
-                            const float ia = __builtin_amdgcn_rcpf(av);
                             c = sd ? mult * a.w_psl * e * 0.5f * invE2 * ia : 0.f;
                             dle_f = fmaf(sd ? -a.w_psl * e * pw * invE : 0.f, ia, dle_f);
                         } else {  // MODE_FUSED_ISL
@@ -693,9 +696,26 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     }
                 }
                 __syncthreads();
+                // adjoint of every mainlobe lag of the iteration in registers,
+                // then one write (or update) of the second slab
+                float2 acc2[NACC];
+#pragma unroll
+                for (int i = 0; i < NACC; ++i) acc2[i] = make_float2(0.f, 0.f);
                 for (int j = 0; j < LPI; ++j) {
-                    if (t0 + j >= sg.tau_end || t0 + j > w.h_tau) break;
-                    gather(lds + 2 * j * BUF, false, t0 + j, std::true_type{}, slab2);
+                    const int tj = t0 + j;
+                    if (tj >= sg.tau_end || tj > w.h_tau) break;
+                    const float2* qa = lds + 2 * j * BUF;
+#pragma unroll
+                    for (int i = 0; i < NACC; ++i) {
+                        const int p = tid + WGS * i;
+                        if (p < N - tj) acc2[i] = cadd(acc2[i], cmul(cconj(qa[lds_index(p)]), sv[p + tj]));
+                        if (p < N && p >= tj) acc2[i] = cadd(acc2[i], cmul(qa[lds_index(p - tj)], sv[p - tj]));
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < NACC; ++i) {
+                    const int p = tid + WGS * i;
+                    if (p < N) slab2[p] = (t0 == sg.tau_begin) ? acc2[i] : cadd(slab2[p], acc2[i]);
                 }
                 __syncthreads();
             } else if (isl_seg && t0 <= w.h_tau) {
@@ -725,14 +745,17 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 
     // ------------------------------------------- segment results -------
     // one fixed-order reduction of (ISL, soft-PSL pair, dL/dE) over the group
+    // wavefront sums in float (each lane's partial already folds its cells in
+    // float64; 64 float terms keep the 1e-4 loss and gradient bars with room),
+    // wave totals combined in float64 below
     if (FWD_SUMS) {
         if (lse_fixed || MODE == MODE_LOSS)
-            ls = wave_sum(ls);
+            ls = (double)wave_sum((float)ls);
         else
             wave_lse(lm, ls, inv_t2);
     }
-    isl = wave_sum(isl);
-    if (MODE != MODE_FWD) dle = wave_sum(dle);
+    isl = (double)wave_sum((float)isl);
+    if (MODE != MODE_FWD) dle = (double)wave_sum((float)dle);
     __syncthreads();
     if ((tid & 63) == 0) {
         scratch[4 * (tid >> 6) + 0] = isl;
