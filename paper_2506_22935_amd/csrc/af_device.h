@@ -237,13 +237,29 @@ struct Plan {
     static constexpr int RLAST = 1 << (LOG_MH - (NPASS - 1) * LOG_P);
 };
 
+// ------------------------------------------------------- twiddle tables --
+// w_M^i = exp(-j 2 pi i / M) for 0 <= i < M of the transform's M = 2 MH.
+// TwTable reads one table (index scaled by sh when the table serves a larger
+// transform); TwSplit multiplies two short tables, hi[i >> b] * lo[i mod 2^b],
+// which fit in LDS beside the transform buffers of large sizes.
+struct TwTable {
+    const float2* t;
+    int sh;
+    __device__ __forceinline__ float2 operator()(int i) const { return t[i << sh]; }
+};
+struct TwSplit {
+    const float2* hi;
+    const float2* lo;
+    int b;
+    __device__ __forceinline__ float2 operator()(int i) const { return cmul(hi[i >> b], lo[i & ((1 << b) - 1)]); }
+};
+
 // Pass number PASS (0-based) with stride NS = P^PASS and radix R.
 // in: v laid out as slots [b*R + r] = x[j + r*MH/R], j = l + L*b
 // out: written to LDS y[(j/NS)*NS*R + j%NS + r*NS] unless LAST, in which
 //      case the values stay in registers: slot [b*R + r] = X[j + r*MH/R].
-template <int MH, int P, int R, int NS, int SIGN, bool LAST>
-__device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, const float2* __restrict__ tw,
-                                              int tw_shift) {
+template <int MH, int P, int R, int NS, int SIGN, bool LAST, typename Tw>
+__device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, const Tw& tw, int tw_shift) {
     constexpr int L = MH / P;
     constexpr int NB = P / R;
 #pragma unroll
@@ -252,10 +268,10 @@ __device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, con
         const int k = j & (NS - 1);
         float2* u = v + b * R;
         if constexpr (NS > 1) {
-            // exp(SIGN j 2pi r k / (NS R)) = w_MMAX^(r k MMAX/(NS R))
+            // exp(SIGN j 2pi r k / (NS R)) = w_M^(r k M/(NS R))
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[(r * k) << tw_shift];
+                float2 w = tw((r * k) << tw_shift);
                 if (SIGN > 0) w.y = -w.y;
                 u[r] = cmul(u[r], w);
             }
@@ -293,17 +309,16 @@ __device__ __forceinline__ void read_group(float2* v, const float2* lds, int l) 
 // Full transform of one lane group.  Synchronisation between passes goes
 // through SYNC(), which must make every lane's LDS stores visible to every
 // lane of the group (a work-group barrier or a wavefront-level fence).
-// tw is the table for MMAX = MH << (tw_shift_base): exp(-j 2pi i / MMAX).
-template <int MH, int P, int SIGN, typename Sync>
-__device__ __forceinline__ void fft_group(float2* v, float2* lds, int l, const float2* __restrict__ tw,
-                                          int mmax_over_mh, Sync sync) {
+// tw gives w_M^i for the transform's M = 2 MH.
+template <int MH, int P, int SIGN, typename Tw, typename Sync>
+__device__ __forceinline__ void fft_group(float2* v, float2* lds, int l, const Tw& tw, Sync sync) {
     using PL = Plan<MH, P>;
     constexpr int L = PL::L;
     constexpr int NPASS = PL::NPASS;
     constexpr int RL = PL::RLAST;
-    // tw index for pass with NS, R: (r k) * (MMAX / (NS R))
-    // MMAX / (NS R) = mmax_over_mh * MH / (NS R), a power of two -> shift
-    const int sh0 = __builtin_ctz(mmax_over_mh);
+    // tw index for pass with NS, R: (r k) * (M / (NS R)), M / (NS R) =
+    // 2 MH / (NS R), a power of two -> shift
+    constexpr int sh0 = 1;
     static_assert(NPASS >= 1 && NPASS <= 4, "transform size out of range");
     if constexpr (NPASS == 1) {
         stockham_pass<MH, P, RL, 1, SIGN, true>(v, lds, l, tw, 0);

@@ -243,9 +243,24 @@ __device__ void stage_twiddles(const AfArgs& a, float2* twl, int twsh) {
     __syncthreads();
 }
 
-template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC>
-__device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, const float2* twl,
-                                                int twsh, const float2* s_lds, bool s_in_lds, double* scratch,
+// Copy the two short twiddle tables of TwSplit (lo: w_M^j, j < 2^b; hi:
+// w_M^(h 2^b), h < M / 2^b) from the global table, then synchronise.
+template <int WGS, int MH, int B>
+__device__ void stage_split_twiddles(const AfArgs& a, float2* hi, float2* lo, int twsh) {
+    constexpr int M = 2 * MH;
+    constexpr int NLO = 1 << B, NHI = M >> B;
+    for (int j = threadIdx.x; j < NLO + NHI; j += WGS) {
+        if (j < NLO)
+            lo[j] = a.tw[j << twsh];
+        else
+            hi[j - NLO] = a.tw[((j - NLO) << B) << twsh];
+    }
+    __syncthreads();
+}
+
+template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, typename Tw>
+__device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, const Tw& twl,
+                                                const float2* s_lds, bool s_in_lds, double* scratch,
                                                 const WaveState& ws) {
     constexpr int L = MH / P;
     constexpr int G = WGS / L;
@@ -274,7 +289,6 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const int tshift = a.log2_mmax - w.log2m;  // w_M^i = tw[i << tshift]
     const float2* __restrict__ sg_s = a.s + w.s_off;
     const float2* __restrict__ tw = a.tw;
-    const int tw_mh = 2 << twsh;  // table entries per MH
     // transform passes exchange data only inside the lane group: when the
     // group is exactly one wavefront, ordering its own LDS accesses suffices
     auto sync = []() {
@@ -373,7 +387,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             for (int r = 0; r < P; ++r) {
                 const int m = l + r * L;
                 float2 x = cmulc(sv[m + tz], sv[m]);
-                if (h) x = cmul(x, twl[m << twsh]);
+                if (h) x = cmul(x, twl(m));
                 v[r] = x;
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
@@ -384,22 +398,22 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 float2 x = make_float2(0.f, 0.f);
                 if (active && m < S) {
                     x = cmulc(sv[m + tau], sv[m]);
-                    if (h) x = cmul(x, twl[m << twsh]);
+                    if (h) x = cmul(x, twl(m));
                 }
                 v[r] = x;
                 // bound how many loads the scheduler keeps in flight
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
         }
-        fft_group<MH, P, -1>(v, buf, l, twl, tw_mh, sync);
+        fft_group<MH, P, -1>(v, buf, l, twl, sync);
     };
     // Q' of half h: inverse transform, w_M^{-m} on the odd half, stored to
     // this group's buffer in natural order
     auto inverse_to_lds = [&](float2* v, int h) {
-        fft_group<MH, P, +1>(v, buf, l, twl, tw_mh, sync);
+        fft_group<MH, P, +1>(v, buf, l, twl, sync);
         if (h) {
 #pragma unroll
-            for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl[(l + q * L) << twsh]);
+            for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl(l + q * L));
         }
         if constexpr (L % 32 == 0) {
             const int bi = lds_index(l);
@@ -690,7 +704,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         float2 qv = make_float2(0.f, 0.f);
                         for (int b = 0; b < n_mb; ++b) {
                             const int ti = ((b - w.h_k) * m) & (M - 1);
-                            qv = cadd(qv, cmulc(hb[b], twl[ti << twsh]));
+                            qv = cadd(qv, cmulc(hb[b], twl(ti)));
                         }
                         qb[lds_index(m)] = qv;
                     }
@@ -808,9 +822,13 @@ struct Variant {
                (SPLIT ? 2 * ((1 << lg) / P) <= WGS : ((1 << lg) / P) <= WGS);
     }
     // dynamic LDS of one instance: transform buffers, then the twiddle table
-    // w_M^i for i < M = 2^(lg+1)
+    // w_M^i for i < M = 2^(lg+1), or (TW_LDS = 0) its two short factors
+    static constexpr int split_bits(int lg) { return (lg + 2) / 2; }
+    static constexpr int split_lds_bytes(int lg) { return (((2 << lg) >> split_bits(lg)) + (1 << split_bits(lg))) * 8; }
     static constexpr int buf_lds_bytes(int lg) { return (WGS / ((1 << lg) / P)) * ((1 << lg) + ((1 << lg) >> 5)) * 8; }
-    static constexpr int fft_lds_bytes(int lg) { return buf_lds_bytes(lg) + (TW_LDS ? (2 << lg) * 8 : 0); }
+    static constexpr int fft_lds_bytes(int lg) {
+        return buf_lds_bytes(lg) + (TW_LDS ? (2 << lg) * 8 : split_lds_bytes(lg));
+    }
 };
 
 //                 P  split WGS waves LG range  s, twiddles in LDS
@@ -831,9 +849,18 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     float2* lds = dyn;
     float2* s_lds = V::S_LDS ? dyn + V::fft_lds_bytes(LG) / 8 : nullptr;
     float2* tw_lds = V::TW_LDS ? dyn + V::buf_lds_bytes(LG) / 8 : nullptr;
-    const float2* twl = V::TW_LDS ? tw_lds : a.tw;
     const int twsh_global = a.log2_mmax - (LG + 1);
-    const int twsh = V::TW_LDS ? 0 : twsh_global;
+    constexpr int TB = V::split_bits(LG);
+    float2* tw_lo = dyn + V::buf_lds_bytes(LG) / 8;
+    float2* tw_hi = tw_lo + (1 << TB);
+    using Tw = std::conditional_t<V::TW_LDS != 0, TwTable, TwSplit>;
+    Tw twl;
+    if constexpr (V::TW_LDS) {
+        twl = TwTable{tw_lds, 0};
+    } else {
+        twl = TwSplit{tw_hi, tw_lo, TB};
+        if (blockIdx.x < a.n_segs) stage_split_twiddles<V::WGS, MH, TB>(a, tw_hi, tw_lo, twsh_global);
+    }
     WaveState st;
     st.wave = -1;
     // the first item's descriptor travels with the staging loads; each later
@@ -858,8 +885,8 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
             const WaveDesc w = a.single ? a.w0 : a.waves[sg.wave];
             stage_wave<MODE, V::WGS, MH>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st, nullptr, 0);
         }
-        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG)>(a, sg, lds, twl, twsh, s_lds, V::S_LDS != 0,
-                                                                      scratch, st);
+        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG)>(a, sg, lds, twl, s_lds, V::S_LDS != 0, scratch,
+                                                                      st);
     }
 }
 
