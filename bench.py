@@ -199,9 +199,15 @@ def bench_uneven(args, torch):
     from paper_2506_22935_amd import af, workloads as W
     ns, ms, phases = W.uneven_batch(512, seed=args.seed)
     cells = int(sum((2 * n - 1) * m for n, m in zip(ns, ms)))
-    plan = af.Plan(ns.tolist(), ms.tolist(), eps=1e-12)
+    plan = af.Plan(ns.tolist(), ms.tolist(), eps=1e-12, variant=args.variant)
     log("uneven: %d waveforms, %.3g cells, %d segments" % (len(ns), cells, plan.summary()["segments"]))
     st = af.PhaseState(torch.from_numpy(np.concatenate(phases).astype(np.float32)).cuda())
+    tuned = None
+    if args.variant < 0:
+        # the plan's autotuner times every variant that fits each size class
+        v, tms = plan.autotune(st.s)
+        tuned = dict(largest_class_variant=v, tuned_pass_ms=round(tms, 4))
+        log("autotuned: largest class -> variant %d, %.3f ms per fused pass" % (v, tms))
     terms = torch.empty(plan.batch, 4, device="cuda")
     ws = plan.workspace
     for _ in range(args.warmup):
@@ -228,7 +234,7 @@ def bench_uneven(args, torch):
     out = dict(value=cells / (ms_step * 1e-3), ms_per_step=ms_step,
                config=dict(workload="uneven: 512 random-phase codes, N log-uniform [64,4096], M=next pow2>=2N, "
                                     "full lag grid, ISL fwd+bwd + Adam step, %d steps in one HIP graph" % args.steps,
-                           waveforms=len(ns), cells=cells, segments=plan.summary()["segments"],
+                           waveforms=len(ns), cells=cells, segments=plan.summary()["segments"], autotune=tuned,
                            isl_sum_before=isl0, isl_sum_after=isl1),
                roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                              frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,

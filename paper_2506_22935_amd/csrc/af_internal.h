@@ -126,7 +126,7 @@ hipError_t launch_phase_to_signal(const float* phi, float2* s, int64_t count, hi
 struct VariantInfo {
     int lo, hi, p, split, wgs, s_lds, fits, fft_lds, nacc;
 };
-constexpr int kNumVariants = 5;
+constexpr int kNumVariants = 6;
 VariantInfo variant_info(int v, int lg);
 int variant_max_resident(int mode, int variant, int lg, int dyn_lds_bytes);
 hipError_t launch_af(int mode, int variant, int lg, const AfArgs& a, int grid, int dyn_lds_bytes, hipStream_t st);

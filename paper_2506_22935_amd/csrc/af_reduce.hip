@@ -43,11 +43,13 @@ void* variant_kernel_1(int mode, int lg);
 void* variant_kernel_2(int mode, int lg);
 void* variant_kernel_3(int mode, int lg);
 void* variant_kernel_4(int mode, int lg);
+void* variant_kernel_5(int mode, int lg);
 VariantInfo variant_info_0(int lg);
 VariantInfo variant_info_1(int lg);
 VariantInfo variant_info_2(int lg);
 VariantInfo variant_info_3(int lg);
 VariantInfo variant_info_4(int lg);
+VariantInfo variant_info_5(int lg);
 
 VariantInfo variant_info(int v, int lg) {
     switch (v) {
@@ -56,6 +58,7 @@ VariantInfo variant_info(int v, int lg) {
         case 2: return variant_info_2(lg);
         case 3: return variant_info_3(lg);
         case 4: return variant_info_4(lg);
+        case 5: return variant_info_5(lg);
     }
     return VariantInfo{};
 }
@@ -67,6 +70,7 @@ static void* kernel_for(int mode, int variant, int lg) {
         case 2: return variant_kernel_2(mode, lg);
         case 3: return variant_kernel_3(mode, lg);
         case 4: return variant_kernel_4(mode, lg);
+        case 5: return variant_kernel_5(mode, lg);
     }
     return nullptr;
 }

@@ -837,6 +837,7 @@ using V1 = Variant<16, 1, 512, 2, 12, 12, 1, 0>; // M 8192
 using V2 = Variant<16, 0, 1024, 4, 13, 14, 0, 0>; // M 16384..32768, halves in turn
 using V3 = Variant<8, 1, 256, 2, 6, 10, 1, 1>;   // more lanes per lag, M <= 2048
 using V4 = Variant<32, 1, 256, 1, 8, 11, 1, 1>;  // fewer passes, M 512..4096
+using V5 = Variant<32, 1, 256, 1, 12, 12, 1, 0>; // M 8192: 32 points per lane, one wave per SIMD
 
 // Persistent kernel over one size class: work group g runs items g, g + grid,
 // g + 2 grid, ... of the class's list, which the planner sorted longest first

@@ -326,6 +326,28 @@ def test_fused_pass_matches_two_passes(af):
     assert np.allclose(a[0].cpu().numpy(), b[0].cpu().numpy(), rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("variant", [1, 5])
+def test_m8192_variants(af, variant):
+    # the two kernel variants for M = 8192 (512-thread groups; 32 points per
+    # lane with one wave per SIMD): forward, ISL loss and magnitude backward
+    say("M=8192 variant", variant)
+    ns, m = [300, 1000], 8192
+    codes = [W.random_code(n, seed=700 + n) for n in ns]
+    plan = af.Plan(ns, [m, m], eps=EPS, variant=variant)
+    assert plan.summary()["variant"] == variant
+    s = packed(codes)
+    mag, _, _ = plan.forward(s, mag=True)
+    terms, g, _ = plan.loss(s, w_isl=1.0, w_psl=0.0)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.complex128)
+    for b, n in enumerate(ns):
+        sr = ref_c64(codes[b])
+        ref = O.loss_and_grad(sr, m, n - 1, O.LossParams(eps=EPS))
+        assert np.max(np.abs(plan.grid(mag, b).cpu().numpy() - ref["a"])) <= TOL_A, "mag %d" % b
+        assert abs(terms[b, 1].item() - ref["isl"]) <= 1e-4 * ref["isl"]
+        check_grad(g[plan.s_offsets[b]:plan.s_offsets[b] + n], ref["g"], "M=8192 v%d wave %d" % (variant, b))
+
+
 def test_weighted_isl_batch(af):
     # descriptor-weighted ISL on a slice of the proposal workload (N=256, M=512)
     say("weighted isl batch")
