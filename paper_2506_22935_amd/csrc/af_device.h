@@ -28,6 +28,31 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float cabs2(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
 
+// ------------------------------------------------------ buffer access --
+// A buffer resource: base address and byte range in scalar registers, a
+// 32-bit per-lane byte offset per access.  Loads beyond the range return zero
+// and stores beyond it are dropped (the hardware checks the per-lane offset),
+// so global rows and sample arrays need neither 64-bit lane addresses nor
+// bounds predicates.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit access, no swizzle
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ float2 buf_load2(Rsrc r, int byte_off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+__device__ __forceinline__ void buf_store2(Rsrc r, int byte_off, float2 v) {
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, byte_off, 0, 0);
+}
+__device__ __forceinline__ float buf_load1(Rsrc r, int byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+__device__ __forceinline__ void buf_store1(Rsrc r, int byte_off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 0);
+}
+
 // ------------------------------------------------ wavefront reductions --
 // Lane exchange through DPP: quad permutations and row rotations act inside
 // rows of 16 lanes; the four row sums are then read out lane by lane.  The
@@ -258,7 +283,7 @@ struct TwSplit {
 // in: v laid out as slots [b*R + r] = x[j + r*MH/R], j = l + L*b
 // out: written to LDS y[(j/NS)*NS*R + j%NS + r*NS] unless LAST, in which
 //      case the values stay in registers: slot [b*R + r] = X[j + r*MH/R].
-template <int MH, int P, int R, int NS, int SIGN, bool LAST, typename Tw>
+template <int MH, int P, int R, int NS, int SIGN, bool LAST, bool LEAN, typename Tw>
 __device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, const Tw& tw, int tw_shift) {
     constexpr int L = MH / P;
     constexpr int NB = P / R;
@@ -274,6 +299,8 @@ __device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, con
                 float2 w = tw((r * k) << tw_shift);
                 if (SIGN > 0) w.y = -w.y;
                 u[r] = cmul(u[r], w);
+                // register-lean instances: a few twiddles in flight at a time
+                if (LEAN && (r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
             }
         }
         Dft<R, SIGN>::run(u);
@@ -309,8 +336,9 @@ __device__ __forceinline__ void read_group(float2* v, const float2* lds, int l) 
 // Full transform of one lane group.  Synchronisation between passes goes
 // through SYNC(), which must make every lane's LDS stores visible to every
 // lane of the group (a work-group barrier or a wavefront-level fence).
-// tw gives w_M^i for the transform's M = 2 MH.
-template <int MH, int P, int SIGN, typename Tw, typename Sync>
+// tw gives w_M^i for the transform's M = 2 MH.  LEAN bounds the twiddle loads
+// in flight (instances with few registers per lane).
+template <int MH, int P, int SIGN, bool LEAN = false, typename Tw, typename Sync>
 __device__ __forceinline__ void fft_group(float2* v, float2* lds, int l, const Tw& tw, Sync sync) {
     using PL = Plan<MH, P>;
     constexpr int L = PL::L;
@@ -321,29 +349,29 @@ __device__ __forceinline__ void fft_group(float2* v, float2* lds, int l, const T
     constexpr int sh0 = 1;
     static_assert(NPASS >= 1 && NPASS <= 4, "transform size out of range");
     if constexpr (NPASS == 1) {
-        stockham_pass<MH, P, RL, 1, SIGN, true>(v, lds, l, tw, 0);
+        stockham_pass<MH, P, RL, 1, SIGN, true, LEAN>(v, lds, l, tw, 0);
     } else {
-        stockham_pass<MH, P, P, 1, SIGN, false>(v, lds, l, tw, 0);
+        stockham_pass<MH, P, P, 1, SIGN, false, LEAN>(v, lds, l, tw, 0);
         sync();
         constexpr int NS1 = P;
         constexpr int R1 = NPASS == 2 ? RL : P;
         read_group<MH, P, R1>(v, lds, l);
         sync();
-        stockham_pass<MH, P, R1, NS1, SIGN, NPASS == 2>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS1 * R1));
+        stockham_pass<MH, P, R1, NS1, SIGN, NPASS == 2, LEAN>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS1 * R1));
         if constexpr (NPASS >= 3) {
             sync();
             constexpr int NS2 = P * P;
             constexpr int R2 = NPASS == 3 ? RL : P;
         read_group<MH, P, R2>(v, lds, l);
             sync();
-            stockham_pass<MH, P, R2, NS2, SIGN, NPASS == 3>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS2 * R2));
+            stockham_pass<MH, P, R2, NS2, SIGN, NPASS == 3, LEAN>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS2 * R2));
             if constexpr (NPASS >= 4) {
                 sync();
                 constexpr int NS3 = P * P * P;
                 constexpr int R3 = RL;
                 read_group<MH, P, R3>(v, lds, l);
                 sync();
-                stockham_pass<MH, P, R3, NS3, SIGN, true>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS3 * R3));
+                stockham_pass<MH, P, R3, NS3, SIGN, true, LEAN>(v, lds, l, tw, sh0 + PL::LOG_MH - PL::log2(NS3 * R3));
             }
         }
     }

@@ -274,9 +274,9 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     static_assert(L >= 1 && G >= (SPLIT ? 2 : 1), "group does not fit the work group");
     static_assert(!SPLIT || (2 * BUF * 2 >= 2 * M_), "row staging does not fit");
 
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
     const int grp = tid / L;
-    const int l = tid - grp * L;
+    int l = tid - grp * L;
     const int lam = SPLIT ? (grp >> 1) : grp;
     const int hsel = SPLIT ? ((L % 64 == 0) ? __builtin_amdgcn_readfirstlane(grp & 1) : (grp & 1)) : 0;
     const int t2 = tid - lam * TPL;  // thread index among the lag's threads
@@ -324,8 +324,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 #pragma unroll
     for (int i = 0; i < ((NEEDS_INV && !GACC) ? NACC : 1); ++i) acc[i] = make_float2(0.f, 0.f);
     float2* const slab = NEEDS_INV ? a.slabs + w.slab_off + (int64_t)(sg.rec - w.seg_begin) * N : nullptr;
+    // global samples (variants without samples in LDS) and the slab of the
+    // halves-in-turn variants through buffer resources over exactly N values
+    const Rsrc s_rs = make_rsrc(sg_s, (unsigned)N * 8u);
+    const Rsrc slab_rs = make_rsrc(slab, NEEDS_INV ? (unsigned)N * 8u : 0u);
     if (NEEDS_INV && GACC) {
-        for (int p = tid; p < N; p += WGS) slab[p] = make_float2(0.f, 0.f);
+        for (int p = tid; p < N; p += WGS) buf_store2(slab_rs, p * 8, make_float2(0.f, 0.f));
     }
     // lag-product adjoint of lag tj from Q' in LDS (qa, plus qa + BUF when the
     // two halves sit in two buffers)
@@ -338,25 +342,27 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         for (int i = 0; i < NACC; ++i) {
             const int p = tid + WGS * i;
             if (p < N) {
-                float2 sum = TO_DST ? gdst[p] : (GACC ? slab[p] : acc[(GACC || TO_DST) ? 0 : i]);
+                float2 sum = TO_DST ? gdst[p] : (GACC ? buf_load2(slab_rs, p * 8) : acc[(GACC || TO_DST) ? 0 : i]);
                 if (p < Sj) {
                     float2 Q = qa[lds_index(p)];
                     if (two) Q = cadd(Q, qa[BUF + lds_index(p)]);
-                    sum = cadd(sum, cmul(cconj(Q), sv[p + tj]));
+                    sum = cadd(sum, cmul(cconj(Q), s_in_lds ? sv[p + tj] : buf_load2(s_rs, (p + tj) * 8)));
                 }
                 const int m = p - tj;
                 if (m >= 0) {
                     float2 Q = qa[lds_index(m)];
                     if (two) Q = cadd(Q, qa[BUF + lds_index(m)]);
-                    sum = cadd(sum, cmul(Q, sv[m]));
+                    sum = cadd(sum, cmul(Q, s_in_lds ? sv[m] : buf_load2(s_rs, m * 8)));
                 }
                 if (TO_DST)
                     gdst[p] = sum;
                 else if (GACC)
-                    slab[p] = sum;
+                    buf_store2(slab_rs, p * 8, sum);
                 else
                     acc[(GACC || TO_DST) ? 0 : i] = sum;
             }
+            // slab accumulation: bound the loads the scheduler keeps in flight
+            if (GACC && (i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
     };
     const bool compl_isl = a.band_w == nullptr && w.full_window != 0;
@@ -378,7 +384,6 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 
     // Y' of lag tau, half h, in the exit layout v[q] = Y'[2 (l + qL) + h]
     auto lag_spectrum = [&](float2* v, int h, int tau, bool active) {
-        const int S = N - tau;
         if (s_in_lds) {
             // zero-padded samples: r'[m] = 0 for m >= N - tau comes out of
             // the product itself; an inactive lag reads zeros
@@ -392,25 +397,26 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
         } else {
+            // samples through the buffer resource over [0, N): the range
+            // check zeroes s[m + tau] for m >= N - tau; an inactive lag reads
+            // only zeros
+            const int tz = active ? tau : N;
 #pragma unroll
             for (int r = 0; r < P; ++r) {
                 const int m = l + r * L;
-                float2 x = make_float2(0.f, 0.f);
-                if (active && m < S) {
-                    x = cmulc(sv[m + tau], sv[m]);
-                    if (h) x = cmul(x, twl(m));
-                }
+                float2 x = cmulc(buf_load2(s_rs, (m + tz) * 8), buf_load2(s_rs, m * 8));
+                if (h) x = cmul(x, twl(m));
                 v[r] = x;
                 // bound how many loads the scheduler keeps in flight
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
         }
-        fft_group<MH, P, -1>(v, buf, l, twl, sync);
+        fft_group<MH, P, -1, (WGS >= 1024)>(v, buf, l, twl, sync);
     };
     // Q' of half h: inverse transform, w_M^{-m} on the odd half, stored to
     // this group's buffer in natural order
     auto inverse_to_lds = [&](float2* v, int h) {
-        fft_group<MH, P, +1>(v, buf, l, twl, sync);
+        fft_group<MH, P, +1, (WGS >= 1024)>(v, buf, l, twl, sync);
         if (h) {
 #pragma unroll
             for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl(l + q * L));
@@ -434,6 +440,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         const float wu = (banded && active) ? bu[(31 * tau) / N] : 1.f;
         const int64_t row_p = w.grid_off + (int64_t)(T + (active ? tau : 0)) * M;
         const int64_t row_n = w.grid_off + (int64_t)(T - (active ? tau : 0)) * M;
+        // rows tau and -tau of the halves-in-turn epilogue (empty when inactive)
+        const unsigned row_bytes = active ? (unsigned)M * 4u : 0u;
+        const Rsrc mag_p = make_rsrc(HAS_MAG_OUT && a.mag ? a.mag + row_p : nullptr, HAS_MAG_OUT && a.mag ? row_bytes : 0u);
+        const Rsrc mag_n = make_rsrc(HAS_MAG_OUT && a.mag ? a.mag + row_n : nullptr, HAS_MAG_OUT && a.mag ? row_bytes : 0u);
+        const Rsrc gm_p = make_rsrc(MODE == MODE_BWD_MAG ? a.grad_mag + row_p : nullptr, MODE == MODE_BWD_MAG ? row_bytes : 0u);
+        const Rsrc gm_n = make_rsrc(MODE == MODE_BWD_MAG ? a.grad_mag + row_n : nullptr, MODE == MODE_BWD_MAG ? row_bytes : 0u);
 
         // prefetch the two upstream rows (tau, -tau) while the transform runs
         constexpr int NPF = (MODE == MODE_BWD_MAG && SPLIT) ? (2 * M / 4) / TPL : 1;
@@ -453,19 +465,27 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 #pragma unroll 1
         for (int hh = 0; hh < (SPLIT ? 1 : 2); ++hh) {
             const int h = SPLIT ? hsel : hh;
+            if constexpr (WGS >= 1024) {
+                // 128 registers per lane: have every lane-index expression
+                // recomputed in the loop (integer arithmetic) rather than
+                // hoisted out of it and spilled
+                asm volatile("" : "+v"(l), "+v"(tid));
+            }
             float2 v[P];
             if (NEEDS_INV && a.load_store) {
-                const float2* ys = a.ystore + w.store_off + (int64_t)(active ? tau : 0) * M + h * MH;
+                // an inactive lag gets an empty range: zeros
+                const Rsrc ys = make_rsrc(a.ystore + w.store_off + (int64_t)(active ? tau : 0) * M + h * MH,
+                                          active ? (unsigned)MH * 8u : 0u);
 #pragma unroll
-                for (int q = 0; q < P; ++q) v[q] = active ? ys[l + q * L] : make_float2(0.f, 0.f);
+                for (int q = 0; q < P; ++q) v[q] = buf_load2(ys, (l + q * L) * 8);
             } else {
                 lag_spectrum(v, h, tau, active);
             }
             // v[q] = Y'[2 (l + qL) + h]
             if (MODE == MODE_FWD && a.ystore && active) {
-                float2* ys = a.ystore + w.store_off + (int64_t)tau * M + h * MH;
+                const Rsrc ys = make_rsrc(a.ystore + w.store_off + (int64_t)tau * M + h * MH, (unsigned)MH * 8u);
 #pragma unroll
-                for (int q = 0; q < P; ++q) ys[l + q * L] = v[q];
+                for (int q = 0; q < P; ++q) buf_store2(ys, (l + q * L) * 8, v[q]);
             }
             if constexpr (SPLIT) {
                 if (mag_out || MODE == MODE_BWD_MAG || chi_out) __syncthreads();  // transform buffers free
@@ -518,8 +538,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                                 rowbuf[k] = av;
                                 rowbuf[M + kn] = av;
                             } else if (active) {
-                                a.mag[row_p + k] = av;
-                                if (tau > 0) a.mag[row_n + kn] = av;
+                                buf_store1(mag_p, k * 4, av);
+                                if (tau > 0) buf_store1(mag_n, kn * 4, av);
                             }
                         }
                         if constexpr (COMPL)
@@ -545,8 +565,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                                 g = rowbuf[k];
                                 if (tau > 0) g += rowbuf[M + kn];
                             } else {
-                                g = active ? a.grad_mag[row_p + k] : 0.f;
-                                if (active && tau > 0) g += a.grad_mag[row_n + kn];
+                                g = buf_load1(gm_p, k * 4);
+                                if (tau > 0) g += buf_load1(gm_n, kn * 4);
                             }
                             g = active ? g : 0.f;
                             c = 0.5f * g * invE2 * ia;
