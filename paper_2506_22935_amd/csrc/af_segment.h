@@ -465,12 +465,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 #pragma unroll 1
         for (int hh = 0; hh < (SPLIT ? 1 : 2); ++hh) {
             const int h = SPLIT ? hsel : hh;
-            if constexpr (WGS >= 1024) {
-                // 128 registers per lane: have every lane-index expression
-                // recomputed in the loop (integer arithmetic) rather than
-                // hoisted out of it and spilled
-                asm volatile("" : "+v"(l), "+v"(tid));
-            }
+            // have every lane-index expression (LDS and row offsets, bin
+            // numbers) recomputed in the loop from an opaque lane index:
+            // cheap integer arithmetic, where hoisting it out of the loop
+            // keeps dozens of values live and spills them
+            asm volatile("" : "+v"(l), "+v"(tid));
             float2 v[P];
             if (NEEDS_INV && a.load_store) {
                 // an inactive lag gets an empty range: zeros
