@@ -25,7 +25,6 @@ namespace {
 constexpr int kMaxLds = 160 * 1024;
 constexpr int kMinM = 128;
 constexpr int kMaxM = 32768;
-constexpr int kCtrlWords = 64;  // 2 per size class + 2 for the optimiser step
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 int ilog2(int64_t x) {
@@ -76,7 +75,6 @@ struct af_plan {
     SegDesc* d_segs = nullptr;
     graf::RBlock* d_chunks = nullptr;  // reduce blocks
     float2* d_tw = nullptr;
-    unsigned* d_ctrl = nullptr;
     size_t cap_segs = 0, cap_chunks = 0;
 };
 
@@ -87,12 +85,10 @@ void free_tables(af_plan* p) {
     if (p->d_segs) (void)hipFree(p->d_segs);
     if (p->d_chunks) (void)hipFree(p->d_chunks);
     if (p->d_tw) (void)hipFree(p->d_tw);
-    if (p->d_ctrl) (void)hipFree(p->d_ctrl);
     p->d_waves = nullptr;
     p->d_segs = nullptr;
     p->d_chunks = nullptr;
     p->d_tw = nullptr;
-    p->d_ctrl = nullptr;
 }
 
 // Can variant v run transform size 2^lg for waveforms up to max_n samples?
@@ -279,11 +275,6 @@ af_status build_schedule(af_plan* p) {
         p->cap_chunks = rblocks.size();
     }
     if (!p->d_waves && hipMalloc(&p->d_waves, (size_t)B * sizeof(WaveDesc)) != hipSuccess) return hip_fail();
-    if (!p->d_ctrl) {
-        if (hipMalloc(&p->d_ctrl, kCtrlWords * sizeof(unsigned)) != hipSuccess) return hip_fail();
-        if (hipMemset(p->d_ctrl, 0, kCtrlWords * sizeof(unsigned)) != hipSuccess) return hip_fail();
-    }
-    if (2 * C + 2 > kCtrlWords) return AF_ERR_UNSUPPORTED;
     if (hipMemcpy(p->d_waves, wd.data(), (size_t)B * sizeof(WaveDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_segs, exec.data(), exec.size() * sizeof(SegDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_chunks, rblocks.data(), rblocks.size() * sizeof(graf::RBlock), hipMemcpyHostToDevice) !=
@@ -386,7 +377,6 @@ ReduceArgs reduce_args(const af_plan* p, const void* s, const WsView& v) {
     r.slabs2 = v.slabs2;
     r.energy = v.energy;
     r.temp = 1.f;
-    r.ctrl = p->d_ctrl + (kCtrlWords - 2);
     return r;
 }
 

@@ -111,7 +111,6 @@ struct ReduceArgs {
     float* adam_v;
     float2* s_next;       // exp(j phi_new)
     int* step;            // device step counter (1-based after increment)
-    unsigned* ctrl;       // [1] exit counter for the step increment
     float lr, beta1, beta2, adam_eps;
 };
 

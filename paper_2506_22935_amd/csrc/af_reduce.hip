@@ -10,23 +10,17 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
     reduce_chunk<false>(a, (int)blockIdx.x, 0, sh, sh2);
 }
 
-// Reduce, then one Adam step; the last block to finish advances the device
-// step counter.
+// Reduce, then one Adam step with step number *step + 1; the counter itself
+// is advanced by step_advance_kernel afterwards (a completion counter that
+// every block bumps would serialise thousands of device-scope atomics and
+// cache write-backs on one address).
 __global__ __launch_bounds__(256) void reduce_adam_kernel(ReduceArgs a) {
     __shared__ double sh[16];
     __shared__ float2 sh2[256];
-    const int t_prev = *a.step;  // read before this block signals completion
-    reduce_chunk<true>(a, (int)blockIdx.x, t_prev, sh, sh2);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned done = atomicAdd(&a.ctrl[0], 1u);
-        if (done == gridDim.x - 1) {
-            atomicExch(a.step, t_prev + 1);
-            atomicExch(&a.ctrl[0], 0u);
-        }
-    }
+    reduce_chunk<true>(a, (int)blockIdx.x, *a.step, sh, sh2);
 }
+
+__global__ void step_advance_kernel(int* step) { *step += 1; }
 
 __global__ __launch_bounds__(256) void phase_to_signal_kernel(const float* phi, float2* s, int64_t count) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -102,6 +96,9 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
 hipError_t launch_reduce_adam(const ReduceArgs& a, hipStream_t st) {
     if (a.n_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(reduce_adam_kernel, dim3(a.n_blocks), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, st, a.step);
     return hipGetLastError();
 }
 
