@@ -55,7 +55,7 @@ extern "C" {
 typedef enum {
     AF_OK = 0,
     AF_ERR_INVALID_ARG = -1, /* null pointer, bad size, bad offset */
-    AF_ERR_UNSUPPORTED = -2, /* M not a power of two, M < 2N, M > 32768, N too long for M */
+    AF_ERR_UNSUPPORTED = -2, /* M not a power of two, M < 2N, M > 32768, N too long for M; GEMM shape */
     AF_ERR_BUDGET = -3,      /* workspace cannot fit the budget even with recomputation */
     AF_ERR_HIP = -4,         /* a HIP runtime call failed */
     AF_ERR_WORKSPACE = -5,   /* workspace smaller than af_plan_workspace_size */
@@ -191,14 +191,29 @@ af_status af_optim_step(const af_plan* plan, float* phi, float* adam_m, float* a
  *   1: out_f32 = C + bias[n]
  *   2: out_f32 = Z = C + bias[n]; out_bf16 = GELU(Z)   (exact erf GELU)
  *   3: out_f32 = dZ = C * GELU'(aux) ; out_bf16 = dZ     (aux = Z of the layer)
- * m and n must be multiples of 64, k a multiple of 32 (AF_ERR_UNSUPPORTED
- * otherwise); a and b 16-byte aligned. */
+ * m and n must be multiples of 64, k a multiple of 64 (AF_ERR_UNSUPPORTED
+ * otherwise); a, b and ws 16-byte aligned.
+ * tile: 0 automatic, else BM x BN x BK of one work group's output tile and k
+ * step: 1: 128x128x64, 2: 128x64x64, 3: 64x128x64, 4: 64x64x64, 5-8: the
+ * same tiles with BK 128 (BM must divide m, BN n, BK k).  split_k: 0
+ * automatic, or s in [1, 16] with k a multiple of BK s: the k range is cut
+ * into s parts whose float32 partial sums (s * m * n floats in ws) are added
+ * in part order by a second kernel that applies the epilogue, so results are
+ * reproducible for a given (tile, split_k).  af_gemm_config resolves the
+ * automatic choices for the current device and reports the workspace bytes
+ * (0 without a split; ws may then be NULL). */
+af_status af_gemm_config(int32_t m, int32_t n, int32_t k, int32_t tile, int32_t split_k, int32_t* tile_out,
+                         int32_t* split_out, size_t* ws_bytes);
 af_status af_gemm_bf16(int32_t layout, int32_t epilogue, int32_t m, int32_t n, int32_t k, const void* a,
                        const void* b, const float* bias, const float* aux, float* out_f32, void* out_bf16,
-                       void* stream);
+                       int32_t tile, int32_t split_k, void* ws, size_t ws_bytes, void* stream);
 
-/* out[c] = sum over r of in[r][c] (float32, fixed summation order). */
-af_status af_colsum(int32_t rows, int32_t cols, const float* in, float* out, void* stream);
+/* out[c] = sum over r of in[r][c] (float32): row chunks summed into ws, then
+ * the chunk sums added in chunk order.  ws must hold
+ * af_colsum_workspace_size bytes (device memory). */
+af_status af_colsum_workspace_size(int32_t rows, int32_t cols, size_t* bytes);
+af_status af_colsum(int32_t rows, int32_t cols, const float* in, float* out, void* ws, size_t ws_bytes,
+                    void* stream);
 
 /* One bias-corrected Adam step (step >= 1 is the 1-based step number) on
  * count float32 parameters; param_bf16 (nullable) receives their bfloat16

@@ -62,8 +62,12 @@ SIGNATURES = {
     "af_phase_to_signal": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "af_optim_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(AfLossParams),
                                      ctypes.POINTER(AfAdamParams), _VP, _VP, _SZ, _VP]),
-    "af_gemm_bf16": (ctypes.c_int, [_I32, _I32, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
-    "af_colsum": (ctypes.c_int, [_I32, _I32, _VP, _VP, _VP]),
+    "af_gemm_config": (ctypes.c_int, [_I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                      ctypes.POINTER(_SZ)]),
+    "af_gemm_bf16": (ctypes.c_int, [_I32, _I32, _I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _I32, _I32, _VP,
+                                    _SZ, _VP]),
+    "af_colsum_workspace_size": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(_SZ)]),
+    "af_colsum": (ctypes.c_int, [_I32, _I32, _VP, _VP, _VP, _SZ, _VP]),
     "af_adam_update": (ctypes.c_int, [_I64, _VP, _VP, _VP, _VP, _I32, ctypes.POINTER(AfAdamParams), _VP, _VP]),
     "af_to_bf16": (ctypes.c_int, [_I64, _VP, _VP, _VP]),
     "af_phase_grad": (ctypes.c_int, [_I64, _VP, _VP, _VP, _VP, _VP]),

@@ -459,7 +459,7 @@ const char* af_status_string(af_status s) {
     switch (s) {
         case AF_OK: return "ok";
         case AF_ERR_INVALID_ARG: return "invalid argument";
-        case AF_ERR_UNSUPPORTED: return "unsupported shape (M must be a power of two in [128, 32768] with M >= 2N)";
+        case AF_ERR_UNSUPPORTED: return "unsupported shape (AF: M a power of two in [128, 32768], M >= 2N; GEMM: m, n multiples of 64 and of the tile, k of 32 x split)";
         case AF_ERR_BUDGET: return "workspace does not fit the budget";
         case AF_ERR_HIP: return "HIP runtime error";
         case AF_ERR_WORKSPACE: return "workspace too small";

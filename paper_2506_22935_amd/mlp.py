@@ -23,9 +23,32 @@ def _st():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def gemm(layout, epi, m, n, k, a, b, bias=None, aux=None, out_f32=None, out_bf16=None):
+_WS = {}  # device -> uint8 workspace shared by the split-k GEMMs and column sums (stream-ordered)
+
+
+def _workspace(nbytes, device):
+    key = torch.device(device).index if torch.device(device).index is not None else torch.cuda.current_device()
+    ws = _WS.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
+        _WS[key] = ws
+    return ws
+
+
+def gemm_config(m, n, k, tile=0, split_k=0):
+    """(tile, split_k, workspace bytes) the library uses for this shape."""
+    t, s, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    L.check("af_gemm_config", L.lib().af_gemm_config(m, n, k, tile, split_k, ctypes.byref(t), ctypes.byref(s),
+                                                     ctypes.byref(b)))
+    return t.value, s.value, b.value
+
+
+def gemm(layout, epi, m, n, k, a, b, bias=None, aux=None, out_f32=None, out_bf16=None, tile=0, split_k=0):
+    _, _, need = gemm_config(m, n, k, tile, split_k)
+    ws = _workspace(need, a.device) if need else None
     L.check("af_gemm_bf16", L.lib().af_gemm_bf16(layout, epi, m, n, k, _p(a), _p(b), _p(bias), _p(aux),
-                                                 _p(out_f32), _p(out_bf16), _st()))
+                                                 _p(out_f32), _p(out_bf16), tile, split_k, _p(ws),
+                                                 need, _st()))
 
 
 def to_bf16(x, out=None):
@@ -35,7 +58,10 @@ def to_bf16(x, out=None):
 
 
 def colsum(x, out):
-    L.check("af_colsum", L.lib().af_colsum(x.shape[0], x.shape[1], _p(x), _p(out), _st()))
+    need = ctypes.c_size_t()
+    L.check("af_colsum_workspace_size", L.lib().af_colsum_workspace_size(x.shape[0], x.shape[1], ctypes.byref(need)))
+    ws = _workspace(need.value, x.device)
+    L.check("af_colsum", L.lib().af_colsum(x.shape[0], x.shape[1], _p(x), _p(out), _p(ws), need.value, _st()))
     return out
 
 

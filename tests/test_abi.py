@@ -88,3 +88,27 @@ def test_null_arguments(lib):
     assert lib.af_phase_to_signal(None, None, 5, None) == -1
     sz = ctypes.c_size_t()
     assert lib.af_plan_workspace_size(None, ctypes.byref(sz)) == -1
+
+
+def test_gemm_config_resolution(lib):
+    # automatic tiles and splits (the host rule without a device assumes 256
+    # compute units): a tile that divides the shape, a split that divides k
+    # into whole k tiles, workspace for the partial sums exactly when split
+    from paper_2506_22935_amd import mlp as M
+    bk = {1: 64, 2: 64, 3: 64, 4: 64, 5: 128, 6: 128, 7: 128, 8: 128}
+    bm = {1: 128, 2: 128, 3: 64, 4: 64, 5: 128, 6: 128, 7: 64, 8: 64}
+    bn = {1: 128, 2: 64, 3: 128, 4: 64, 5: 128, 6: 64, 7: 128, 8: 64}
+    for m, n, k in [(4096, 1024, 1024), (4096, 1024, 64), (4096, 256, 1024), (1024, 1024, 4096), (256, 1024, 4096),
+                    (1024, 64, 4096), (128, 64, 192), (64, 64, 64)]:
+        t, s, b = M.gemm_config(m, n, k)
+        assert m % bm[t] == 0 and n % bn[t] == 0 and k % (bk[t] * s) == 0, (m, n, k, t, s)
+        assert b == (s * m * n * 4 if s > 1 else 0)
+    assert M.gemm_config(1024, 1024, 4096)[1] > 1               # few output tiles: k is split
+    assert M.gemm_config(4096, 1024, 1024)[1] == 1              # enough output tiles: no split
+    assert M.gemm_config(256, 384, 768, tile=3, split_k=12) == (3, 12, 12 * 256 * 384 * 4)
+    for bad in [(100, 64, 64, 0, 0), (128, 64, 96, 0, 0), (64, 64, 64, 1, 0), (128, 128, 128, 5, 2),
+                (128, 128, 1024, 0, 17), (128, 128, 128, 9, 0)]:
+        with pytest.raises(L.AfError):
+            M.gemm_config(*bad)
+    n = ctypes.c_size_t()
+    assert lib.af_colsum_workspace_size(4096, 1024, ctypes.byref(n)) == 0 and n.value % (1024 * 4) == 0

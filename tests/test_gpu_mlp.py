@@ -44,7 +44,7 @@ def test_gemm_layouts_exact_small_integers(M):
     # so each layout must match the float64 product exactly
     say("gemm layouts")
     rng = np.random.default_rng(0)
-    m, n, k = 128, 64, 96
+    m, n, k = 128, 64, 192
     A = rng.integers(-4, 5, (m, k)).astype(np.float32)
     Bnk = rng.integers(-4, 5, (n, k)).astype(np.float32)
     ref = A.astype(np.float64) @ Bnk.T.astype(np.float64)
@@ -56,6 +56,68 @@ def test_gemm_layouts_exact_small_integers(M):
     assert np.array_equal(out.cpu().numpy(), ref)
     M.gemm(M.TN, M.E_F32, m, n, k, to16(A.T), to16(Bnk.T), out_f32=out)
     assert np.array_equal(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("layout", [0, 1, 2])
+@pytest.mark.parametrize("tile,split", [(1, 1), (2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1), (8, 1), (1, 2), (2, 4),
+                                        (3, 12), (4, 3), (5, 2), (6, 3), (7, 6), (8, 2)])
+def test_gemm_tiles_and_splits_exact(M, layout, tile, split):
+    # every tile shape and split-k path, several tiles in m and n, integer
+    # operands (exact in float32): the result equals the float64 product
+    say("gemm tile", layout, tile, split)
+    rng = np.random.default_rng(10 + tile + 5 * split)
+    m, n, k = 256, 384, 768
+    A = rng.integers(-4, 5, (m, k)).astype(np.float32)
+    Bnk = rng.integers(-4, 5, (n, k)).astype(np.float32)
+    ref = A.astype(np.float64) @ Bnk.T.astype(np.float64)
+    to16 = lambda x: M.to_bf16(torch.from_numpy(np.ascontiguousarray(x)).cuda())
+    a = to16(A.T) if layout == M.TN else to16(A)
+    b = to16(Bnk) if layout == M.NT else to16(Bnk.T)
+    out = torch.full((m, n), float("nan"), device="cuda")
+    M.gemm(layout, M.E_F32, m, n, k, a, b, out_f32=out, tile=tile, split_k=split)
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("split", [1, 4])
+def test_gemm_split_epilogues(M, split):
+    # the split-k reduction applies every epilogue like the one-pass kernel
+    say("gemm split epilogues", split)
+    rng = np.random.default_rng(20 + split)
+    m, n, k = 128, 256, 512
+    A = rng.standard_normal((m, k)).astype(np.float32)
+    W = (rng.standard_normal((n, k)) * 0.05).astype(np.float32)
+    b = rng.standard_normal(n).astype(np.float32)
+    aux = rng.standard_normal((m, n)).astype(np.float32)
+    a16, w16 = M.to_bf16(torch.from_numpy(A).cuda()), M.to_bf16(torch.from_numpy(W).cuda())
+    Z = O.bf16_round(A).astype(np.float64) @ O.bf16_round(W).T.astype(np.float64)
+    outs = {}
+    for epi in (M.E_F32, M.E_BIAS_F32, M.E_BIAS_GELU, M.E_GELU_BWD):
+        f = torch.empty(m, n, device="cuda")
+        h = torch.empty(m, n, dtype=torch.bfloat16, device="cuda")
+        M.gemm(M.NT, epi, m, n, k, a16, w16, bias=torch.from_numpy(b).cuda(), aux=torch.from_numpy(aux).cuda(),
+               out_f32=f, out_bf16=h, tile=1, split_k=split)
+        outs[epi] = (f.cpu().numpy(), h.float().cpu().numpy())
+    sc = np.max(np.abs(Z))
+    assert np.max(np.abs(outs[M.E_F32][0] - Z)) <= 1e-5 * sc
+    assert np.max(np.abs(outs[M.E_BIAS_F32][0] - (Z + b))) <= 1e-5 * sc
+    assert np.max(np.abs(outs[M.E_BIAS_GELU][0] - (Z + b))) <= 1e-5 * sc
+    g = O.gelu(Z + b)
+    assert np.max(np.abs(outs[M.E_BIAS_GELU][1] - g)) <= 2 ** -8 * np.max(np.abs(g)) + 1e-5 * sc
+    dz = Z * O.gelu_grad(aux.astype(np.float64))
+    assert np.max(np.abs(outs[M.E_GELU_BWD][0] - dz)) <= 1e-5 * np.max(np.abs(dz)) * 4
+    assert np.max(np.abs(outs[M.E_GELU_BWD][1] - dz)) <= 2 ** -8 * np.max(np.abs(dz)) + 1e-5 * np.max(np.abs(dz))
+
+
+@pytest.mark.parametrize("rows,cols", [(1, 64), (7, 300), (4096, 1024), (4096, 256), (513, 64)])
+def test_colsum_vs_float64(M, rows, cols):
+    say("colsum", rows, cols)
+    rng = np.random.default_rng(rows + cols)
+    x = rng.standard_normal((rows, cols)).astype(np.float32)
+    out = torch.empty(cols, device="cuda")
+    M.colsum(torch.from_numpy(x).cuda(), out)
+    ref = x.astype(np.float64).sum(axis=0)
+    # float32 sums of rows terms: error ~ sqrt(rows) 2^-24 |x|
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 8 * np.sqrt(rows) * 2 ** -24 * np.max(np.abs(x)) * 4 + 1e-6
 
 
 def test_gemm_bias_gelu_epilogues(M):
