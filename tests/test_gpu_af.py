@@ -329,7 +329,7 @@ def test_fused_pass_matches_two_passes(af):
 @pytest.mark.parametrize("variant", [1, 5])
 def test_m8192_variants(af, variant):
     # the two kernel variants for M = 8192 (512-thread groups; 32 points per
-    # lane with one wave per SIMD): forward, ISL loss and magnitude backward
+    # lane with one wave per SIMD): forward, ISL loss and ISL + soft-PSL loss
     say("M=8192 variant", variant)
     ns, m = [300, 1000], 8192
     codes = [W.random_code(n, seed=700 + n) for n in ns]
@@ -338,14 +338,19 @@ def test_m8192_variants(af, variant):
     s = packed(codes)
     mag, _, _ = plan.forward(s, mag=True)
     terms, g, _ = plan.loss(s, w_isl=1.0, w_psl=0.0)
+    terms2, g2, _ = plan.loss(s, w_isl=1.0, w_psl=1.0, temp=0.05)
     torch.cuda.synchronize()
     g = g.cpu().numpy().astype(np.complex128)
+    g2 = g2.cpu().numpy().astype(np.complex128)
     for b, n in enumerate(ns):
         sr = ref_c64(codes[b])
         ref = O.loss_and_grad(sr, m, n - 1, O.LossParams(eps=EPS))
         assert np.max(np.abs(plan.grid(mag, b).cpu().numpy() - ref["a"])) <= TOL_A, "mag %d" % b
         assert abs(terms[b, 1].item() - ref["isl"]) <= 1e-4 * ref["isl"]
         check_grad(g[plan.s_offsets[b]:plan.s_offsets[b] + n], ref["g"], "M=8192 v%d wave %d" % (variant, b))
+        ref2 = O.loss_and_grad(sr, m, n - 1, O.LossParams(eps=EPS, w_isl=1.0, w_psl=1.0, temp=0.05))
+        assert abs(terms2[b, 0].item() - ref2["loss"]) <= 1e-4 * abs(ref2["loss"])
+        check_grad(g2[plan.s_offsets[b]:plan.s_offsets[b] + n], ref2["g"], "M=8192 psl v%d wave %d" % (variant, b))
 
 
 def test_weighted_isl_batch(af):
