@@ -214,10 +214,12 @@ af_status build_schedule(af_plan* p) {
         (void)0;
     }
     // reduce blocks: 16 slab subgroups per block when waveforms have many
-    // segments, 4 otherwise
+    // segments, 4 for a few dozen, and one (256 samples per block, every
+    // slab load of a thread in flight at once) for at most 32: the many
+    // short waveforms of a large batch then need a quarter of the blocks
     int max_segs = 0;
     for (int b = 0; b < B; ++b) max_segs = std::max(max_segs, wd[b].seg_count);
-    const int sg_log = max_segs >= 64 ? 4 : 2;
+    const int sg_log = max_segs >= 64 ? 4 : (max_segs > 32 ? 2 : 0);
     for (int b = 0; b < B; ++b)
         for (int c = 0; c < wd[b].n; c += (256 >> sg_log)) rpos.push_back(make_int2(b, c));
 

@@ -77,7 +77,7 @@ struct AfArgs {
 // The slab reduction runs 256-thread blocks over (256 >> sg_log) samples of
 // one waveform; the threads split the waveform's slabs into 2^sg_log
 // interleaved subgroups and add the subgroup sums in a fixed order
-// (deterministic, no atomics).  sg_log is 2 or 4, picked by the planner.
+// (deterministic, no atomics).  sg_log is 0, 2 or 4, picked by the planner.
 
 // One block of the gradient reduction: samples [p0, p0 + 256 >> sg_log) of
 // waveform `wave`, with that waveform's descriptor alongside so that a block
