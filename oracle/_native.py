@@ -40,6 +40,10 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         h.oracle_chi_rows.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp]
         h.oracle_chi_rows.restype = ctypes.c_int
+        h.oracle_chi_circ.argtypes = [ctypes.c_int, dp, dp]
+        h.oracle_chi_circ.restype = ctypes.c_int
+        h.oracle_adjoint_circ.argtypes = [ctypes.c_int, dp, dp, dp]
+        h.oracle_adjoint_circ.restype = ctypes.c_int
         h.oracle_threads.argtypes = []
         h.oracle_threads.restype = ctypes.c_int
         _handle = h
@@ -89,4 +93,27 @@ def adjoint(s, m, max_lag, G):
                               _ptr(G.view(np.float64)), _ptr(g.view(np.float64)))
     if rc != 0:
         raise ValueError("oracle_adjoint rejected n=%d m=%d max_lag=%d" % (n, m, max_lag))
+    return g
+
+
+def chi_circ(s):
+    """Direct-sum periodic AF, rows tau in [0, N), bins k in [0, N)."""
+    s = np.ascontiguousarray(np.asarray(s, dtype=np.complex128))
+    n = s.shape[0]
+    out = np.empty((n, n), dtype=np.complex128)
+    if lib().oracle_chi_circ(n, _ptr(s.view(np.float64)), _ptr(out.view(np.float64))) != 0:
+        raise ValueError("oracle_chi_circ rejected n=%d" % n)
+    return out
+
+
+def adjoint_circ(s, G):
+    """Adjoint of the periodic AF applied to G = dL/d conj(chi_c), [N][N]."""
+    s = np.ascontiguousarray(np.asarray(s, dtype=np.complex128))
+    G = np.ascontiguousarray(np.asarray(G, dtype=np.complex128))
+    n = s.shape[0]
+    assert G.shape == (n, n)
+    g = np.empty(n, dtype=np.complex128)
+    if lib().oracle_adjoint_circ(n, _ptr(s.view(np.float64)), _ptr(G.view(np.float64)),
+                                 _ptr(g.view(np.float64))) != 0:
+        raise ValueError("oracle_adjoint_circ rejected n=%d" % n)
     return g

@@ -29,6 +29,15 @@
  * [2T+1][M] with row i <-> tau = i - T.  Twiddles come from libm cos/sin of
  * the integer-reduced angle (k*n mod M), so each carries one rounding.
  * Returns 0 on success, -1 on a bad argument.
+ *
+ * The periodic (circular) AF of the paper's own Eqs. 2 and 7 and Algorithm 1
+ * takes the lag index modulo N and N Doppler bins:
+ *
+ *   chi_c[tau, k] = sum_{n=0}^{N-1} s[n] * conj(s[(n - tau) mod N]) * exp(-j 2 pi k n / N)
+ *
+ * for tau, k in [0, N), row-major [N][N] with row tau; its adjoint is the
+ * formula above with every sample index taken modulo N and Q_tau over N
+ * bins (oracle_chi_circ, oracle_adjoint_circ).
  */
 #define _USE_MATH_DEFINES
 #include <math.h>
@@ -201,6 +210,110 @@ int oracle_adjoint(int n, int m, int max_lag, const double *s, const double *G, 
                 re += qr * sr - qi * si;
                 im += qr * si + qi * sr;
             }
+        }
+        g[2 * p] = re;
+        g[2 * p + 1] = im;
+    }
+    free(Q);
+    free(w);
+    return 0;
+}
+
+/* w[i] = exp(-j 2 pi i / N), i in [0, N), any N >= 1 */
+static double *twiddle_table_any(int n)
+{
+    double *w = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!w) return NULL;
+    for (int i = 0; i < n; ++i) {
+        double a = -2.0 * M_PI * (double)i / (double)n;
+        w[2 * i] = cos(a);
+        w[2 * i + 1] = sin(a);
+    }
+    return w;
+}
+
+int oracle_chi_circ(int n, const double *s, double *chi)
+{
+    if (n < 1 || !s || !chi) return -1;
+    double *w = twiddle_table_any(n);
+    if (!w) return -1;
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int tau = 0; tau < n; ++tau) {
+        /* r[t] = s[t] * conj(s[(t - tau) mod N]) for every t */
+        double *r = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+        for (int t = 0; t < n; ++t) {
+            const int u = (t - tau + n) % n;
+            double ar = s[2 * t], ai = s[2 * t + 1];
+            double br = s[2 * u], bi = -s[2 * u + 1];
+            r[2 * t] = ar * br - ai * bi;
+            r[2 * t + 1] = ar * bi + ai * br;
+        }
+        double *row = chi + (size_t)tau * (size_t)n * 2;
+        for (int k = 0; k < n; ++k) {
+            double re = 0.0, im = 0.0;
+            for (int t = 0; t < n; ++t) {
+                int64_t idx = ((int64_t)k * (int64_t)t) % n;
+                double wr = w[2 * idx], wi = w[2 * idx + 1];
+                re += r[2 * t] * wr - r[2 * t + 1] * wi;
+                im += r[2 * t] * wi + r[2 * t + 1] * wr;
+            }
+            row[2 * k] = re;
+            row[2 * k + 1] = im;
+        }
+        free(r);
+    }
+    free(w);
+    return 0;
+}
+
+int oracle_adjoint_circ(int n, const double *s, const double *G, double *g)
+{
+    if (n < 1 || !s || !G || !g) return -1;
+    double *w = twiddle_table_any(n);
+    if (!w) return -1;
+    /* Q[tau][t] = sum_k G[tau][k] * exp(+j 2 pi k t / N) */
+    double *Q = (double *)malloc(sizeof(double) * 2 * (size_t)n * (size_t)n);
+    if (!Q) { free(w); return -1; }
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int tau = 0; tau < n; ++tau) {
+        const double *row = G + (size_t)tau * (size_t)n * 2;
+        double *q = Q + (size_t)tau * (size_t)n * 2;
+        for (int t = 0; t < n; ++t) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < n; ++k) {
+                int64_t idx = ((int64_t)k * (int64_t)t) % n;
+                double wr = w[2 * idx], wi = -w[2 * idx + 1];
+                re += row[2 * k] * wr - row[2 * k + 1] * wi;
+                im += row[2 * k] * wi + row[2 * k + 1] * wr;
+            }
+            q[2 * t] = re;
+            q[2 * t + 1] = im;
+        }
+    }
+
+#pragma omp parallel for schedule(static)
+    for (int p = 0; p < n; ++p) {
+        double re = 0.0, im = 0.0;
+        for (int tau = 0; tau < n; ++tau) {
+            const double *q = Q + (size_t)tau * (size_t)n * 2;
+            /* s[p] appears conjugated in r_tau[t] at t = (p + tau) mod N and
+             * plain at t = p: Q_tau[p] * s[(p - tau) mod N] from the plain
+             * factor, conj(Q_tau[(p + tau) mod N]) * s[(p + tau) mod N] from
+             * the conjugated one */
+            const int a = (p - tau + n) % n;
+            double qr = q[2 * p], qi = q[2 * p + 1];
+            double sr = s[2 * a], si = s[2 * a + 1];
+            re += qr * sr - qi * si;
+            im += qr * si + qi * sr;
+            const int b = (p + tau) % n;
+            qr = q[2 * b];
+            qi = -q[2 * b + 1];
+            sr = s[2 * b];
+            si = s[2 * b + 1];
+            re += qr * sr - qi * si;
+            im += qr * si + qi * sr;
         }
         g[2 * p] = re;
         g[2 * p + 1] = im;

@@ -27,6 +27,8 @@ __all__ = [
     "loss_and_grad", "loss_grad_from_chi", "magnitude_backward", "grad_from_upstream", "phase_grad",
     "adam_step", "bf16_round", "gelu", "gelu_grad", "mlp_forward",
     "mlp_backward", "psl_db", "chi_rows_fft", "magnitude_backward_fft",
+    "chi_circular", "circular_lag_distance", "circular_mainlobe_mask", "circular_isl_weights",
+    "loss_and_grad_circular", "magnitude_backward_circular",
 ]
 
 
@@ -133,10 +135,15 @@ def loss_terms(c, E, n, params):
     """Loss value and its pieces from a complex grid c (no gradient)."""
     T = (c.shape[0] - 1) // 2
     m = c.shape[1]
-    p = power(c, E)
-    a = np.sqrt(p + params.eps)
     side = ~mainlobe_mask(m, T, params.h_tau, params.h_k)
     W = isl_weights(n, m, T, params.h_tau, params.h_k, params.u, params.v)
+    return _loss_terms_on(c, E, params, side, W)
+
+
+def _loss_terms_on(c, E, params, side, W):
+    """The loss pieces of a grid c with its sidelobe region and ISL weights."""
+    p = power(c, E)
+    a = np.sqrt(p + params.eps)
     isl = float(np.sum(W * p))
     av = a[side]
     mx = float(av.max())
@@ -167,6 +174,14 @@ def loss_grad_from_chi(s, m, T, c, params):
     n = s.shape[0]
     E = energy(s)
     t = loss_terms(c, E, n, params)
+    G, dLdE = _cell_upstream(t, c, E, params)
+    g = grad_from_upstream(s, m, T, G, dLdE)
+    t.update(g=g, G=G, dLdE=dLdE, chi=c, E=E)
+    return t
+
+
+def _cell_upstream(t, c, E, params):
+    """G = dL/d conj(chi) per cell and dL/dE from the loss pieces t."""
     a, p, side, W = t["a"], t["p"], t["side"], t["W"]
     q = np.zeros_like(a)
     q[side] = np.exp((a[side] - t["lse_max"]) / params.temp) / t["lse_sum"]
@@ -174,9 +189,7 @@ def loss_grad_from_chi(s, m, T, c, params):
     G = coef * c
     dLdE = (-2.0 * params.w_isl * t["isl"] / E
             - params.w_psl * float(np.sum(q * p / (E * a))))
-    g = grad_from_upstream(s, m, T, G, dLdE)
-    t.update(g=g, G=G, dLdE=dLdE, chi=c, E=E)
-    return t
+    return G, dLdE
 
 
 def magnitude_backward(s, m, max_lag, grad_mag, eps):
@@ -207,6 +220,74 @@ def grad_from_upstream(s, m, max_lag, G, dLdE):
 def phase_grad(s, g):
     """dL/dphi for s = exp(j phi): 2 Im(conj(s) * dL/d conj(s))."""
     return 2.0 * np.imag(np.conj(s) * g)
+
+
+# ----------------------------------------------------------------------------
+# the periodic (circular) AF: the paper's own Eqs. 2 and 7 and Algorithm 1
+# ----------------------------------------------------------------------------
+# The lag index wraps modulo N and the Doppler transform has N bins (no zero
+# padding): chi_c[tau, k] = sum_{n<N} s[n] conj(s[(n - tau) mod N])
+# exp(-j 2 pi k n / N), tau, k in [0, N); grids are [N, N] with row tau.
+# Lag tau and lag N - tau are the two signs of one circular lag: the
+# mainlobe is |tau|_c = min(tau, N - tau) <= h_tau, |k_c| <= h_k, with k_c
+# the centred bin over N.
+
+def chi_circular(s):
+    """Periodic AF by its defining sum (C core, direct DFT, no FFT)."""
+    return _native.chi_circ(np.asarray(s, dtype=np.complex128))
+
+
+def circular_lag_distance(n):
+    tau = np.arange(n)
+    return np.minimum(tau, n - tau)
+
+
+def circular_mainlobe_mask(n, h_tau, h_k):
+    return (circular_lag_distance(n)[:, None] <= h_tau) & (np.abs(centred_bins(n))[None, :] <= h_k)
+
+
+def circular_isl_weights(n, h_tau, h_k, u=None, v=None):
+    """As isl_weights with |tau|_c and N bins: u[floor(31 |tau|_c / N)] *
+    v[floor(31 |k_c| / (N/2 + 1))] off the mainlobe (1 without u, v)."""
+    if u is None:
+        W = np.ones((n, n))
+    else:
+        u = np.asarray(u, dtype=np.float64)
+        v = np.asarray(v, dtype=np.float64)
+        iu = (31 * circular_lag_distance(n)) // n
+        iv = (31 * np.abs(centred_bins(n))) // (n // 2 + 1)
+        W = u[iu][:, None] * v[iv][None, :]
+    W[circular_mainlobe_mask(n, h_tau, h_k)] = 0.0
+    return W
+
+
+def loss_and_grad_circular(s, params):
+    """The loss of Sec. 5 on the periodic AF and dL/d conj(s): the per-cell
+    upstream as in loss_and_grad, then the periodic lag-product adjoint."""
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
+    E = energy(s)
+    c = chi_circular(s)
+    side = ~circular_mainlobe_mask(n, params.h_tau, params.h_k)
+    W = circular_isl_weights(n, params.h_tau, params.h_k, params.u, params.v)
+    t = _loss_terms_on(c, E, params, side, W)
+    G, dLdE = _cell_upstream(t, c, E, params)
+    g = _native.adjoint_circ(s, G) + dLdE * s
+    t.update(g=g, G=G, dLdE=dLdE, chi=c, E=E)
+    return t
+
+
+def magnitude_backward_circular(s, grad_mag, eps):
+    """dL/d conj(s) for an upstream dL/da on the periodic magnitude grid."""
+    s = np.asarray(s, dtype=np.complex128)
+    E = energy(s)
+    c = chi_circular(s)
+    p = power(c, E)
+    a = np.sqrt(p + eps)
+    ga = np.asarray(grad_mag, dtype=np.float64)
+    G = ga * c / (2.0 * E * E * a)
+    dLdE = -float(np.sum(ga * p / (E * a)))
+    return _native.adjoint_circ(s, G) + dLdE * s
 
 
 # ----------------------------------------------------------------------------

@@ -442,3 +442,112 @@ def test_chi_rows_is_the_direct_grid():
     s = rand_complex(n, 33)
     taus = [-28, -3, 0, 5, 28]
     assert np.array_equal(O.chi_rows(s, m, taus), O.chi(s, m, T)[[t + T for t in taus]])
+
+
+# --------------------------------------------------------------------------
+# the periodic (circular) AF, Eqs. 2 and 7 and Algorithm 1
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_circular_is_folded_aperiodic(n):
+    # with N Doppler bins, lag tau of the periodic product collects the
+    # aperiodic lags tau and tau - N: chi_c(tau) = chi(tau) + chi(tau - N)
+    s = rand_complex(n, 40 + n)
+    cc = O.chi_circular(s)
+    ca = O.chi(s, n)  # rows tau = -(N-1) .. N-1, M = N bins
+    T = n - 1
+    assert np.max(np.abs(cc[0] - ca[T])) <= 1e-12 * O.energy(s)
+    for tau in range(1, n):
+        assert np.max(np.abs(cc[tau] - (ca[T + tau] + ca[T + tau - n]))) <= 1e-12 * O.energy(s)
+
+
+@pytest.mark.parametrize("n", [7, 16, 24])
+def test_circular_moyal_origin_peak_symmetry(n):
+    s = rand_complex(n, 50 + n)
+    c = O.chi_circular(s)
+    E = O.energy(s)
+    # sum over the N x N grid of |chi_c|^2 = N E^2 (each sample product
+    # |s[n]|^2 |s[n - tau]|^2 summed over tau gives E |s[n]|^2)
+    assert abs(np.sum(np.abs(c) ** 2) - n * E * E) <= 1e-11 * n * E * E
+    assert abs(c[0, 0] - E) <= 1e-12 * E
+    assert np.max(np.abs(c)) <= E * (1 + 1e-12)
+    # |chi_c(-tau, -k)| = |chi_c(tau, k)| with indices modulo N
+    idx = (-np.arange(n)) % n
+    assert np.max(np.abs(np.abs(c[idx][:, idx]) - np.abs(c))) <= 1e-11 * E
+
+
+@pytest.mark.parametrize("n,u", [(16, 3), (64, 5), (15, 2), (13, 4)])
+def test_zadoff_chu_periodic_af_is_a_line(n, u):
+    # Zadoff-Chu: s[n] = exp(j pi u n^2 / N) (N even), exp(j pi u n (n+1) / N)
+    # (N odd), gcd(u, N) = 1.  The periodic lag product is a pure tone of
+    # frequency u tau, so |chi_c(tau, k)| = N where k = u tau mod N, else 0.
+    k = np.arange(n)
+    s = np.exp(1j * np.pi * u * (k * k if n % 2 == 0 else k * (k + 1)) / n)
+    a = np.abs(O.chi_circular(s))
+    line = np.zeros((n, n), dtype=bool)
+    line[np.arange(n), (u * np.arange(n)) % n] = True
+    assert np.max(np.abs(a[line] - n)) <= 1e-10 * n
+    assert np.max(a[~line]) <= 1e-10 * n
+
+
+def test_circular_rectangular_pulse():
+    # s = 1: every periodic lag product is 1, so chi_c(tau, k) = N delta_k
+    n = 32
+    c = O.chi_circular(np.ones(n))
+    ref = np.zeros((n, n))
+    ref[:, 0] = n
+    assert np.max(np.abs(c - ref)) <= 1e-10 * n
+
+
+def test_circular_isl_complement_and_mask():
+    # uniform full-grid ISL = N - sum of mainlobe power (periodic Moyal);
+    # the mainlobe holds (2 h_tau + 1)(2 h_k + 1) cells
+    n = 32
+    s = rand_unimodular(n, 60)
+    params = O.LossParams(w_isl=1.0, h_tau=2, h_k=1)
+    t = O.loss_and_grad_circular(s, params)
+    main = O.circular_mainlobe_mask(n, 2, 1)
+    assert main.sum() == 5 * 3
+    assert main[n - 2, 0] and main[2, n - 1] and not main[3, 0] and not main[0, 2]
+    assert abs(t["isl"] - (n - np.sum(t["p"][main]))) <= 1e-10 * n
+
+
+def _loss_value_circ(s, params):
+    return O.loss_and_grad_circular(s, params)["loss"]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("n", [8, 12])
+def test_circular_loss_grad_finite_differences(case, n):
+    case = dict(case)
+    if case.pop("weighted", False):
+        rng = np.random.default_rng(14)
+        case.update(u=rng.uniform(size=31), v=rng.uniform(size=31))
+    params = O.LossParams(**case)
+    s = rand_complex(n, 70 + n)
+    g = O.loss_and_grad_circular(s, params)["g"]
+    fd = _fd_grad(lambda x: _loss_value_circ(x, params), s)
+    assert np.max(np.abs(g - fd)) <= 1e-6 * max(1.0, np.max(np.abs(fd)))
+
+
+def test_circular_magnitude_backward_finite_differences():
+    n, eps = 10, 1e-12
+    s = rand_complex(n, 80)
+    rng = np.random.default_rng(81)
+    ga = rng.standard_normal((n, n))
+
+    def f(x):
+        c = O.chi_circular(x)
+        return float(np.sum(ga * O.magnitude(c, O.energy(x), eps)))
+
+    g = O.magnitude_backward_circular(s, ga, eps)
+    fd = _fd_grad(f, s)
+    assert np.max(np.abs(g - fd)) <= 1e-6 * max(1.0, np.max(np.abs(fd)))
+
+
+def test_circular_normalised_gradient_orthogonal_to_s():
+    # the normalised losses are invariant to s -> c s (c complex), so
+    # sum_n conj(s_n) g_n = 0 for the periodic AF too
+    s = rand_complex(16, 90)
+    g = O.loss_and_grad_circular(s, O.LossParams(w_isl=1.0, w_psl=1.0, temp=0.1))["g"]
+    assert abs(np.vdot(s, g)) <= 1e-12 * np.linalg.norm(s) * np.linalg.norm(g) * 16
