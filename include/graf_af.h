@@ -62,16 +62,27 @@ typedef enum {
     AF_ERR_NO_DEVICE = -6    /* no usable gfx950 device */
 } af_status;
 
+/* af_wave.flags: the periodic (circular) AF of Sec. 3 Eq. 2 and Sec. 4.1
+ * Eq. 7 / Algorithm 1 instead of the aperiodic one:
+ *   chi[tau, k] = sum_{n<N} s[n] conj(s[(n - tau) mod N]) e^{-j 2 pi k n / N}
+ * for tau, k in [0, N): requires m = n, max_lag = -1 or n - 1 and n a power
+ * of two in [64, 4096] (AF_ERR_UNSUPPORTED otherwise); the grids are
+ * [N][N] with row tau (no centring), the mainlobe is min(tau, N - tau) <=
+ * h_tau, |k_c| <= h_k with k_c centred over N bins (h_tau, h_k <= N/2), and
+ * the shaping weights use min(tau, N - tau) and N/2 + 1 in place of |tau| and
+ * M/2 + 1.  Every call supports both kinds, also mixed in one batch. */
+#define AF_WAVE_PERIODIC 1
+
 /* One waveform of a batch. */
 typedef struct {
     int32_t n;        /* samples, >= 1 */
-    int32_t m;        /* Doppler bins: power of two with 2n <= m, 128 <= m <= 32768 */
+    int32_t m;        /* Doppler bins: power of two with 2n <= m, 128 <= m <= 32768 (periodic: m = n) */
     int32_t max_lag;  /* T: lags -T..T with 0 <= T <= n - 1; -1 means n - 1 */
     int32_t h_tau;    /* mainlobe half-width in lags (built-in loss only) */
     int32_t h_k;      /* mainlobe half-width in Doppler bins (built-in loss only) */
-    int32_t reserved; /* must be 0 */
+    int32_t flags;    /* 0, or AF_WAVE_PERIODIC */
     int64_t s_off;    /* first complex64 sample of this waveform in the packed input */
-    int64_t grid_off; /* first element of this waveform's [2T+1][M] grids */
+    int64_t grid_off; /* first element of this waveform's grids ([2T+1][M], periodic [N][N]) */
 } af_wave;
 
 /* Plan options (zero-initialise, then set what you need). */

@@ -27,7 +27,7 @@ __all__ = [
     "loss_and_grad", "loss_grad_from_chi", "magnitude_backward", "grad_from_upstream", "phase_grad",
     "adam_step", "bf16_round", "gelu", "gelu_grad", "mlp_forward",
     "mlp_backward", "psl_db", "chi_rows_fft", "magnitude_backward_fft",
-    "chi_circular", "circular_lag_distance", "circular_mainlobe_mask", "circular_isl_weights",
+    "chi_circular", "chi_circular_rows", "circular_lag_distance", "circular_mainlobe_mask", "circular_isl_weights",
     "loss_and_grad_circular", "magnitude_backward_circular",
 ]
 
@@ -235,6 +235,21 @@ def phase_grad(s, g):
 def chi_circular(s):
     """Periodic AF by its defining sum (C core, direct DFT, no FFT)."""
     return _native.chi_circ(np.asarray(s, dtype=np.complex128))
+
+
+def chi_circular_rows(s, taus):
+    """Rows tau of the periodic AF for N a power of two, from the aperiodic
+    direct sums with M = N: lag tau of the periodic product collects the
+    aperiodic lags tau and tau - N (pinned against chi_circular)."""
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
+    out = np.empty((len(taus), n), dtype=np.complex128)
+    for i, tau in enumerate(taus):
+        tau = int(tau) % n
+        out[i] = chi_rows(s, n, [tau])[0]
+        if tau > 0:
+            out[i] += chi_rows(s, n, [tau - n])[0]
+    return out
 
 
 def circular_lag_distance(n):

@@ -16,9 +16,12 @@ STATUS = {0: "AF_OK", -1: "AF_ERR_INVALID_ARG", -2: "AF_ERR_UNSUPPORTED", -3: "A
           -4: "AF_ERR_HIP", -5: "AF_ERR_WORKSPACE", -6: "AF_ERR_NO_DEVICE"}
 
 
+AF_WAVE_PERIODIC = 1  # af_wave.flags: the periodic (circular) AF
+
+
 class AfWave(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("max_lag", ctypes.c_int32),
-                ("h_tau", ctypes.c_int32), ("h_k", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("h_tau", ctypes.c_int32), ("h_k", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("s_off", ctypes.c_int64), ("grid_off", ctypes.c_int64)]
 
 

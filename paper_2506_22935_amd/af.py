@@ -34,15 +34,18 @@ def _need(t, dtype, name):
 class Plan:
     """A batch layout: per waveform N, M, lag half-width T and mainlobe
     half-widths.  Waveforms pack back to back in s; grids pack back to back.
+    periodic (bool or one per waveform): the circular AF of N = M bins with
+    [N][N] grids (row tau in [0, N)) instead of the aperiodic [2T+1][M].
     """
 
     def __init__(self, lengths, ms, max_lags=None, h_tau=1, h_k=1, eps=1e-12, store_mode=0,
-                 budget_bytes=0, variant=-1, segment_iters=0, loss_passes=0):
+                 budget_bytes=0, variant=-1, segment_iters=0, loss_passes=0, periodic=False):
         lengths = [int(n) for n in lengths]
         ms = [int(m) for m in ms]
         B = len(lengths)
         if len(ms) != B:
             raise ValueError("lengths and ms differ in length")
+        periodic = [bool(periodic)] * B if isinstance(periodic, (bool, int)) else [bool(x) for x in periodic]
         max_lags = [n - 1 for n in lengths] if max_lags is None else [int(t) for t in max_lags]
         max_lags = [n - 1 if t < 0 else t for n, t in zip(lengths, max_lags)]
         h_tau = [int(h_tau)] * B if isinstance(h_tau, int) else [int(x) for x in h_tau]
@@ -53,14 +56,17 @@ class Plan:
         for b in range(B):
             w = waves[b]
             w.n, w.m, w.max_lag = lengths[b], ms[b], max_lags[b]
-            w.h_tau, w.h_k, w.reserved = h_tau[b], h_k[b], 0
+            w.h_tau, w.h_k = h_tau[b], h_k[b]
+            w.flags = L.AF_WAVE_PERIODIC if periodic[b] else 0
             w.s_off, w.grid_off = s_off, g_off
+            rows = lengths[b] if periodic[b] else 2 * max_lags[b] + 1
             self.s_offsets.append(s_off)
             self.grid_offsets.append(g_off)
-            self.rows.append(2 * max_lags[b] + 1)
+            self.rows.append(rows)
             s_off += lengths[b]
-            g_off += (2 * max_lags[b] + 1) * ms[b]
+            g_off += rows * ms[b]
         self.batch, self.lengths, self.ms, self.max_lags = B, lengths, ms, max_lags
+        self.periodic = periodic
         self.total_samples, self.total_cells = s_off, g_off
         opts = L.AfPlanOpts(eps=float(eps), store_mode=int(store_mode), budget_bytes=int(budget_bytes),
                             variant=int(variant), segment_iters=int(segment_iters),
@@ -101,7 +107,8 @@ class Plan:
         return self._ws
 
     def grid(self, flat, b):
-        """View of waveform b's [2T+1, M] grid inside a packed grid tensor."""
+        """View of waveform b's grid ([2T+1, M], periodic [N, N]) inside a
+        packed grid tensor."""
         o = self.grid_offsets[b]
         return flat[o:o + self.rows[b] * self.ms[b]].view(self.rows[b], self.ms[b])
 

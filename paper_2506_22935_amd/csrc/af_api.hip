@@ -25,6 +25,8 @@ namespace {
 constexpr int kMaxLds = 160 * 1024;
 constexpr int kMinM = 128;
 constexpr int kMaxM = 32768;
+constexpr int kMinCircN = 64;   // periodic AF: N = M, the split variants' sizes
+constexpr int kMaxCircN = 4096;
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 int ilog2(int64_t x) {
@@ -50,7 +52,8 @@ struct af_plan {
     // schedule: one class per distinct M, each with its own kernel variant,
     // slice of the execution order, grid and work-queue counters
     struct Class {
-        int lg = 0;          // log2(M/2)
+        int lg = 0;          // log2(M/2) (the kernel's M: 2N for a periodic class)
+        int circ = 0;        // periodic waveforms
         int variant = -1;
         int begin = 0, count = 0;  // slice of the execution order
         int grid[graf::kNumModes] = {};
@@ -91,25 +94,37 @@ void free_tables(af_plan* p) {
     p->d_tw = nullptr;
 }
 
-// Can variant v run transform size 2^lg for waveforms up to max_n samples?
-bool variant_fits(int v, int lg, int max_n) {
+// Periodic (circular) waveforms: N = M bins, run as the even half of the
+// kernel's M = 2N split with lag pairs tau, N - tau for tau in [0, N/2].
+bool is_circ(const af_wave& w) { return (w.flags & AF_WAVE_PERIODIC) != 0; }
+int kernel_m(const af_wave& w) { return is_circ(w) ? 2 * w.n : w.m; }
+int pair_lags(const af_wave& w) { return is_circ(w) ? w.n / 2 : w.max_lag; }
+int64_t grid_cells(const af_wave& w) {
+    return is_circ(w) ? (int64_t)w.n * w.n : (int64_t)(2 * w.max_lag + 1) * w.m;
+}
+
+// Can variant v run transform size 2^lg (periodic or not) for waveforms up
+// to max_n samples?
+bool variant_fits(int v, int lg, int max_n, int circ) {
     const VariantInfo vi = graf::variant_info(v, lg);
-    if (!vi.fits) return false;
+    if (!vi.fits || (circ && !vi.circ)) return false;
     const int lds = vi.fft_lds + (vi.s_lds ? 8 * (2 << lg) : 0);  // samples zero-padded to M
     return lds <= kMaxLds;
 }
 
-int default_variant(int lg, int max_n) {
+int default_variant(int lg, int max_n, int circ) {
     const int order[] = {0, 1, 2};
     for (int v : order)
-        if (variant_fits(v, lg, max_n)) return v;
+        if (variant_fits(v, lg, max_n, circ)) return v;
     return -1;
 }
 
-int lags_per_iter(const VariantInfo& vi, int m) {
+// lags per iteration of a work group: one per lane-group pair (split
+// halves), one per lane group (halves in turn, or periodic)
+int lags_per_iter(const VariantInfo& vi, int m, int circ) {
     const int L = (m / 2) / vi.p;
     const int groups = vi.wgs / L;
-    return vi.split ? groups / 2 : groups;
+    return (vi.split && !circ) ? groups / 2 : groups;
 }
 
 af_status hip_fail() { return AF_ERR_HIP; }
@@ -119,35 +134,36 @@ af_status hip_fail() { return AF_ERR_HIP; }
 // opt_variant if it fits, else the default for that size.
 af_status build_schedule(af_plan* p) {
     const int B = p->batch;
-    // classes by transform size, largest first
-    std::vector<int> lgs;
-    for (const af_wave& w : p->waves) lgs.push_back(ilog2(w.m) - 1);
-    std::sort(lgs.begin(), lgs.end());
-    lgs.erase(std::unique(lgs.begin(), lgs.end()), lgs.end());
-    std::reverse(lgs.begin(), lgs.end());
-    const int C = (int)lgs.size();
+    // classes by (transform size, periodic), largest first; key 2 lg + circ
+    std::vector<int> keys;
+    for (const af_wave& w : p->waves) keys.push_back(2 * (ilog2(kernel_m(w)) - 1) + (is_circ(w) ? 1 : 0));
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    std::reverse(keys.begin(), keys.end());
+    const int C = (int)keys.size();
     if ((int)p->forced.size() != C) p->forced.assign(C, -1);
     std::vector<af_plan::Class> cls(C);
     std::vector<int> cls_of_wave(B);
     for (int b = 0; b < B; ++b) {
-        const int lg = ilog2(p->waves[b].m) - 1;
-        const int c = (int)(std::find(lgs.begin(), lgs.end(), lg) - lgs.begin());
+        const int key = 2 * (ilog2(kernel_m(p->waves[b])) - 1) + (is_circ(p->waves[b]) ? 1 : 0);
+        const int c = (int)(std::find(keys.begin(), keys.end(), key) - keys.begin());
         cls_of_wave[b] = c;
-        cls[c].lg = lg;
+        cls[c].lg = key >> 1;
+        cls[c].circ = key & 1;
         cls[c].max_n = std::max(cls[c].max_n, p->waves[b].n);
     }
     int total_slots = 0;
     for (int c = 0; c < C; ++c) {
         af_plan::Class& k = cls[c];
         int v = p->forced[c];
-        if (v < 0 && p->opt_variant >= 0 && variant_fits(p->opt_variant, k.lg, k.max_n)) v = p->opt_variant;
-        if (v < 0) v = default_variant(k.lg, k.max_n);
-        if (v < 0 || !variant_fits(v, k.lg, k.max_n)) return AF_ERR_UNSUPPORTED;
+        if (v < 0 && p->opt_variant >= 0 && variant_fits(p->opt_variant, k.lg, k.max_n, k.circ)) v = p->opt_variant;
+        if (v < 0) v = default_variant(k.lg, k.max_n, k.circ);
+        if (v < 0 || !variant_fits(v, k.lg, k.max_n, k.circ)) return AF_ERR_UNSUPPORTED;
         k.variant = v;
         const VariantInfo vi = graf::variant_info(v, k.lg);
         k.dyn_lds = vi.fft_lds + (vi.s_lds ? 8 * (2 << k.lg) : 0);  // samples zero-padded to M
         for (int mode = 0; mode < graf::kNumModes; ++mode) {
-            const int r = graf::variant_max_resident(mode, v, k.lg, k.dyn_lds);
+            const int r = graf::variant_max_resident(mode, v, k.lg, k.circ, k.dyn_lds);
             if (r <= 0) return AF_ERR_UNSUPPORTED;
             k.grid[mode] = r * p->cus;  // capped by the segment count below
         }
@@ -162,9 +178,11 @@ af_status build_schedule(af_plan* p) {
         const af_wave& w = p->waves[b];
         const af_plan::Class& k = cls[cls_of_wave[b]];
         const VariantInfo vi = graf::variant_info(k.variant, k.lg);
-        lpi[b] = lags_per_iter(vi, w.m);
-        iters[b] = (w.max_lag + 1 + lpi[b] - 1) / lpi[b];
-        cost_iter[b] = (double)lpi[b] * w.m * ilog2(w.m);
+        const int mk = kernel_m(w);
+        lpi[b] = lags_per_iter(vi, mk, k.circ);
+        iters[b] = (pair_lags(w) + 1 + lpi[b] - 1) / lpi[b];
+        // a periodic lag runs one half-size transform, an aperiodic pair two
+        cost_iter[b] = (double)lpi[b] * (k.circ ? mk / 2 : mk) * ilog2(mk);
         total += iters[b] * cost_iter[b];
     }
     const double target = total / (2.0 * std::max(1, total_slots));
@@ -180,10 +198,13 @@ af_status build_schedule(af_plan* p) {
                                        : std::max(1, (int)std::lround(target / std::max(cost_iter[b], 1.0)));
         per = std::min(per, iters[b]);
         WaveDesc& d = wd[b];
+        const int mk = kernel_m(w);
         d.n = w.n;
-        d.m = w.m;
-        d.T = w.max_lag;
-        d.log2m = ilog2(w.m);
+        d.m = mk;
+        d.T = pair_lags(w);
+        d.log2m = ilog2(mk);
+        d.circ = is_circ(w) ? 1 : 0;
+        d.moyal = is_circ(w) ? w.n : mk;
         d.s_off = w.s_off;
         d.grid_off = w.grid_off;
         d.store_off = store_elems;
@@ -192,12 +213,12 @@ af_status build_schedule(af_plan* p) {
         d.h_tau = w.h_tau;
         d.h_k = w.h_k;
         d.band_off = 62 * b;
-        d.full_window = w.max_lag == w.n - 1 ? 1 : 0;
+        d.full_window = (is_circ(w) || w.max_lag == w.n - 1) ? 1 : 0;
         for (int it = 0; it < iters[b]; it += per) {
             SegDesc sd;
             sd.wave = b;
             sd.tau_begin = it * lpi[b];
-            sd.tau_end = std::min(w.max_lag + 1, (it + per) * lpi[b]);
+            sd.tau_end = std::min(pair_lags(w) + 1, (it + per) * lpi[b]);
             sd.rec = (int)segs.size();
             segs.push_back(sd);
             seg_cost.push_back(std::min(per, iters[b] - it) * cost_iter[b]);
@@ -210,7 +231,8 @@ af_status build_schedule(af_plan* p) {
             if (segs[i].tau_begin <= w.h_tau) ++d.isl_segs;
         d.slab2_off = slab2_elems;
         slab2_elems += (int64_t)d.isl_segs * w.n;
-        store_elems += (int64_t)(w.max_lag + 1) * w.m;
+        // spectra per lag pair: M (two halves), or N for a periodic lag
+        store_elems += (int64_t)(pair_lags(w) + 1) * (is_circ(w) ? w.n : w.m);
         (void)0;
     }
     // reduce blocks: 16 slab subgroups per block when waveforms have many
@@ -314,11 +336,17 @@ af_status validate_plan_inputs(int32_t batch, const af_wave* waves, const af_pla
     if (opts->loss_passes < 0 || opts->loss_passes > 1) return AF_ERR_INVALID_ARG;
     for (int b = 0; b < batch; ++b) {
         const af_wave& w = waves[b];
-        if (w.n < 1 || w.s_off < 0 || w.grid_off < 0 || w.h_tau < 0 || w.h_k < 0 || w.reserved != 0)
+        if (w.n < 1 || w.s_off < 0 || w.grid_off < 0 || w.h_tau < 0 || w.h_k < 0 || (w.flags & ~AF_WAVE_PERIODIC))
             return AF_ERR_INVALID_ARG;
         if (w.grid_off % 4 != 0) return AF_ERR_INVALID_ARG;  // rows move as 16-byte vectors
         const int T = w.max_lag < 0 ? w.n - 1 : w.max_lag;
         if (w.max_lag < -1 || T > w.n - 1) return AF_ERR_INVALID_ARG;
+        if (is_circ(w)) {
+            // periodic: N = M bins, a power of two in [64, 4096], every lag
+            if (w.m != w.n || T != w.n - 1 || w.h_tau > w.n / 2 || w.h_k > w.n / 2) return AF_ERR_INVALID_ARG;
+            if (!is_pow2(w.n) || w.n < kMinCircN || w.n > kMaxCircN) return AF_ERR_UNSUPPORTED;
+            continue;
+        }
         if (!is_pow2(w.m) || w.m < kMinM || w.m > kMaxM || w.m < 2 * (int64_t)w.n) return AF_ERR_UNSUPPORTED;
     }
     return AF_OK;
@@ -395,7 +423,7 @@ af_status launch(const af_plan* p, int mode, const AfArgs& a0, hipStream_t st, i
             a.w0 = p->wave_desc[k.single_wave];
             a.w0_index = k.single_wave;
         }
-        hipError_t e = graf::launch_af(mode, k.variant, k.lg, a, k.grid[mode], k.dyn_lds, st);
+        hipError_t e = graf::launch_af(mode, k.variant, k.lg, k.circ, a, k.grid[mode], k.dyn_lds, st);
         if (e != hipSuccess) return AF_ERR_HIP;
     }
     return AF_OK;
@@ -493,9 +521,9 @@ af_status af_plan_create(int32_t batch, const af_wave* waves, const af_plan_opts
     int64_t mmax = 0;
     for (af_wave& w : p->waves) {
         if (w.max_lag < 0) w.max_lag = w.n - 1;
-        mmax = std::max<int64_t>(mmax, w.m);
+        mmax = std::max<int64_t>(mmax, kernel_m(w));
         p->max_n = std::max(p->max_n, w.n);
-        p->cells += (int64_t)(2 * w.max_lag + 1) * w.m;
+        p->cells += grid_cells(w);
     }
     p->eps = opts->eps;
     p->store_mode = opts->store_mode;
@@ -715,7 +743,7 @@ af_status af_plan_autotune(af_plan* p, const void* s, void* ws, size_t ws_bytes,
     for (int c = 0; c < C && rc == AF_OK; ++c) {
         float best_t = 0.f;
         for (int v = 0; v < graf::kNumVariants; ++v) {
-            if (!variant_fits(v, p->classes[c].lg, p->classes[c].max_n)) continue;
+            if (!variant_fits(v, p->classes[c].lg, p->classes[c].max_n, p->classes[c].circ)) continue;
             p->forced[c] = v;
             if (build_schedule(p) != AF_OK || p->ws_total > ws_bytes) continue;
             const WsView view = ws_view(p, ws);

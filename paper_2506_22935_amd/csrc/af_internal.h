@@ -20,6 +20,10 @@ struct WaveDesc {
                               // taken as M - (mainlobe power), Moyal's identity
     int isl_segs;             // its segments that hold mainlobe lags (tau <= h_tau)
     int64_t slab2_off;        // first complex64 of their second slabs
+    int circ;                 // periodic AF: N = M/2 bins, lag pairs tau, N - tau
+                              // for tau in [0, T = N/2], grid [N][N]
+    int moyal;                // sum of p over the whole grid with a full window:
+                              // M (aperiodic) or N (periodic)
 };
 
 // One work item: lags [tau_begin, tau_end) (tau >= 0) of one waveform.
@@ -124,10 +128,12 @@ hipError_t launch_phase_to_signal(const float* phi, float2* s, int64_t count, hi
 // when s_lds, 8 bytes per sample of the longest waveform it runs.
 struct VariantInfo {
     int lo, hi, p, split, wgs, s_lds, fits, fft_lds, nacc;
+    int circ;  // has periodic-AF instances
 };
 constexpr int kNumVariants = 6;
 VariantInfo variant_info(int v, int lg);
-int variant_max_resident(int mode, int variant, int lg, int dyn_lds_bytes);
-hipError_t launch_af(int mode, int variant, int lg, const AfArgs& a, int grid, int dyn_lds_bytes, hipStream_t st);
+int variant_max_resident(int mode, int variant, int lg, int circ, int dyn_lds_bytes);
+hipError_t launch_af(int mode, int variant, int lg, int circ, const AfArgs& a, int grid, int dyn_lds_bytes,
+                     hipStream_t st);
 
 }  // namespace graf

@@ -115,8 +115,9 @@ __device__ __forceinline__ float total_dlde(const ReduceArgs& a, const WaveTotal
 }
 // the loss terms (one thread per waveform writes them)
 __device__ __forceinline__ float4 loss_terms(const ReduceArgs& a, const WaveDesc& w, const WaveTotals& t, float E) {
-    // complement waveforms carry ISL - M (Moyal: the full grid holds M E^2)
-    const double isl = t.isl_raw + ((a.uniform_w && w.full_window) ? (double)w.m : 0.0);
+    // complement waveforms carry ISL - M (Moyal: the full grid holds M E^2;
+    // N E^2 for the periodic AF)
+    const double isl = t.isl_raw + ((a.uniform_w && w.full_window) ? (double)w.moyal : 0.0);
     const float soft = (t.lse_s > 0.0) ? (float)((double)t.lse_m + (double)a.temp * log(t.lse_s)) : 0.f;
     const double loss = (double)a.w_isl * isl + (a.w_psl != 0.f ? (double)a.w_psl * (double)soft : 0.0);
     return make_float4((float)loss, (float)isl, soft, E);

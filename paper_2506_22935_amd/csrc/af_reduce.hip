@@ -32,12 +32,12 @@ __global__ __launch_bounds__(256) void phase_to_signal_kernel(const float* phi, 
 }
 
 // ------------------------------------------------------------ launchers --
-void* variant_kernel_0(int mode, int lg);
-void* variant_kernel_1(int mode, int lg);
-void* variant_kernel_2(int mode, int lg);
-void* variant_kernel_3(int mode, int lg);
-void* variant_kernel_4(int mode, int lg);
-void* variant_kernel_5(int mode, int lg);
+void* variant_kernel_0(int mode, int lg, int circ);
+void* variant_kernel_1(int mode, int lg, int circ);
+void* variant_kernel_2(int mode, int lg, int circ);
+void* variant_kernel_3(int mode, int lg, int circ);
+void* variant_kernel_4(int mode, int lg, int circ);
+void* variant_kernel_5(int mode, int lg, int circ);
 VariantInfo variant_info_0(int lg);
 VariantInfo variant_info_1(int lg);
 VariantInfo variant_info_2(int lg);
@@ -57,21 +57,21 @@ VariantInfo variant_info(int v, int lg) {
     return VariantInfo{};
 }
 
-static void* kernel_for(int mode, int variant, int lg) {
+static void* kernel_for(int mode, int variant, int lg, int circ) {
     switch (variant) {
-        case 0: return variant_kernel_0(mode, lg);
-        case 1: return variant_kernel_1(mode, lg);
-        case 2: return variant_kernel_2(mode, lg);
-        case 3: return variant_kernel_3(mode, lg);
-        case 4: return variant_kernel_4(mode, lg);
-        case 5: return variant_kernel_5(mode, lg);
+        case 0: return variant_kernel_0(mode, lg, circ);
+        case 1: return variant_kernel_1(mode, lg, circ);
+        case 2: return variant_kernel_2(mode, lg, circ);
+        case 3: return variant_kernel_3(mode, lg, circ);
+        case 4: return variant_kernel_4(mode, lg, circ);
+        case 5: return variant_kernel_5(mode, lg, circ);
     }
     return nullptr;
 }
 
-int variant_max_resident(int mode, int variant, int lg, int dyn_lds_bytes) {
+int variant_max_resident(int mode, int variant, int lg, int circ, int dyn_lds_bytes) {
     const VariantInfo vi = variant_info(variant, lg);
-    void* k = vi.fits ? kernel_for(mode, variant, lg) : nullptr;
+    void* k = (vi.fits && (!circ || vi.circ)) ? kernel_for(mode, variant, lg, circ) : nullptr;
     if (!k) return 0;
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_lds_bytes) != hipSuccess) return 0;
     int blocks = 0;
@@ -79,9 +79,10 @@ int variant_max_resident(int mode, int variant, int lg, int dyn_lds_bytes) {
     return blocks;
 }
 
-hipError_t launch_af(int mode, int variant, int lg, const AfArgs& a, int grid, int dyn_lds_bytes, hipStream_t st) {
+hipError_t launch_af(int mode, int variant, int lg, int circ, const AfArgs& a, int grid, int dyn_lds_bytes,
+                     hipStream_t st) {
     const VariantInfo vi = variant_info(variant, lg);
-    void* k = vi.fits ? kernel_for(mode, variant, lg) : nullptr;
+    void* k = (vi.fits && (!circ || vi.circ)) ? kernel_for(mode, variant, lg, circ) : nullptr;
     if (!k || grid <= 0) return hipErrorInvalidValue;
     void* args[] = {(void*)&a};
     return hipLaunchKernel(k, dim3(grid), dim3(vi.wgs), args, (size_t)dyn_lds_bytes, st);

@@ -113,8 +113,10 @@ struct WaveState {
 // with twl != nullptr also copy this size's twiddles w_M^i (i < 2 MH) from the
 // global table; for the loss backward also merge the forward pass records
 // into the soft-PSL normaliser.  Every global load is issued before the first
-// barrier, so one memory round trip covers all of them.
-template <int MODE, int WGS, int MH>
+// barrier, so one memory round trip covers all of them.  CIRC (periodic AF,
+// N = MH): the samples are staged twice, s_lds[p] = s[p mod N] for p < 2 N,
+// so that the lag product reads s[(m + tau) mod N] as s_lds[m + tau].
+template <int MODE, int WGS, int MH, bool CIRC = false>
 __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2* s_lds, bool s_in_lds,
                            double* scratch, WaveState& st, float2* twl, int twsh) {
     constexpr int NPT = (MH + WGS - 1) / WGS;
@@ -156,7 +158,16 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
     float e = 0.f;
 #pragma unroll
     for (int i = 0; i < NPT; ++i) e += cabs2(sx[i]);
-    if (s_in_lds) {
+    if (CIRC && s_in_lds) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int p = tid + i * WGS;
+            if (p < MH) {
+                s_lds[p] = sx[i];
+                s_lds[p + MH] = sx[i];
+            }
+        }
+    } else if (s_in_lds) {
         // 2 MH entries, zero from N on: every lag product index m + tau
         // (m < MH, tau <= N) reads a sample or a zero
 #pragma unroll
@@ -258,16 +269,24 @@ __device__ void stage_split_twiddles(const AfArgs& a, float2* hi, float2* lo, in
     __syncthreads();
 }
 
-template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, typename Tw>
+// CIRC: the periodic AF of N = MH samples (lag index modulo N, N Doppler
+// bins).  Its N-point spectrum of the lag product is the even half of the
+// aperiodic M = 2N split, so every lane group takes a lag of its own; one
+// transform gives rows tau and N - tau of the [N][N] grid (tau = 0 and
+// tau = N/2 give one row each), and the lag product and its adjoint index
+// samples modulo N.
+template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, bool CIRC, typename Tw>
 __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, const Tw& twl,
                                                 const float2* s_lds, bool s_in_lds, double* scratch,
                                                 const WaveState& ws) {
     constexpr int L = MH / P;
     constexpr int G = WGS / L;
-    constexpr int LPI = SPLIT ? G / 2 : G;
+    constexpr int LPI = (SPLIT && !CIRC) ? G / 2 : G;  // lags per iteration
     constexpr int BUF = LdsSize<MH>::value;
-    constexpr int TPL = SPLIT ? 2 * L : L;  // threads per lag
+    constexpr int TPL = (SPLIT && !CIRC) ? 2 * L : L;  // threads per lag
     constexpr int M_ = 2 * MH;
+    constexpr int RL = CIRC ? MH : M_;  // grid row length (Doppler bins)
+    static_assert(!CIRC || SPLIT, "periodic AF needs a split variant");
     constexpr bool NEEDS_INV = MODE != MODE_FWD;
     constexpr bool HAS_MAG_OUT = MODE == MODE_FWD || MODE == MODE_FUSED_ISL || MODE == MODE_LOSS;
     constexpr bool FWD_SUMS = MODE == MODE_FWD || MODE == MODE_LOSS;  // soft-PSL partials
@@ -277,11 +296,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     int tid = threadIdx.x;
     const int grp = tid / L;
     int l = tid - grp * L;
-    const int lam = SPLIT ? (grp >> 1) : grp;
-    const int hsel = SPLIT ? ((L % 64 == 0) ? __builtin_amdgcn_readfirstlane(grp & 1) : (grp & 1)) : 0;
+    const int lam = (SPLIT && !CIRC) ? (grp >> 1) : grp;
+    const int hsel = (SPLIT && !CIRC) ? ((L % 64 == 0) ? __builtin_amdgcn_readfirstlane(grp & 1) : (grp & 1)) : 0;
     const int t2 = tid - lam * TPL;  // thread index among the lag's threads
     float2* buf = lds + grp * BUF;
-    float* rowbuf = reinterpret_cast<float*>(lds + (SPLIT ? 2 * lam : lam) * BUF);
+    float* rowbuf = reinterpret_cast<float*>(lds + ((SPLIT && !CIRC) ? 2 * lam : lam) * BUF);
 
     const WaveDesc w = a.single ? a.w0 : a.waves[sg.wave];
     const int N = w.n, T = w.T;
@@ -337,6 +356,25 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     // that the register accumulators stay in registers)
     auto gather = [&](const float2* qa, bool two, int tj, auto to_dst, float2* gdst) {
         constexpr bool TO_DST = decltype(to_dst)::value;
+        if constexpr (CIRC) {
+            // conj(Q[p]) s[(p + tj) mod N] + Q[(p - tj) mod N] s[(p - tj) mod N]
+            // (samples staged twice: s_lds[p + tj] is s[(p + tj) mod N])
+#pragma unroll
+            for (int i = 0; i < NACC; ++i) {
+                const int p = tid + WGS * i;
+                if (p < N) {
+                    float2 sum = TO_DST ? gdst[p] : acc[TO_DST ? 0 : i];
+                    sum = cadd(sum, cmul(cconj(qa[lds_index(p)]), sv[p + tj]));
+                    const int m = p >= tj ? p - tj : p - tj + N;
+                    sum = cadd(sum, cmul(qa[lds_index(m)], sv[m]));
+                    if (TO_DST)
+                        gdst[p] = sum;
+                    else
+                        acc[TO_DST ? 0 : i] = sum;
+                }
+            }
+            return;
+        }
         const int Sj = N - tj;
 #pragma unroll
         for (int i = 0; i < NACC; ++i) {
@@ -384,7 +422,18 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 
     // Y' of lag tau, half h, in the exit layout v[q] = Y'[2 (l + qL) + h]
     auto lag_spectrum = [&](float2* v, int h, int tau, bool active) {
-        if (s_in_lds) {
+        if (CIRC) {
+            // r'[m] = s[(m + tau) mod N] conj(s[m]), m < N = MH; an inactive
+            // lag (tau may lie past N/2 + 1) reads lag 0 and gives zero
+            const int tz = active ? tau : 0;
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                const int m = l + r * L;
+                const float2 x = cmulc(sv[m + tz], sv[m]);
+                v[r] = active ? x : make_float2(0.f, 0.f);
+                if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+        } else if (s_in_lds) {
             // zero-padded samples: r'[m] = 0 for m >= N - tau comes out of
             // the product itself; an inactive lag reads zeros
             const int tz = active ? tau : N;
@@ -435,11 +484,14 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         // lane groups of whole wavefronts: the lag is wave-uniform
         const int tau = (L % 64 == 0) ? __builtin_amdgcn_readfirstlane(t0 + lam) : t0 + lam;
         const bool active = tau < sg.tau_end;
-        const float mult = tau > 0 ? 2.f : 1.f;
+        // does lag tau have a distinct partner row -tau (periodic: N - tau)?
+        const bool two_rows = CIRC ? (tau > 0 && 2 * tau != N) : (tau > 0);
+        const float mult = two_rows ? 2.f : 1.f;
         const bool main_tau = tau <= w.h_tau;
         const float wu = (banded && active) ? bu[(31 * tau) / N] : 1.f;
-        const int64_t row_p = w.grid_off + (int64_t)(T + (active ? tau : 0)) * M;
-        const int64_t row_n = w.grid_off + (int64_t)(T - (active ? tau : 0)) * M;
+        const int tz = active ? tau : 0;
+        const int64_t row_p = CIRC ? w.grid_off + (int64_t)tz * RL : w.grid_off + (int64_t)(T + tz) * M;
+        const int64_t row_n = CIRC ? w.grid_off + (int64_t)(tz ? N - tz : 0) * RL : w.grid_off + (int64_t)(T - tz) * M;
         // rows tau and -tau of the halves-in-turn epilogue (empty when inactive)
         const unsigned row_bytes = active ? (unsigned)M * 4u : 0u;
         const Rsrc mag_p = make_rsrc(HAS_MAG_OUT && a.mag ? a.mag + row_p : nullptr, HAS_MAG_OUT && a.mag ? row_bytes : 0u);
@@ -448,16 +500,16 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         const Rsrc gm_n = make_rsrc(MODE == MODE_BWD_MAG ? a.grad_mag + row_n : nullptr, MODE == MODE_BWD_MAG ? row_bytes : 0u);
 
         // prefetch the two upstream rows (tau, -tau) while the transform runs
-        constexpr int NPF = (MODE == MODE_BWD_MAG && SPLIT) ? (2 * M / 4) / TPL : 1;
+        constexpr int NPF = (MODE == MODE_BWD_MAG && SPLIT) ? (2 * RL / 4) / TPL : 1;
         float4 gpre[NPF];
         if (MODE == MODE_BWD_MAG && SPLIT) {
 #pragma unroll
             for (int i = 0; i < NPF; ++i) {
                 const int f = t2 + i * TPL;  // float4 index over both rows
-                const int r = f >= M / 4;
+                const int r = f >= RL / 4;
                 const int64_t base = r ? row_n : row_p;
-                gpre[i] = (active && (tau > 0 || !r))
-                              ? *reinterpret_cast<const float4*>(a.grad_mag + base + 4 * (f - r * (M / 4)))
+                gpre[i] = (active && (two_rows || !r))
+                              ? *reinterpret_cast<const float4*>(a.grad_mag + base + 4 * (f - r * (RL / 4)))
                               : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
@@ -473,7 +525,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             float2 v[P];
             if (NEEDS_INV && a.load_store) {
                 // an inactive lag gets an empty range: zeros
-                const Rsrc ys = make_rsrc(a.ystore + w.store_off + (int64_t)(active ? tau : 0) * M + h * MH,
+                const Rsrc ys = make_rsrc(a.ystore + w.store_off + (int64_t)(active ? tau : 0) * (CIRC ? MH : M) + h * MH,
                                           active ? (unsigned)MH * 8u : 0u);
 #pragma unroll
                 for (int q = 0; q < P; ++q) v[q] = buf_load2(ys, (l + q * L) * 8);
@@ -482,7 +534,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             }
             // v[q] = Y'[2 (l + qL) + h]
             if (MODE == MODE_FWD && a.ystore && active) {
-                const Rsrc ys = make_rsrc(a.ystore + w.store_off + (int64_t)tau * M + h * MH, (unsigned)MH * 8u);
+                const Rsrc ys = make_rsrc(a.ystore + w.store_off + (int64_t)tau * (CIRC ? MH : M) + h * MH,
+                                          (unsigned)MH * 8u);
 #pragma unroll
                 for (int q = 0; q < P; ++q) buf_store2(ys, (l + q * L) * 8, v[q]);
             }
@@ -513,9 +566,10 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 const float c_main = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    const int k = 2 * (l + q * L) + h;
-                    const int kn = k ? M - k : 0;
-                    const int kc = k < (M >> 1) ? k : M - k;  // |centred bin|
+                    // bin of the grid row (periodic: v[q] is bin l + qL of N)
+                    const int k = CIRC ? l + q * L : 2 * (l + q * L) + h;
+                    const int kn = k ? RL - k : 0;
+                    const int kc = k < (RL >> 1) ? k : RL - k;  // |centred bin|
                     const float pw = cabs2(v[q]) * invE2;
                     // a = sqrt(x) and 1/a = rsqrt(x): modes that need both take
                     // one reciprocal square root and a multiply
@@ -529,13 +583,13 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     float wt = 1.f;
                     if constexpr (BANDED) {
                         // the band index is in [0, 30] for every bin
-                        wt = wu * bv[floor_div_small(31 * kc, (M >> 1) + 1)];
+                        wt = wu * bv[floor_div_small(31 * kc, (RL >> 1) + 1)];
                     }
                     if (HAS_MAG_OUT) {
                         if (mag_out) {
                             if (SPLIT) {
                                 rowbuf[k] = av;
-                                rowbuf[M + kn] = av;
+                                rowbuf[RL + kn] = av;
                             } else if (active) {
                                 buf_store1(mag_p, k * 4, av);
                                 if (tau > 0) buf_store1(mag_n, kn * 4, av);
@@ -562,7 +616,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                             float g;
                             if (SPLIT) {
                                 g = rowbuf[k];
-                                if (tau > 0) g += rowbuf[M + kn];
+                                if (two_rows) g += rowbuf[RL + kn];
                             } else {
                                 g = buf_load1(gm_p, k * 4);
                                 if (tau > 0) g += buf_load1(gm_n, kn * 4);
@@ -581,7 +635,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         } else if constexpr (MODE == MODE_LOSS) {
                             if (direct_isl && main_cell) {
                                 // H of the ISL part on this mainlobe bin
-                                const int ks = k < (M >> 1) ? k : k - M;
+                                const int ks = k < (RL >> 1) ? k : k - RL;
                                 mlb[lam * n_mb + ks + w.h_k] = cscale(v[q], -mult * a.w_isl * invE2);
                             }
                             // soft-PSL part without the normaliser 1/S
@@ -647,10 +701,10 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     __syncthreads();
                     const float4* rb4 = reinterpret_cast<const float4*>(rowbuf);
                     if (active) {
-                        for (int f = t2; f < 2 * (M / 4); f += TPL) {
-                            const int r = f >= M / 4;
-                            if (r && tau == 0) break;
-                            float4* dst = reinterpret_cast<float4*>(a.mag + (r ? row_n : row_p)) + (f - r * (M / 4));
+                        for (int f = t2; f < 2 * (RL / 4); f += TPL) {
+                            const int r = f >= RL / 4;
+                            if (r && !two_rows) break;
+                            float4* dst = reinterpret_cast<float4*>(a.mag + (r ? row_n : row_p)) + (f - r * (RL / 4));
                             *dst = rb4[f];
                         }
                     }
@@ -660,13 +714,14 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     __syncthreads();
                     float2* yb = reinterpret_cast<float2*>(rowbuf);
 #pragma unroll
-                    for (int q = 0; q < P; ++q) yb[2 * (l + q * L) + h] = v[q];
+                    for (int q = 0; q < P; ++q) yb[CIRC ? l + q * L : 2 * (l + q * L) + h] = v[q];
                     __syncthreads();
                     if (active) {
-                        for (int k = t2; k < M; k += TPL) {
-                            const int ti = (int)(((int64_t)k * tau) & (M - 1));
+                        for (int k = t2; k < RL; k += TPL) {
+                            // w_RL^{k tau} = w_M^{(M / RL) k tau}
+                            const int ti = (int)(((int64_t)k * tau * (M / RL)) & (M - 1));
                             a.chi[row_p + k] = cmul(yb[k], tw[ti << tshift]);
-                            if (tau > 0) a.chi[row_n + k] = cconj(yb[k ? M - k : 0]);
+                            if (two_rows) a.chi[row_n + k] = cconj(yb[k ? RL - k : 0]);
                         }
                     }
                 }
@@ -706,7 +761,10 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // lag-product adjoint for every lag of this iteration
             for (int j = 0; j < LPI; ++j) {
                 if (t0 + j >= sg.tau_end) break;
-                gather(lds + 2 * j * BUF, true, t0 + j, std::false_type{}, nullptr);
+                if (CIRC)
+                    gather(lds + j * BUF, false, t0 + j, std::false_type{}, nullptr);
+                else
+                    gather(lds + 2 * j * BUF, true, t0 + j, std::false_type{}, nullptr);
             }
         }
         __syncthreads();
@@ -717,12 +775,13 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 for (int j = 0; j < LPI; ++j) {
                     const int tj = t0 + j;
                     if (tj >= sg.tau_end || tj > w.h_tau) break;
-                    float2* qb = lds + 2 * j * BUF;
+                    float2* qb = lds + (CIRC ? j : 2 * j) * BUF;
                     const float2* hb = mlb + j * n_mb;
-                    for (int m = tid; m < N - tj; m += WGS) {
+                    for (int m = tid; m < (CIRC ? N : N - tj); m += WGS) {
                         float2 qv = make_float2(0.f, 0.f);
                         for (int b = 0; b < n_mb; ++b) {
-                            const int ti = ((b - w.h_k) * m) & (M - 1);
+                            // exp(+j 2 pi k m / RL) = conj(w_M^{(M / RL) k m})
+                            const int ti = ((b - w.h_k) * m * (M / RL)) & (M - 1);
                             qv = cadd(qv, cmulc(hb[b], twl(ti)));
                         }
                         qb[lds_index(m)] = qv;
@@ -737,12 +796,20 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 for (int j = 0; j < LPI; ++j) {
                     const int tj = t0 + j;
                     if (tj >= sg.tau_end || tj > w.h_tau) break;
-                    const float2* qa = lds + 2 * j * BUF;
+                    const float2* qa = lds + (CIRC ? j : 2 * j) * BUF;
 #pragma unroll
                     for (int i = 0; i < NACC; ++i) {
                         const int p = tid + WGS * i;
-                        if (p < N - tj) acc2[i] = cadd(acc2[i], cmul(cconj(qa[lds_index(p)]), sv[p + tj]));
-                        if (p < N && p >= tj) acc2[i] = cadd(acc2[i], cmul(qa[lds_index(p - tj)], sv[p - tj]));
+                        if (CIRC) {
+                            if (p < N) {
+                                acc2[i] = cadd(acc2[i], cmul(cconj(qa[lds_index(p)]), sv[p + tj]));
+                                const int m = p >= tj ? p - tj : p - tj + N;
+                                acc2[i] = cadd(acc2[i], cmul(qa[lds_index(m)], sv[m]));
+                            }
+                        } else {
+                            if (p < N - tj) acc2[i] = cadd(acc2[i], cmul(cconj(qa[lds_index(p)]), sv[p + tj]));
+                            if (p < N && p >= tj) acc2[i] = cadd(acc2[i], cmul(qa[lds_index(p - tj)], sv[p - tj]));
+                        }
                     }
                 }
 #pragma unroll
@@ -760,8 +827,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 const float c_main = -mult * a.w_isl * invE2;
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    const int k = 2 * (l + q * L) + hsel;
-                    const int kc = k < (M >> 1) ? k : M - k;
+                    const int k = CIRC ? l + q * L : 2 * (l + q * L) + hsel;
+                    const int kc = k < (RL >> 1) ? k : RL - k;
                     const bool main_cell = active && main_tau && kc <= w.h_k;
                     v[q] = cscale(v[q], main_cell ? c_main : 0.f);
                 }
@@ -769,7 +836,10 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 __syncthreads();
                 for (int j = 0; j < LPI; ++j) {
                     if (t0 + j >= sg.tau_end) break;
-                    gather(lds + 2 * j * BUF, true, t0 + j, std::true_type{}, slab2);
+                    if (CIRC)
+                        gather(lds + j * BUF, false, t0 + j, std::true_type{}, slab2);
+                    else
+                        gather(lds + 2 * j * BUF, true, t0 + j, std::true_type{}, slab2);
                 }
                 __syncthreads();
             }
@@ -861,8 +931,9 @@ using V5 = Variant<32, 1, 256, 1, 12, 12, 1, 0>; // M 8192: 32 points per lane, 
 // Persistent kernel over one size class: work group g runs items g, g + grid,
 // g + 2 grid, ... of the class's list, which the planner sorted longest first
 // (a static, deterministic assignment).
-template <int MODE, typename V, int LG>
+template <int MODE, typename V, int LG, bool CIRC = false>
 __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
+    static_assert(!CIRC || (V::SPLIT && V::S_LDS), "periodic AF: split variants with samples in LDS");
     extern __shared__ float2 dyn[];
     __shared__ double scratch[64];
     constexpr int MH = 1 << LG;
@@ -891,7 +962,7 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
         if (a.single) {
             // one waveform: its samples, the twiddles and the first item's
             // descriptor travel in the same memory round trip
-            stage_wave<MODE, V::WGS, MH>(a, a.w0, a.w0_index, s_lds, V::S_LDS != 0, scratch, st, tw_lds,
+            stage_wave<MODE, V::WGS, MH, CIRC>(a, a.w0, a.w0_index, s_lds, V::S_LDS != 0, scratch, st, tw_lds,
                                          twsh_global);
         } else if (tw_lds) {
             stage_twiddles<V::WGS, MH>(a, tw_lds, twsh_global);
@@ -903,9 +974,10 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
         if (sg.wave != st.wave) {
             // a class with one waveform carries its descriptor in the arguments
             const WaveDesc w = a.single ? a.w0 : a.waves[sg.wave];
-            stage_wave<MODE, V::WGS, MH>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st, nullptr, 0);
+            stage_wave<MODE, V::WGS, MH, CIRC>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st, nullptr, 0);
         }
-        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG)>(a, sg, lds, twl, s_lds, V::S_LDS != 0, scratch,
+        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG), CIRC>(a, sg, lds, twl, s_lds, V::S_LDS != 0,
+                                                                            scratch,
                                                                       st);
     }
 }

@@ -12,28 +12,34 @@ namespace graf {
 #define GRAF_CAT(a, b) GRAF_CAT2(a, b)
 using VSel = GRAF_CAT(V, GRAF_VARIANT);
 
-template <int MODE, int LG>
+template <int MODE, int LG, bool CIRC>
 static void* pick_lg(int lg) {
     if constexpr (LG > 15) {
         return nullptr;
     } else {
         if (lg == LG) {
-            if constexpr (VSel::fits(LG)) return (void*)af_kernel<MODE, VSel, LG>;
+            if constexpr (VSel::fits(LG) && (!CIRC || (VSel::SPLIT && VSel::S_LDS)))
+                return (void*)af_kernel<MODE, VSel, LG, CIRC>;
             return nullptr;
         }
-        return pick_lg<MODE, LG + 1>(lg);
+        return pick_lg<MODE, LG + 1, CIRC>(lg);
     }
 }
 
-void* GRAF_CAT(variant_kernel_, GRAF_VARIANT)(int mode, int lg) {
+template <bool CIRC>
+static void* pick_mode(int mode, int lg) {
     switch (mode) {
-        case MODE_FWD: return pick_lg<MODE_FWD, 1>(lg);
-        case MODE_BWD_MAG: return pick_lg<MODE_BWD_MAG, 1>(lg);
-        case MODE_BWD_LOSS: return pick_lg<MODE_BWD_LOSS, 1>(lg);
-        case MODE_FUSED_ISL: return pick_lg<MODE_FUSED_ISL, 1>(lg);
-        case MODE_LOSS: return pick_lg<MODE_LOSS, 1>(lg);
+        case MODE_FWD: return pick_lg<MODE_FWD, 1, CIRC>(lg);
+        case MODE_BWD_MAG: return pick_lg<MODE_BWD_MAG, 1, CIRC>(lg);
+        case MODE_BWD_LOSS: return pick_lg<MODE_BWD_LOSS, 1, CIRC>(lg);
+        case MODE_FUSED_ISL: return pick_lg<MODE_FUSED_ISL, 1, CIRC>(lg);
+        case MODE_LOSS: return pick_lg<MODE_LOSS, 1, CIRC>(lg);
     }
     return nullptr;
+}
+
+void* GRAF_CAT(variant_kernel_, GRAF_VARIANT)(int mode, int lg, int circ) {
+    return circ ? pick_mode<true>(mode, lg) : pick_mode<false>(mode, lg);
 }
 
 VariantInfo GRAF_CAT(variant_info_, GRAF_VARIANT)(int lg) {
@@ -44,6 +50,7 @@ VariantInfo GRAF_CAT(variant_info_, GRAF_VARIANT)(int lg) {
     vi.split = VSel::SPLIT;
     vi.wgs = VSel::WGS;
     vi.s_lds = VSel::S_LDS;
+    vi.circ = VSel::SPLIT && VSel::S_LDS;
     vi.fits = 0;
     vi.fft_lds = 0;
     vi.nacc = 0;

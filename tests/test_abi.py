@@ -46,7 +46,7 @@ def _create(lib, waves, **opt):
     goff = 0
     for i, (n, m, T) in enumerate(waves):
         arr[i].n, arr[i].m, arr[i].max_lag = n, m, T
-        arr[i].h_tau, arr[i].h_k, arr[i].reserved = 1, 1, 0
+        arr[i].h_tau, arr[i].h_k, arr[i].flags = 1, 1, 0
         arr[i].s_off, arr[i].grid_off = off, goff
         off += n
         goff += (2 * (n - 1 if T < 0 else T) + 1) * m
@@ -75,7 +75,17 @@ def test_plan_validation(lib, waves, code):
 
 
 def test_plan_validation_fields(lib):
-    assert _create(lib, [(64, 128, -1)], fields={"reserved": 1}) == -1
+    assert _create(lib, [(64, 128, -1)], fields={"flags": 2}) == -1
+    # periodic AF: m = n, a power of two in [64, 4096], every lag, h <= n/2
+    per = {"flags": L.AF_WAVE_PERIODIC}
+    assert _create(lib, [(64, 128, -1)], fields=per) == -1
+    assert _create(lib, [(64, 64, 10)], fields=per) == -1
+    assert _create(lib, [(64, 64, -1)], fields=dict(per, h_tau=33)) == -1
+    assert _create(lib, [(96, 96, -1)], fields=per) == -2
+    assert _create(lib, [(32, 32, -1)], fields=per) == -2
+    assert _create(lib, [(8192, 8192, -1)], fields=per) == -2
+    assert _create(lib, [(64, 64, -1)], fields=per) not in (-1, -2)
+    assert _create(lib, [(4096, 4096, -1)], fields=per) not in (-1, -2)
     assert _create(lib, [(64, 128, -1)], fields={"grid_off": 2}) == -1
     assert _create(lib, [(64, 128, -1)], fields={"h_tau": -1}) == -1
     assert _create(lib, [(64, 128, -1)], store_mode=3) == -1

@@ -551,3 +551,10 @@ def test_circular_normalised_gradient_orthogonal_to_s():
     s = rand_complex(16, 90)
     g = O.loss_and_grad_circular(s, O.LossParams(w_isl=1.0, w_psl=1.0, temp=0.1))["g"]
     assert abs(np.vdot(s, g)) <= 1e-12 * np.linalg.norm(s) * np.linalg.norm(g) * 16
+
+
+def test_circular_rows_match_the_grid():
+    s = rand_complex(64, 91)
+    c = O.chi_circular(s)
+    taus = [0, 1, 31, 32, 33, 63]
+    assert np.max(np.abs(O.chi_circular_rows(s, taus) - c[taus])) <= 1e-12 * O.energy(s)
