@@ -366,6 +366,69 @@ def bench_proposal(args, torch):
     return out
 
 
+def bench_periodic(args, torch):
+    """The periodic (circular) AF of Eqs. 2 and 7 / Algorithm 1 at the paper's
+    own waveform length: 4096 random-phase codes, N = M = 256, the full N x N
+    grid each, ISL (|tau|_c <= 1, |k_c| <= 1) + soft-PSL (T = 0.05) forward +
+    backward per step (one fused pass and the reduction), inputs in HBM."""
+    import numpy as np
+    from paper_2506_22935_amd import af, workloads as W
+    B, n = 4096, 256
+    phases = W.random_phases(B * n, seed=args.seed + 11)
+    s = torch.from_numpy(W.unimodular(phases)).cuda()
+    cells = B * n * n
+    plan = af.Plan([n] * B, [n] * B, eps=1e-12, variant=args.variant, periodic=True)
+    log("periodic: %d waveforms N=M=%d, %.3g cells, %d segments, variant %d"
+        % (B, n, cells, plan.summary()["segments"], plan.summary()["variant"]))
+    terms = torch.empty(B, 4, device="cuda")
+    grad = torch.empty(B * n, dtype=torch.complex64, device="cuda")
+    ws = plan.workspace
+    lp = dict(w_isl=1.0, w_psl=1.0, temp=0.05)
+
+    def step():
+        plan.loss(s, grad=True, ws=ws, out_terms=terms, out_grad=grad, **lp)
+
+    for _ in range(args.warmup):
+        step()
+    ms = timed(step, args.steps, torch)
+    fused_ms = timed(lambda: plan.loss_stage(0, s, terms, grad, None, ws=ws, **lp), 20, torch)
+    # one forward and one inverse N-point transform per lag tau in [0, N/2]
+    flops = B * 2.0 * fft_flops(n // 2 + 1, n)
+    ach = flops / (fused_ms * 1e-3) / 1e12
+    log("periodic: %.4f ms/step, fused pass %.4f ms, mean ISL %.3f, mean soft-PSL %.4f"
+        % (ms, fused_ms, float(terms[:, 1].mean()), float(terms[:, 2].mean())))
+    out = dict(value=cells / (ms * 1e-3), ms_per_step=ms,
+               config=dict(workload="periodic: 4096 random-phase codes, N=M=256 circular AF (full 256x256 grid), "
+                                    "ISL(|tau|<=1,|k|<=1)+softPSL(T=0.05) fwd+bwd",
+                           waveforms=B, n=n, cells=cells, variant=plan.summary()["variant"],
+                           stage_ms=dict(fused_pass=round(fused_ms, 5))),
+               roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                             frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
+                             kernel="fused periodic loss pass (forward + inverse N-point transforms)",
+                             kernel_ms=round(fused_ms, 5), flops_per_launch=flops))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_periodic(n, phases, budget_s=10.0)
+    return out
+
+
+def cpu_baseline_periodic(n, phases, budget_s=10.0):
+    """The oracle's periodic loss + gradient on consecutive waveforms of the
+    batch until the budget is spent."""
+    import oracle as O
+    from oracle import _native
+    from paper_2506_22935_amd import workloads as W
+    done, t_all = 0, 0.0
+    params = O.LossParams(w_isl=1.0, w_psl=1.0, temp=0.05, eps=1e-12)
+    while t_all < budget_s and (done + 1) * n <= len(phases):
+        s = O.to_c64_exact(W.unimodular(phases[done * n:(done + 1) * n]))
+        t0 = time.perf_counter()
+        O.loss_and_grad_circular(s, params)
+        t_all += time.perf_counter() - t0
+        done += 1
+    return dict(value=done * n * n / t_all, unit="cells/s", cores=_native.threads(), kind="oracle",
+                sample="periodic loss + gradient of the first %d waveforms (N=M=%d), %.1f s" % (done, n, t_all))
+
+
 def bench_copy(args, torch):
     """Plain device copy of known size (counter calibration)."""
     nbytes = 1 << 30
@@ -379,7 +442,7 @@ def bench_copy(args, torch):
 
 
 WORKLOADS = {"single": bench_single, "uneven": bench_uneven, "large": bench_large, "proposal": bench_proposal,
-             "copy": bench_copy}
+             "periodic": bench_periodic, "copy": bench_copy}
 
 
 def main():
