@@ -29,6 +29,7 @@ __all__ = [
     "mlp_backward", "psl_db", "chi_rows_fft", "magnitude_backward_fft",
     "chi_circular", "chi_circular_rows", "circular_lag_distance", "circular_mainlobe_mask", "circular_isl_weights",
     "loss_and_grad_circular", "magnitude_backward_circular",
+    "spectral_variance", "hard_psl", "experiment_loss_and_grad",
 ]
 
 
@@ -303,6 +304,65 @@ def magnitude_backward_circular(s, grad_mag, eps):
     G = ga * c / (2.0 * E * E * a)
     dLdE = -float(np.sum(ga * p / (E * a)))
     return _native.adjoint_circ(s, G) + dLdE * s
+
+
+# ----------------------------------------------------------------------------
+# the experiment loss of Sec. 7.1.1: hard PSL + lambda alpha SpectralVariance
+# ----------------------------------------------------------------------------
+
+def spectral_variance(s):
+    """V = var_j{ P_j / sum P }, P_j = |X_j|^2, X = the N-point DFT of s
+    (no padding), population variance (mean of squared deviations from 1/N);
+    returns (V, dV/d conj(s)).
+
+    With x_j = P_j / S, S = sum P: dV/dP_j = 2 (x_j - sum_k x_k^2) / (N S),
+    and dV/d conj(s[n]) = sum_j dV/dP_j X_j exp(+j 2 pi j n / N)."""
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
+    k = np.arange(n)
+    F = np.exp(-2j * np.pi * np.outer(k, k) / n)  # DFT matrix by its definition
+    X = F @ s
+    P = X.real * X.real + X.imag * X.imag
+    S = float(P.sum())
+    x = P / S
+    V = float(np.mean((x - 1.0 / n) ** 2))
+    c = 2.0 * (x - float(np.sum(x * x))) / (n * S)
+    g = np.conj(F).T @ (c * X)
+    return V, g
+
+
+def hard_psl(c, E, side):
+    """PSL of Eq. 18 as a power ratio: max over the sidelobe cells of
+    p = |chi|^2 / E^2; returns (PSL, (row, bin) of the maximum).  Ties take
+    the first cell in row-major order."""
+    p = power(c, E)
+    pm = np.where(side, p, -np.inf)
+    idx = int(np.argmax(pm))
+    return float(pm.flat[idx]), np.unravel_index(idx, p.shape)
+
+
+def experiment_loss_and_grad(s, m, lam, alpha=2000.0, h_tau=0, h_k=0, periodic=False, eps=1e-12):
+    """L = PSL + lam * alpha * V (Sec. 7.1.1) and dL/d conj(s): the PSL
+    subgradient sits on the maximising cell (dp/d conj(chi) = chi / E^2
+    there, dPSL/dE = -2 PSL / E), the spectral part as in
+    spectral_variance.  The grid is the periodic AF when periodic, else the
+    aperiodic one with M bins and the full lag window."""
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
+    E = energy(s)
+    if periodic:
+        c = chi_circular(s)
+        side = ~circular_mainlobe_mask(n, h_tau, h_k)
+    else:
+        c = chi(s, m, n - 1)
+        side = ~mainlobe_mask(m, n - 1, h_tau, h_k)
+    psl, cell = hard_psl(c, E, side)
+    G = np.zeros_like(c)
+    G[cell] = c[cell] / (E * E)
+    gp = (_native.adjoint_circ(s, G) if periodic else _native.adjoint(s, m, n - 1, G)) - 2.0 * psl / E * s
+    V, gv = spectral_variance(s)
+    return dict(loss=psl + lam * alpha * V, psl=psl, cell=cell, spec_var=V, g=gp + lam * alpha * gv,
+                g_psl=gp, g_spec=gv, chi=c, E=E, a=magnitude(c, E, eps), side=side)
 
 
 # ----------------------------------------------------------------------------

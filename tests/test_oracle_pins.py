@@ -558,3 +558,62 @@ def test_circular_rows_match_the_grid():
     c = O.chi_circular(s)
     taus = [0, 1, 31, 32, 33, 63]
     assert np.max(np.abs(O.chi_circular_rows(s, taus) - c[taus])) <= 1e-12 * O.energy(s)
+
+
+# --------------------------------------------------------------------------
+# the experiment loss of Sec. 7.1.1: hard PSL + lambda alpha SpectralVariance
+# --------------------------------------------------------------------------
+
+def test_spectral_variance_closed_forms():
+    n = 64
+    # an impulse and a Zadoff-Chu code have flat spectra: V = 0
+    assert O.spectral_variance(np.eye(n)[3])[0] <= 1e-30
+    k = np.arange(n)
+    assert O.spectral_variance(np.exp(1j * np.pi * 5 * k * k / n))[0] <= 1e-28
+    # a constant code puts all power in bin 0: x = (1, 0, ..., 0)
+    V = O.spectral_variance(np.ones(n))[0]
+    assert abs(V - (1.0 / n - 1.0 / n ** 2)) <= 1e-15
+    # matches numpy's FFT and population variance
+    s = rand_complex(n, 95)
+    P = np.abs(np.fft.fft(s)) ** 2
+    assert abs(O.spectral_variance(s)[0] - np.var(P / P.sum())) <= 1e-15
+
+
+@pytest.mark.parametrize("n", [8, 16, 13])
+def test_spectral_variance_gradient_finite_differences(n):
+    s = rand_complex(n, 96 + n)
+    V, g = O.spectral_variance(s)
+    fd = _fd_grad(lambda x: O.spectral_variance(x)[0], s)
+    assert np.max(np.abs(g - fd)) <= 1e-7 * max(1e-3, np.max(np.abs(fd)))
+    # V is invariant to s -> c s, so sum conj(s) g = 0
+    assert abs(np.vdot(s, g)) <= 1e-12 * np.linalg.norm(s) * np.linalg.norm(g) * n
+
+
+def test_hard_psl_is_the_brute_force_max():
+    n, m = 16, 32
+    s = rand_unimodular(n, 97)
+    c = O.chi(s, m)
+    E = O.energy(s)
+    side = ~O.mainlobe_mask(m, n - 1, 1, 1)
+    psl, cell = O.hard_psl(c, E, side)
+    best = max(abs(c[i, k]) ** 2 / E ** 2 for i in range(2 * n - 1) for k in range(m) if side[i, k])
+    assert abs(psl - best) <= 1e-15 and side[cell]
+    assert abs(abs(c[cell]) ** 2 / E ** 2 - psl) <= 1e-15
+
+
+@pytest.mark.parametrize("periodic,n,m", [(True, 8, 8), (True, 16, 16), (False, 8, 16)])
+@pytest.mark.parametrize("lam", [0.0, 0.5, 2.0])
+def test_experiment_loss_finite_differences(periodic, n, m, lam):
+    # away from ties the hard max is smooth: central differences of L agree
+    # with the subgradient on the maximising cell plus the spectral part
+    s = rand_complex(n, 98 + n + int(periodic))
+
+    def f(x):
+        return O.experiment_loss_and_grad(x, m, lam, periodic=periodic)["loss"]
+
+    r = O.experiment_loss_and_grad(s, m, lam, periodic=periodic)
+    p = O.power(r["chi"], r["E"])[r["side"]]
+    top = np.sort(np.unique(np.round(p, 14)))[-2:]
+    assert top[1] - top[0] > 1e-6  # a unique maximum up to its twin cell
+    fd = _fd_grad(f, s, h=1e-7)
+    assert np.max(np.abs(r["g"] - fd)) <= 1e-5 * max(1.0, np.max(np.abs(fd)))
