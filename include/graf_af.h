@@ -98,12 +98,24 @@ typedef struct {
 
 typedef struct af_plan af_plan;
 
-/* Built-in loss parameters (Sec. 5.1).  band_w: device float[batch][62] or NULL. */
+/* Built-in loss parameters (Sec. 5.1).  band_w: device float[batch][62] or NULL.
+ * psl_hard = 1 replaces the soft PSL by the hard PSL of Eq. 18 as a power
+ * ratio, max over Omega_s of |chi|^2 / E^2, whose subgradient sits on one
+ * maximising cell (the smallest cell index tau * row length + k on the
+ * tau >= 0 row among equal powers; both cells of a (tau, k), (-tau, -k) pair
+ * give the same gradient), weighted by w_psl.  w_spec weights the spectral
+ * variance of Sec. 7.1.1, var_j(P_j / sum P) with P = |DFT_N(s)|^2 (the
+ * N-point spectrum, population variance; N <= 4096).  The experiment loss
+ * PSL + lambda * alpha * SpectralVariance is w_psl = 1, psl_hard = 1,
+ * w_spec = lambda * alpha.  Zero-initialise the struct: psl_hard = 0 and
+ * w_spec = 0 give the soft-PSL losses above. */
 typedef struct {
     float w_isl;
     float w_psl;
     float psl_temp; /* > 0 */
     const float* band_w;
+    int32_t psl_hard; /* 0 or 1 */
+    float w_spec;
 } af_loss_params;
 
 /* Adam settings for af_optim_step (Kingma & Ba; eps outside the square root). */
@@ -174,6 +186,12 @@ af_status af_loss(const af_plan* plan, const void* s, const af_loss_params* loss
  * equals one af_loss call. */
 af_status af_loss_stage(const af_plan* plan, int32_t stage, const void* s, const af_loss_params* loss,
                         float* terms, float* mag, void* grad_s, void* ws, size_t ws_bytes, void* stream);
+
+/* The spectral variance of Sec. 7.1.1 per waveform (see af_loss_params):
+ * value: device float[batch]; grad_s (nullable): dV/d conj(s), packed like
+ * s (overwritten).  Every waveform must have N <= 4096 (AF_ERR_UNSUPPORTED). */
+af_status af_spectral_variance(const af_plan* plan, const void* s, float* value, void* grad_s, void* ws,
+                               size_t ws_bytes, void* stream);
 
 /* s[i] = exp(j phi[i]) for i < count (device arrays). */
 af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream);

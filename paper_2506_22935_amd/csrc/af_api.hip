@@ -27,6 +27,7 @@ constexpr int kMinM = 128;
 constexpr int kMaxM = 32768;
 constexpr int kMinCircN = 64;   // periodic AF: N = M, the split variants' sizes
 constexpr int kMaxCircN = 4096;
+constexpr int kMaxSpecN = 4096;  // spectral variance: three N-vectors in LDS
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 int ilog2(int64_t x) {
@@ -71,7 +72,8 @@ struct af_plan {
     int log2_mmax = 0;
     int max_n = 0;
     int64_t cells = 0, store_bytes = 0;
-    size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_slabs2 = 0, off_store = 0, ws_total = 0;
+    size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_slabs2 = 0, off_extra = 0, off_vals = 0, off_store = 0,
+           ws_total = 0;
 
     // plan-owned device tables
     WaveDesc* d_waves = nullptr;
@@ -268,7 +270,12 @@ af_status build_schedule(af_plan* p) {
     const size_t slabs_b = align256((size_t)slab_elems * sizeof(float2));
     const size_t slabs2_b = align256((size_t)slab2_elems * sizeof(float2));
     const size_t store_b = align256((size_t)store_elems * sizeof(float2));
-    const size_t base = parts_b + energy_b + slabs_b + slabs2_b;
+    // the experiment loss's gradient (packed like s) and its [B][2] values
+    int64_t s_extent = 0;
+    for (const af_wave& w : p->waves) s_extent = std::max<int64_t>(s_extent, w.s_off + w.n);
+    const size_t extra_b = align256((size_t)s_extent * sizeof(float2));
+    const size_t vals_b = align256((size_t)B * 2 * sizeof(float));
+    const size_t base = parts_b + energy_b + slabs_b + slabs2_b + extra_b + vals_b;
     bool stores;
     if (p->store_mode == 1)
         stores = true;
@@ -325,6 +332,8 @@ af_status build_schedule(af_plan* p) {
     p->off_energy = parts_b;
     p->off_slabs = parts_b + energy_b;
     p->off_slabs2 = parts_b + energy_b + slabs_b;
+    p->off_extra = parts_b + energy_b + slabs_b + slabs2_b;
+    p->off_vals = p->off_extra + extra_b;
     p->off_store = base;
     p->ws_total = base + (stores ? store_b : 0);
     return AF_OK;
@@ -357,6 +366,8 @@ struct WsView {
     float* energy;
     float2* slabs;
     float2* slabs2;
+    float2* extra;
+    float* vals;
     float2* store;
 };
 
@@ -367,6 +378,8 @@ WsView ws_view(const af_plan* p, void* ws) {
     v.energy = (float*)(b + p->off_energy);
     v.slabs = (float2*)(b + p->off_slabs);
     v.slabs2 = (float2*)(b + p->off_slabs2);
+    v.extra = (float2*)(b + p->off_extra);
+    v.vals = (float*)(b + p->off_vals);
     v.store = p->stores ? (float2*)(b + p->off_store) : nullptr;
     return v;
 }
@@ -438,11 +451,19 @@ af_status check_common(const af_plan* p, const void* s, void* ws, size_t ws_byte
     return AF_OK;
 }
 
-af_status check_loss(const af_loss_params* lp) {
+af_status check_loss(const af_plan* p, const af_loss_params* lp) {
     if (!lp) return AF_ERR_INVALID_ARG;
-    if (!(lp->psl_temp > 0.f) || !std::isfinite(lp->w_isl) || !std::isfinite(lp->w_psl)) return AF_ERR_INVALID_ARG;
+    if (!(lp->psl_temp > 0.f) || !std::isfinite(lp->w_isl) || !std::isfinite(lp->w_psl) || !std::isfinite(lp->w_spec))
+        return AF_ERR_INVALID_ARG;
+    if (lp->psl_hard != 0 && lp->psl_hard != 1) return AF_ERR_INVALID_ARG;
+    if (lp->w_spec != 0.f && p->max_n > kMaxSpecN) return AF_ERR_UNSUPPORTED;
     return AF_OK;
 }
+
+// Does the loss take the hard PSL or the spectral variance (the experiment
+// loss's per-waveform kernel)?
+bool hard_psl(const af_loss_params* lp) { return lp->psl_hard != 0 && lp->w_psl != 0.f; }
+bool needs_extra(const af_loss_params* lp) { return hard_psl(lp) || lp->w_spec != 0.f; }
 
 // loss forward/backward into slabs and parts (no reduce)
 // Can ISL + soft-PSL forward and backward run as one pass (MODE_LOSS)?  The
@@ -451,7 +472,7 @@ af_status check_loss(const af_loss_params* lp) {
 // uniform ISL weights with full lag windows (the ISL gradient then lives on
 // the mainlobe cells) and variants that split the two half transforms.
 bool fused_loss_ok(const af_plan* p, const af_loss_params* lp) {
-    if (p->loss_passes_opt == 1 || lp->w_psl == 0.f || lp->band_w != nullptr) return false;
+    if (p->loss_passes_opt == 1 || lp->w_psl == 0.f || lp->psl_hard || lp->band_w != nullptr) return false;
     const float inv_t2 = 1.4426950408889634f / lp->psl_temp;
     if (!(std::sqrt(1.f + p->eps) * inv_t2 < 100.f)) return false;
     for (const af_plan::Class& k : p->classes)
@@ -462,23 +483,86 @@ bool fused_loss_ok(const af_plan* p, const af_loss_params* lp) {
     return true;
 }
 
-af_status loss_passes(const af_plan* p, const void* s, const af_loss_params* lp, float* mag, bool want_grad,
-                      const WsView& v, hipStream_t st, int only_class = -1) {
+// Arguments of the loss passes: the hard PSL takes no soft-PSL sums in the
+// kernels (its maximum is recorded instead)
+AfArgs loss_args(const af_plan* p, const void* s, const af_loss_params* lp, float* mag, const WsView& v) {
     AfArgs a = base_args(p, s, v);
     a.w_isl = lp->w_isl;
-    a.w_psl = lp->w_psl;
+    a.w_psl = lp->psl_hard ? 0.f : lp->w_psl;
     a.temp = lp->psl_temp;
     a.band_w = lp->band_w;
     a.mag = mag;
-    if (!want_grad) return launch(p, graf::MODE_FWD, a, st, only_class);
-    if (lp->w_psl == 0.f) return launch(p, graf::MODE_FUSED_ISL, a, st, only_class);
-    if (fused_loss_ok(p, lp)) return launch(p, graf::MODE_LOSS, a, st, only_class);
-    a.ystore = v.store;
-    af_status rc = launch(p, graf::MODE_FWD, a, st, only_class);
-    if (rc != AF_OK) return rc;
-    a.mag = nullptr;
-    a.load_store = v.store != nullptr;
-    return launch(p, graf::MODE_BWD_LOSS, a, st, only_class);
+    a.psl_hard = hard_psl(lp) ? 1 : 0;
+    return a;
+}
+
+// Do the passes of this loss leave gradient slabs (else the reduction reads
+// none)?  The hard PSL without ISL needs only the forward pass.
+bool loss_writes_slabs(const af_loss_params* lp, bool want_grad) {
+    if (!want_grad) return false;
+    if (lp->psl_hard) return lp->w_isl != 0.f;
+    return true;
+}
+
+// The experiment loss's per-waveform kernel (after the AF pass: it reads the
+// segment records and E)
+af_status launch_extra(const af_plan* p, const void* s, const af_loss_params* lp, bool want_grad, const WsView& v,
+                       hipStream_t st) {
+    if (!needs_extra(lp)) return AF_OK;
+    graf::ExtraArgs e;
+    std::memset(&e, 0, sizeof(e));
+    e.s = (const float2*)s;
+    e.waves = p->d_waves;
+    e.parts = v.parts;
+    e.energy = v.energy;
+    e.tw = p->d_tw;
+    e.log2_mmax = p->log2_mmax;
+    e.psl = hard_psl(lp) ? 1 : 0;
+    e.w_psl = lp->w_psl;
+    e.spec = lp->w_spec != 0.f ? 1 : 0;
+    e.w_spec = lp->w_spec;
+    e.g_extra = want_grad ? v.extra : nullptr;
+    e.vals = v.vals;
+    return graf::launch_extra(e, p->batch, p->max_n, st) == hipSuccess ? AF_OK : AF_ERR_HIP;
+}
+
+af_status loss_passes(const af_plan* p, const void* s, const af_loss_params* lp, float* mag, bool want_grad,
+                      const WsView& v, hipStream_t st, int only_class = -1) {
+    AfArgs a = loss_args(p, s, lp, mag, v);
+    af_status rc;
+    if (!want_grad || (lp->psl_hard && lp->w_isl == 0.f)) {
+        rc = launch(p, graf::MODE_FWD, a, st, only_class);
+    } else if (a.w_psl == 0.f) {
+        rc = launch(p, graf::MODE_FUSED_ISL, a, st, only_class);
+    } else if (fused_loss_ok(p, lp)) {
+        rc = launch(p, graf::MODE_LOSS, a, st, only_class);
+    } else {
+        a.ystore = v.store;
+        rc = launch(p, graf::MODE_FWD, a, st, only_class);
+        if (rc != AF_OK) return rc;
+        a.mag = nullptr;
+        a.load_store = v.store != nullptr;
+        rc = launch(p, graf::MODE_BWD_LOSS, a, st, only_class);
+    }
+    if (rc != AF_OK || only_class >= 0) return rc;
+    return launch_extra(p, s, lp, want_grad, v, st);
+}
+
+// Reduction arguments of a loss call
+ReduceArgs loss_reduce_args(const af_plan* p, const void* s, const af_loss_params* lp, bool want_grad,
+                            const WsView& v) {
+    ReduceArgs r = reduce_args(p, s, v);
+    r.w_isl = lp->w_isl;
+    r.w_psl = lp->w_psl;
+    r.temp = lp->psl_temp;
+    r.uniform_w = lp->band_w == nullptr;
+    r.skip_slabs = loss_writes_slabs(lp, want_grad) ? 0 : 1;
+    r.psl_scaled = want_grad && fused_loss_ok(p, lp);
+    r.psl_hard = hard_psl(lp) ? 1 : 0;
+    r.w_spec = lp->w_spec;
+    r.vals = v.vals;
+    r.g_extra = (want_grad && needs_extra(lp)) ? v.extra : nullptr;
+    return r;
 }
 
 }  // namespace
@@ -617,22 +701,16 @@ af_status af_loss(const af_plan* p, const void* s, const af_loss_params* lp, flo
                   void* ws, size_t ws_bytes, void* stream) {
     af_status rc = check_common(p, s, ws, ws_bytes);
     if (rc != AF_OK) return rc;
-    if ((rc = check_loss(lp)) != AF_OK) return rc;
+    if ((rc = check_loss(p, lp)) != AF_OK) return rc;
     if (!aligned(mag, 16) || !aligned(grad_s, 8) || !aligned(terms, 4) || !aligned(lp->band_w, 4))
         return AF_ERR_INVALID_ARG;
     const WsView v = ws_view(p, ws);
     rc = loss_passes(p, s, lp, mag, grad_s != nullptr, v, (hipStream_t)stream);
     if (rc != AF_OK) return rc;
     if (!terms && !grad_s) return AF_OK;
-    ReduceArgs r = reduce_args(p, s, v);
-    r.w_isl = lp->w_isl;
-    r.w_psl = lp->w_psl;
-    r.temp = lp->psl_temp;
-    r.uniform_w = lp->band_w == nullptr;
+    ReduceArgs r = loss_reduce_args(p, s, lp, grad_s != nullptr, v);
     r.grad = (float2*)grad_s;
     r.terms = terms;
-    r.skip_slabs = grad_s ? 0 : 1;
-    r.psl_scaled = grad_s != nullptr && fused_loss_ok(p, lp);
     return graf::launch_reduce(r, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
 }
 
@@ -640,46 +718,61 @@ af_status af_loss_stage(const af_plan* p, int32_t stage, const void* s, const af
                         float* mag, void* grad_s, void* ws, size_t ws_bytes, void* stream) {
     af_status rc = check_common(p, s, ws, ws_bytes);
     if (rc != AF_OK) return rc;
-    if ((rc = check_loss(lp)) != AF_OK) return rc;
+    if ((rc = check_loss(p, lp)) != AF_OK) return rc;
     if (!aligned(mag, 16) || !aligned(grad_s, 8) || !aligned(terms, 4) || !aligned(lp->band_w, 4))
         return AF_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     const WsView v = ws_view(p, ws);
-    AfArgs a = base_args(p, s, v);
-    a.w_isl = lp->w_isl;
-    a.w_psl = lp->w_psl;
-    a.temp = lp->psl_temp;
-    a.band_w = lp->band_w;
-    a.mag = mag;
-    const bool fused = lp->w_psl == 0.f && grad_s != nullptr;
-    const bool fused_loss = grad_s != nullptr && fused_loss_ok(p, lp);
+    AfArgs a = loss_args(p, s, lp, mag, v);
+    const bool grad = grad_s != nullptr;
+    const bool fwd_only = !grad || (lp->psl_hard && lp->w_isl == 0.f);
+    const bool fused = !fwd_only && a.w_psl == 0.f;
+    const bool fused_loss = !fwd_only && !fused && fused_loss_ok(p, lp);
     switch (stage) {
         case 0:
             if (fused) return launch(p, graf::MODE_FUSED_ISL, a, st);
             if (fused_loss) return launch(p, graf::MODE_LOSS, a, st);
-            a.ystore = grad_s ? v.store : nullptr;
+            a.ystore = fwd_only ? nullptr : v.store;
             return launch(p, graf::MODE_FWD, a, st);
         case 1:
-            if (fused || fused_loss || !grad_s) return AF_OK;
-            a.mag = nullptr;
-            a.ystore = v.store;
-            a.load_store = v.store != nullptr;
-            return launch(p, graf::MODE_BWD_LOSS, a, st);
+            if (!(fwd_only || fused || fused_loss)) {
+                a.mag = nullptr;
+                a.ystore = v.store;
+                a.load_store = v.store != nullptr;
+                rc = launch(p, graf::MODE_BWD_LOSS, a, st);
+                if (rc != AF_OK) return rc;
+            }
+            return launch_extra(p, s, lp, grad, v, st);
         case 2: {
             if (!terms && !grad_s) return AF_OK;
-            ReduceArgs r = reduce_args(p, s, v);
-            r.w_isl = lp->w_isl;
-            r.w_psl = lp->w_psl;
-            r.temp = lp->psl_temp;
-            r.uniform_w = lp->band_w == nullptr;
+            ReduceArgs r = loss_reduce_args(p, s, lp, grad, v);
             r.grad = (float2*)grad_s;
             r.terms = terms;
-            r.skip_slabs = grad_s ? 0 : 1;
-            r.psl_scaled = grad_s != nullptr && fused_loss_ok(p, lp);
             return graf::launch_reduce(r, st) == hipSuccess ? AF_OK : AF_ERR_HIP;
         }
     }
     return AF_ERR_INVALID_ARG;
+}
+
+af_status af_spectral_variance(const af_plan* p, const void* s, float* value, void* grad_s, void* ws, size_t ws_bytes,
+                               void* stream) {
+    af_status rc = check_common(p, s, ws, ws_bytes);
+    if (rc != AF_OK) return rc;
+    if (!value || !aligned(value, 4) || !aligned(grad_s, 8)) return AF_ERR_INVALID_ARG;
+    if (p->max_n > kMaxSpecN) return AF_ERR_UNSUPPORTED;
+    const WsView v = ws_view(p, ws);
+    graf::ExtraArgs e;
+    std::memset(&e, 0, sizeof(e));
+    e.s = (const float2*)s;
+    e.waves = p->d_waves;
+    e.tw = p->d_tw;
+    e.log2_mmax = p->log2_mmax;
+    e.spec = 1;
+    e.w_spec = 1.f;
+    e.g_extra = (float2*)grad_s;
+    e.vals = v.vals;
+    e.spec_out = value;
+    return graf::launch_extra(e, p->batch, p->max_n, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
 }
 
 af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream) {
@@ -693,7 +786,7 @@ af_status af_optim_step(const af_plan* p, float* phi, float* adam_m, float* adam
                         void* stream) {
     af_status rc = check_common(p, s, ws, ws_bytes);
     if (rc != AF_OK) return rc;
-    if ((rc = check_loss(lp)) != AF_OK) return rc;
+    if ((rc = check_loss(p, lp)) != AF_OK) return rc;
     if (!phi || !adam_m || !adam_v || !step || !ad) return AF_ERR_INVALID_ARG;
     if (!(ad->lr > 0.f) || !(ad->beta1 >= 0.f && ad->beta1 < 1.f) || !(ad->beta2 >= 0.f && ad->beta2 < 1.f) ||
         !(ad->eps >= 0.f))
@@ -701,18 +794,13 @@ af_status af_optim_step(const af_plan* p, float* phi, float* adam_m, float* adam
     const WsView v = ws_view(p, ws);
     rc = loss_passes(p, s, lp, nullptr, true, v, (hipStream_t)stream);
     if (rc != AF_OK) return rc;
-    ReduceArgs r = reduce_args(p, s, v);
-    r.w_isl = lp->w_isl;
-    r.w_psl = lp->w_psl;
-    r.temp = lp->psl_temp;
-    r.uniform_w = lp->band_w == nullptr;
+    ReduceArgs r = loss_reduce_args(p, s, lp, true, v);
     r.terms = terms;
     r.phi = phi;
     r.adam_m = adam_m;
     r.adam_v = adam_v;
     r.s_next = (float2*)s;
     r.step = step;
-    r.psl_scaled = fused_loss_ok(p, lp);
     r.lr = ad->lr;
     r.beta1 = ad->beta1;
     r.beta2 = ad->beta2;
@@ -731,10 +819,9 @@ af_status af_plan_autotune(af_plan* p, const void* s, void* ws, size_t ws_bytes,
         return AF_ERR_HIP;
     }
     af_loss_params lp;
+    std::memset(&lp, 0, sizeof(lp));
     lp.w_isl = 1.f;
-    lp.w_psl = 0.f;
     lp.psl_temp = 0.05f;
-    lp.band_w = nullptr;
     const int C = (int)p->classes.size();
     std::vector<int> best(C, -1);
     float total_best = 0.f;

@@ -107,6 +107,13 @@ __device__ __forceinline__ float wave_allmax(float v) {
     return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
 }
 
+// Smallest int over a wavefront (butterfly exchange; every lane gets it).
+__device__ __forceinline__ int wave_allmin_int(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 // Log-sum-exp pairs (m, s) = (max, sum of exp2((x - m) k)) over a wavefront:
 // the common maximum first, then one rescale per lane and a plain sum.
 __device__ __forceinline__ void wave_lse_pair(float& m, double& s, float k) {

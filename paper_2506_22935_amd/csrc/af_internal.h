@@ -34,13 +34,18 @@ struct SegDesc {
 // Per-segment partial results, accumulated in float64 where they are sums
 // over many cells.  isl: the segment's share of the ISL (for a complement
 // waveform, minus its mainlobe power: ISL = M + sum of these); lse_m, lse_s:
-// soft-PSL log-sum-exp pair (max a, sum exp((a - max)/T)); dle: dL/dE share.
+// soft-PSL log-sum-exp pair (max a, sum exp((a - max)/T)); dle: dL/dE share;
+// psl_p, psl_i: the largest sidelobe power of the segment and its cell
+// tau * (row length) + k on the tau >= 0 row (hard PSL; the smallest index
+// among equal powers; psl_p = -1 without a sidelobe cell).
 struct Part {
     double isl;
     double lse_s;
     double dle;
     float lse_m;
-    float pad;
+    float psl_p;
+    int psl_i;
+    int pad;
 };
 
 enum Mode : int {
@@ -76,6 +81,7 @@ struct AfArgs {
     float2* slabs;        // [sum segs*N]
     float2* slabs2;       // [sum isl_segs*N] ISL part of MODE_LOSS
     float* energy;        // [B], written by the segment holding lag 0
+    int psl_hard;         // MODE_FWD / MODE_FUSED_ISL: record the hard-PSL maximum
 };
 
 // The slab reduction runs 256-thread blocks over (256 >> sg_log) samples of
@@ -116,7 +122,33 @@ struct ReduceArgs {
     float2* s_next;       // exp(j phi_new)
     int* step;            // device step counter (1-based after increment)
     float lr, beta1, beta2, adam_eps;
+    // the experiment loss: hard PSL and spectral variance, from extra_kernel
+    int psl_hard;         // the PSL term is the hard maximum (vals[2b])
+    float w_spec;         // weight of the spectral variance (vals[2b + 1])
+    const float2* g_extra;  // their gradient, packed like s; nullable
+    const float* vals;    // [B][2] = hard PSL, spectral variance
 };
+
+// Per-waveform terms of the experiment loss (Sec. 7.1.1): the hard-PSL
+// maximum from the segment records, chi at that cell and its single-cell
+// adjoint, and the spectral variance of the N-point spectrum with its
+// gradient; one 256-thread block per waveform.
+struct ExtraArgs {
+    const float2* s;
+    const WaveDesc* waves;
+    const Part* parts;
+    const float* energy;
+    const float2* tw;     // exp(-j 2 pi i / MMAX)
+    int log2_mmax;
+    int psl;              // compute the hard-PSL part
+    float w_psl;
+    int spec;             // compute the spectral part
+    float w_spec;
+    float2* g_extra;      // gradient out (w_psl * psl part + w_spec * spectral part); nullable
+    float* vals;          // [B][2] out
+    float* spec_out;      // [B] spectral variance out (nullable)
+};
+hipError_t launch_extra(const ExtraArgs& a, int batch, int max_n, hipStream_t st);
 
 // launchers (af_kernels.hip)
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);

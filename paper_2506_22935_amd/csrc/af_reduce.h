@@ -113,14 +113,19 @@ __device__ __forceinline__ float2 slab_sum(const ReduceArgs& a, const WaveDesc& 
 __device__ __forceinline__ float total_dlde(const ReduceArgs& a, const WaveTotals& t, float E) {
     return (float)(-2.0 * (double)a.w_isl * t.isl_raw / (double)E + t.dle);
 }
-// the loss terms (one thread per waveform writes them)
-__device__ __forceinline__ float4 loss_terms(const ReduceArgs& a, const WaveDesc& w, const WaveTotals& t, float E) {
+// the loss terms (one thread per waveform writes them): (L, ISL, PSL term,
+// E) with the soft PSL, or the hard PSL and the spectral variance of the
+// experiment loss from vals
+__device__ __forceinline__ float4 loss_terms(const ReduceArgs& a, const WaveDesc& w, int wave, const WaveTotals& t,
+                                             float E) {
     // complement waveforms carry ISL - M (Moyal: the full grid holds M E^2;
     // N E^2 for the periodic AF)
     const double isl = t.isl_raw + ((a.uniform_w && w.full_window) ? (double)w.moyal : 0.0);
-    const float soft = (t.lse_s > 0.0) ? (float)((double)t.lse_m + (double)a.temp * log(t.lse_s)) : 0.f;
-    const double loss = (double)a.w_isl * isl + (a.w_psl != 0.f ? (double)a.w_psl * (double)soft : 0.0);
-    return make_float4((float)loss, (float)isl, soft, E);
+    const float psl = a.psl_hard ? a.vals[2 * wave]
+                                 : ((t.lse_s > 0.0) ? (float)((double)t.lse_m + (double)a.temp * log(t.lse_s)) : 0.f);
+    double loss = (double)a.w_isl * isl + (a.w_psl != 0.f ? (double)a.w_psl * (double)psl : 0.0);
+    if (a.w_spec != 0.f) loss += (double)a.w_spec * (double)a.vals[2 * wave + 1];
+    return make_float4((float)loss, (float)isl, psl, E);
 }
 
 // Sum of a waveform's second slabs (fused loss pass: the ISL part of the
@@ -188,6 +193,7 @@ __device__ void reduce_chunk(const ReduceArgs& a, int blk, int t_prev, double* s
     if (mine) {
         g.x = fmaf(dLdE, sp.x, g.x);
         g.y = fmaf(dLdE, sp.y, g.y);
+        if (a.g_extra) g = cadd(g, a.g_extra[i]);
         if (ADAM) {
             const float dphi = 2.f * (sp.x * g.y - sp.y * g.x);
             const float t = (float)(t_prev + 1);
@@ -206,7 +212,8 @@ __device__ void reduce_chunk(const ReduceArgs& a, int blk, int t_prev, double* s
             a.grad[i] = g;
         }
     }
-    if (b.p0 == 0 && threadIdx.x == 0 && a.terms) reinterpret_cast<float4*>(a.terms)[b.wave] = loss_terms(a, w, tt, E);
+    if (b.p0 == 0 && threadIdx.x == 0 && a.terms)
+        reinterpret_cast<float4*>(a.terms)[b.wave] = loss_terms(a, w, b.wave, tt, E);
 }
 
 }  // namespace graf

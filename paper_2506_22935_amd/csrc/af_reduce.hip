@@ -31,6 +31,173 @@ __global__ __launch_bounds__(256) void phase_to_signal_kernel(const float* phi, 
     }
 }
 
+// Sum over a 256-thread block in a fixed order (wavefront sums, then the four
+// waves in order); every thread gets the result.
+__device__ float block_sum256(float v, float* sh) {
+    v = wave_allsum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// The experiment loss's per-waveform terms (Sec. 7.1.1, Eq. 18 as a power
+// ratio): the hard-PSL maximum over the segment records (larger power, then
+// the smaller cell index), chi at that cell by its defining sum, and the
+// subgradient there, dp/d conj(chi) = chi / E^2 with dPSL/dE = -2 PSL / E,
+// through the single-cell lag-product adjoint; and the spectral variance
+// V = var(P / sum P) of the N-point spectrum X of s with
+// dV/d conj(s[n]) = sum_j c_j X_j e^{+j 2 pi j n / N},
+// c_j = 2 (x_j - sum x^2) / (N S).  Dynamic LDS: samples, the N twiddles
+// and c_j X_j (3 N complex64).
+__global__ __launch_bounds__(256) void extra_kernel(ExtraArgs a) {
+    extern __shared__ float2 xs[];
+    __shared__ float sh[4];
+    __shared__ float shp[4];
+    __shared__ int shi[4];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const WaveDesc w = a.waves[b];
+    const int N = w.n;
+    const float2* __restrict__ s = a.s + w.s_off;
+    float2* sv = xs;
+    float2* twn = xs + N;
+    float2* cx = xs + 2 * N;
+    for (int p = t; p < N; p += 256) sv[p] = s[p];
+    if (a.spec) {
+        for (int r = t; r < N; r += 256) {
+            float sn, cs;
+            sincospif(2.f * (float)r / (float)N, &sn, &cs);
+            twn[r] = make_float2(cs, -sn);  // exp(-j 2 pi r / N)
+        }
+    }
+    __syncthreads();
+
+    // ---- hard PSL: the maximising cell and chi there
+    float pmax = -1.f;
+    int tau = 0, kst = 0;
+    float2 G = make_float2(0.f, 0.f);
+    float E = 1.f;
+    const int M = w.m;
+    const int RL = w.circ ? N : M;
+    const int tsh = a.log2_mmax - w.log2m;
+    if (a.psl) {
+        float bp = -1.f;
+        int bi = 0x7fffffff;
+        for (int j = t; j < w.seg_count; j += 256) {
+            const Part pr = a.parts[w.seg_begin + j];
+            if (pr.psl_p > bp || (pr.psl_p == bp && pr.psl_i < bi)) {
+                bp = pr.psl_p;
+                bi = pr.psl_i;
+            }
+        }
+        const float wm = wave_allmax(bp);
+        bi = wave_allmin_int(bp == wm ? bi : 0x7fffffff);
+        __syncthreads();
+        if ((t & 63) == 0) {
+            shp[t >> 6] = wm;
+            shi[t >> 6] = bi;
+        }
+        __syncthreads();
+        int ci = shi[0];
+        pmax = shp[0];
+        for (int i = 1; i < 4; ++i)
+            if (shp[i] > pmax || (shp[i] == pmax && shi[i] < ci)) {
+                pmax = shp[i];
+                ci = shi[i];
+            }
+        tau = ci / RL;
+        kst = ci - tau * RL;
+        // chi(tau, k*) = sum_n s[n] conj(s[n - tau]) w^{k* n}: aperiodic over
+        // n in [tau, N) with w = w_M; periodic over every n with the partner
+        // index modulo N and w = w_N = w_M^2
+        float2 c = make_float2(0.f, 0.f);
+        for (int n = t; n < N; n += 256) {
+            int m;
+            if (w.circ) {
+                m = n >= tau ? n - tau : n - tau + N;
+            } else {
+                if (n < tau) continue;
+                m = n - tau;
+            }
+            const int ti = (int)(((int64_t)kst * n * (w.circ ? 2 : 1)) & (M - 1));
+            c = cadd(c, cmul(cmulc(sv[n], sv[m]), a.tw[ti << tsh]));
+        }
+        c.x = block_sum256(c.x, sh);
+        c.y = block_sum256(c.y, sh);
+        E = a.energy[b];
+        const float invE2 = 1.f / (E * E);
+        G = make_float2(c.x * invE2, c.y * invE2);
+    }
+
+    // ---- spectral variance of the N-point spectrum
+    float V = 0.f;
+    if (a.spec) {
+        float ps = 0.f;
+        for (int j = t; j < N; j += 256) {
+            float2 x = make_float2(0.f, 0.f);
+            for (int n = 0; n < N; ++n) x = cadd(x, cmul(sv[n], twn[(int)(((int64_t)j * n) % N)]));
+            cx[j] = x;
+            ps += cabs2(x);
+        }
+        const float S = block_sum256(ps, sh);
+        const float invS = 1.f / S, invN = 1.f / (float)N;
+        float q2 = 0.f, dv = 0.f;
+        for (int j = t; j < N; j += 256) {
+            const float x = cabs2(cx[j]) * invS;
+            q2 = fmaf(x, x, q2);
+            dv = fmaf(x - invN, x - invN, dv);
+        }
+        const float sx2 = block_sum256(q2, sh);
+        V = block_sum256(dv, sh) * invN;
+        const float cs = 2.f * invN * invS;
+        for (int j = t; j < N; j += 256) {
+            const float x = cabs2(cx[j]) * invS;
+            cx[j] = cscale(cx[j], cs * (x - sx2));
+        }
+        __syncthreads();
+    }
+
+    // ---- gradient: w_psl (single-cell adjoint + energy term) + w_spec dV/d conj(s)
+    if (a.g_extra) {
+        for (int p = t; p < N; p += 256) {
+            float2 g = make_float2(0.f, 0.f);
+            if (a.psl) {
+                // Q(n) = G e^{+j 2 pi k* n / RL}
+                auto Q = [&](int n) {
+                    const int ti = (int)(((int64_t)kst * n * (w.circ ? 2 : 1)) & (M - 1));
+                    return cmulc(G, a.tw[ti << tsh]);
+                };
+                float2 gp = make_float2(0.f, 0.f);
+                if (w.circ) {
+                    const int lo = p >= tau ? p - tau : p - tau + N;
+                    const int hi = p + tau < N ? p + tau : p + tau - N;
+                    gp = cadd(cmul(Q(p), sv[lo]), cmul(cconj(Q(hi)), sv[hi]));
+                } else {
+                    if (p >= tau) gp = cmul(Q(p), sv[p - tau]);
+                    if (p + tau < N) gp = cadd(gp, cmul(cconj(Q(p + tau)), sv[p + tau]));
+                }
+                const float de = -2.f * pmax / E;
+                gp.x = fmaf(de, sv[p].x, gp.x);
+                gp.y = fmaf(de, sv[p].y, gp.y);
+                g = cscale(gp, a.w_psl);
+            }
+            if (a.spec) {
+                float2 x = make_float2(0.f, 0.f);
+                for (int j = 0; j < N; ++j) x = cadd(x, cmulc(cx[j], twn[(int)(((int64_t)j * p) % N)]));
+                g = cadd(g, cscale(x, a.w_spec));
+            }
+            a.g_extra[w.s_off + p] = g;
+        }
+    }
+    if (t == 0) {
+        if (a.vals) {
+            a.vals[2 * b] = a.psl ? pmax : 0.f;
+            a.vals[2 * b + 1] = V;
+        }
+        if (a.spec_out) a.spec_out[b] = V;
+    }
+}
+
 // ------------------------------------------------------------ launchers --
 void* variant_kernel_0(int mode, int lg, int circ);
 void* variant_kernel_1(int mode, int lg, int circ);
@@ -100,6 +267,20 @@ hipError_t launch_reduce_adam(const ReduceArgs& a, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, st, a.step);
+    return hipGetLastError();
+}
+
+hipError_t launch_extra(const ExtraArgs& a, int batch, int max_n, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    const int lds = 3 * max_n * (int)sizeof(float2);
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute((const void*)extra_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 3 * 4096 * 8);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(extra_kernel, dim3(batch), dim3(256), (size_t)lds, st, a);
     return hipGetLastError();
 }
 

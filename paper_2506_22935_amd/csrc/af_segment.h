@@ -418,6 +418,10 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
     float2* const mlb = reinterpret_cast<float2*>(scratch);
     double isl = 0.0, ls = 0.0, dle = 0.0;
+    // hard PSL: this lane's largest sidelobe power and its cell (tau >= 0 row)
+    constexpr bool HARD_MODE = MODE == MODE_FWD || MODE == MODE_FUSED_ISL;
+    float hp = -1.f;
+    int hi = 0;
     float lm = (want_lse && (lse_fixed || MODE == MODE_LOSS)) ? lse_ref(a.eps) : -INFINITY;
 
     // Y' of lag tau, half h, in the exit layout v[q] = Y'[2 (l + qL) + h]
@@ -558,11 +562,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // One straight-line copy per loss configuration (shift rule,
             // banded weights, mainlobe complement, soft-PSL on/off): every
             // condition left inside is per lane and becomes a select.
-            auto epilogue = [&](auto fixed_c, auto banded_c, auto compl_c, auto psl_c) {
+            auto epilogue = [&](auto fixed_c, auto banded_c, auto compl_c, auto psl_c, auto hard_c) {
                 constexpr bool FIXED = decltype(fixed_c)::value;
                 constexpr bool BANDED = decltype(banded_c)::value;
                 constexpr bool COMPL = decltype(compl_c)::value;
                 constexpr bool PSL = decltype(psl_c)::value;
+                constexpr bool HARD = decltype(hard_c)::value;  // record the hard-PSL maximum
                 const float c_main = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
@@ -580,6 +585,13 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     const float av = NEED_IA ? xa * ia : __builtin_amdgcn_sqrtf(xa);
                     const bool main_cell = active && main_tau && kc <= w.h_k;
                     const bool sd = active && !main_cell;
+                    if constexpr (HARD) {
+                        // largest power, then the smallest cell index
+                        const int ci = tau * RL + k;
+                        const bool better = sd && (pw > hp || (pw == hp && ci < hi));
+                        hp = better ? pw : hp;
+                        hi = better ? ci : hi;
+                    }
                     float wt = 1.f;
                     if constexpr (BANDED) {
                         // the band index is in [0, 30] for every bin
@@ -653,35 +665,39 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             };
             using T_ = std::integral_constant<bool, true>;
             using F_ = std::integral_constant<bool, false>;
-            auto by_loss = [&](auto fixed_c, auto psl_c) {
+            auto by_loss = [&](auto fixed_c, auto psl_c, auto hard_c) {
                 if (banded)
-                    epilogue(fixed_c, T_{}, F_{}, psl_c);
+                    epilogue(fixed_c, T_{}, F_{}, psl_c, hard_c);
                 else if (compl_isl)
-                    epilogue(fixed_c, F_{}, T_{}, psl_c);
+                    epilogue(fixed_c, F_{}, T_{}, psl_c, hard_c);
                 else
-                    epilogue(fixed_c, F_{}, F_{}, psl_c);
+                    epilogue(fixed_c, F_{}, F_{}, psl_c, hard_c);
             };
             if constexpr (MODE == MODE_FWD) {
-                if (!want_lse)
-                    by_loss(T_{}, F_{});
+                if (!want_lse && a.psl_hard)
+                    by_loss(T_{}, F_{}, T_{});
+                else if (!want_lse)
+                    by_loss(T_{}, F_{}, F_{});
                 else if (lse_fixed)
-                    by_loss(T_{}, T_{});
+                    by_loss(T_{}, T_{}, F_{});
                 else
-                    by_loss(F_{}, T_{});
+                    by_loss(F_{}, T_{}, F_{});
             } else if constexpr (MODE == MODE_BWD_LOSS) {
                 if (a.w_psl != 0.f)
-                    by_loss(T_{}, T_{});
+                    by_loss(T_{}, T_{}, F_{});
                 else
-                    by_loss(T_{}, F_{});
+                    by_loss(T_{}, F_{}, F_{});
             } else if constexpr (MODE == MODE_BWD_MAG) {
-                epilogue(T_{}, F_{}, F_{}, F_{});
+                epilogue(T_{}, F_{}, F_{}, F_{}, F_{});
             } else if constexpr (MODE == MODE_LOSS) {
                 if (compl_isl)
-                    epilogue(T_{}, F_{}, T_{}, T_{});
+                    epilogue(T_{}, F_{}, T_{}, T_{}, F_{});
                 else
-                    epilogue(T_{}, F_{}, F_{}, T_{});
+                    epilogue(T_{}, F_{}, F_{}, T_{}, F_{});
+            } else if (a.psl_hard) {
+                by_loss(T_{}, F_{}, T_{});
             } else {
-                by_loss(T_{}, F_{});
+                by_loss(T_{}, F_{}, F_{});
             }
             isl += (double)(mult * isl_f);
             dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f);
@@ -859,12 +875,23 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
     isl = (double)wave_sum((float)isl);
     if (MODE != MODE_FWD) dle = (double)wave_sum((float)dle);
+    // hard PSL: the wavefront's largest power, then its smallest cell index
+    const bool hard = HARD_MODE && a.psl_hard;
+    if (hard) {
+        const float wmx = wave_allmax(hp);
+        hi = wave_allmin_int(hp == wmx ? hi : 0x7fffffff);
+        hp = wmx;
+    }
     __syncthreads();
     if ((tid & 63) == 0) {
         scratch[4 * (tid >> 6) + 0] = isl;
         scratch[4 * (tid >> 6) + 1] = (double)lm;
         scratch[4 * (tid >> 6) + 2] = ls;
         scratch[4 * (tid >> 6) + 3] = dle;
+        if (hard) {
+            scratch[64 + 2 * (tid >> 6)] = (double)hp;
+            scratch[65 + 2 * (tid >> 6)] = (double)hi;
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -873,11 +900,22 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         pr.lse_s = 0.0;
         pr.dle = 0.0;
         pr.lse_m = -INFINITY;
-        pr.pad = 0.f;
+        pr.psl_p = -1.f;
+        pr.psl_i = 0;
+        pr.pad = 0;
         for (int i = 0; i < WGS / 64; ++i) {
             pr.isl += scratch[4 * i + 0];
             if (FWD_SUMS) lse_merge(pr.lse_m, pr.lse_s, (float)scratch[4 * i + 1], scratch[4 * i + 2], inv_t2);
             pr.dle += scratch[4 * i + 3];
+            if (hard) {
+                // waves in order: larger power, then the smaller cell index
+                const float p = (float)scratch[64 + 2 * i];
+                const int c = (int)scratch[65 + 2 * i];
+                if (p > pr.psl_p || (p == pr.psl_p && c < pr.psl_i)) {
+                    pr.psl_p = p;
+                    pr.psl_i = c;
+                }
+            }
         }
         if (MODE == MODE_BWD_LOSS)
             a.parts[sg.rec].dle = pr.dle;
@@ -935,7 +973,8 @@ template <int MODE, typename V, int LG, bool CIRC = false>
 __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     static_assert(!CIRC || (V::SPLIT && V::S_LDS), "periodic AF: split variants with samples in LDS");
     extern __shared__ float2 dyn[];
-    __shared__ double scratch[64];
+    // block reductions; [64, 96) holds the per-wave hard-PSL records
+    __shared__ double scratch[96];
     constexpr int MH = 1 << LG;
     float2* lds = dyn;
     float2* s_lds = V::S_LDS ? dyn + V::fft_lds_bytes(LG) / 8 : nullptr;
