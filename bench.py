@@ -429,6 +429,96 @@ def cpu_baseline_periodic(n, phases, budget_s=10.0):
                 sample="periodic loss + gradient of the first %d waveforms (N=M=%d), %.1f s" % (done, n, t_all))
 
 
+def bench_experiment(args, torch):
+    """The paper's experiment (Sec. 7.1): L = PSL + lambda * alpha *
+    SpectralVariance (alpha = 2000, hard PSL as a power ratio, mainlobe the
+    origin cell only) on the periodic AF of N = M = 256 random-phase codes,
+    Adam lr 0.01 for 2000 iterations, lambda in {0, 0.25, 0.5, 1, 2}; 512
+    codes per lambda, the iterations captured in a HIP graph (100 steps,
+    replayed 20 times).  A step is one optimiser iteration of the batch."""
+    import numpy as np
+    from paper_2506_22935_amd import af, workloads as W
+    B, n, iters, chunk, alpha = 512, 256, 2000, 100, 2000.0
+    lams = [0.0, 0.25, 0.5, 1.0, 2.0]
+    phases = W.random_phases(B * n, seed=args.seed + 21)
+    plan = af.Plan([n] * B, [n] * B, h_tau=0, h_k=0, eps=1e-12, periodic=True)
+    ws = plan.workspace
+    terms = torch.empty(B, 4, device="cuda")
+    per = {}
+    total_ms = 0.0
+    for lam in lams:
+        kw = dict(w_isl=0.0, w_psl=1.0, psl_hard=True, w_spec=lam * alpha, lr=0.01)
+        st = af.PhaseState(torch.from_numpy(phases.astype(np.float32)).cuda())
+        plan.loss(st.s, w_isl=0.0, w_psl=1.0, psl_hard=True, w_spec=lam * alpha, grad=False, out_terms=terms)
+        psl0 = float(terms[:, 2].mean())
+        # warm the kernels on a scratch state, then capture `chunk` steps
+        scratch = af.PhaseState(st.phi.clone())
+        for _ in range(3):
+            plan.optim_step(scratch, ws=ws, terms=terms, **kw)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                for _ in range(chunk):
+                    plan.optim_step(st, ws=ws, terms=terms, **kw)
+        ms = timed(lambda: [g.replay() for _ in range(iters // chunk)], 1, torch)
+        total_ms += ms
+        plan.loss(st.s, w_isl=0.0, w_psl=1.0, psl_hard=True, w_spec=lam * alpha, grad=False, out_terms=terms)
+        v, _ = plan.spectral_variance(st.s, ws=ws)
+        psl = terms[:, 2].double()
+        per[str(lam)] = dict(ms_per_iteration=round(ms / iters, 5), seconds_2000_iterations=round(ms / 1e3, 4),
+                             mean_loss=float(terms[:, 0].mean()), mean_psl_db=float((10 * psl.log10()).mean()),
+                             mean_psl_db_start=round(10 * math.log10(psl0), 3),
+                             mean_spectral_variance=float(v.mean()), step_counter=int(st.step.item()))
+        log("experiment lambda %.2f: %.4f ms/iteration, PSL %.2f dB (start %.2f), spectral variance %.3g, loss %.4f"
+            % (lam, ms / iters, per[str(lam)]["mean_psl_db"], per[str(lam)]["mean_psl_db_start"],
+               per[str(lam)]["mean_spectral_variance"], per[str(lam)]["mean_loss"]))
+    # roofline of the dominant kernel: the forward pass, one N-point transform per lag tau in [0, N/2]
+    grad = torch.empty(B * n, dtype=torch.complex64, device="cuda")
+    s = torch.from_numpy(W.unimodular(phases)).cuda()
+    lpk = dict(w_isl=0.0, w_psl=1.0, psl_hard=True, w_spec=0.5 * alpha)
+    fwd_ms = timed(lambda: plan.loss_stage(0, s, terms, grad, None, ws=ws, **lpk), 50, torch)
+    extra_ms = timed(lambda: plan.loss_stage(1, s, terms, grad, None, ws=ws, **lpk), 50, torch)
+    flops = B * fft_flops(n // 2 + 1, n)
+    ach = flops / (fwd_ms * 1e-3) / 1e12
+    steps_total = B * iters * len(lams)
+    out = dict(metric="experiment-loss Adam iterations/s (waveform-iterations)", unit="waveform-iterations/s",
+               value=steps_total / (total_ms * 1e-3), ms_per_step=total_ms / (iters * len(lams)),
+               config=dict(workload="experiment: PSL + lambda*2000*SpectralVariance, periodic AF N=M=256, Adam lr "
+                                    "0.01 x 2000 iterations, lambda in {0,0.25,0.5,1,2}, 512 codes per lambda",
+                           waveforms_per_lambda=B, n=n, iterations=iters, per_lambda=per,
+                           stage_ms=dict(forward_pass=round(fwd_ms, 5), psl_and_spectral_terms=round(extra_ms, 5)),
+                           paper_context="Sec. 7.2 (laptop CPU, one waveform): ~67 s for 2000 iterations at "
+                                         "lambda 0.5, final loss 0.022; spectral variance 2.02e-5 (lambda 0), "
+                                         "3.03e-6 (0.5), 8.02e-7 (2)"),
+               roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                             frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
+                             kernel="forward pass with the hard-PSL maximum (one N-point transform per lag)",
+                             kernel_ms=round(fwd_ms, 5), flops_per_launch=flops))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_experiment(n, phases, budget_s=10.0)
+    return out
+
+
+def cpu_baseline_experiment(n, phases, budget_s=10.0):
+    """The oracle's experiment loss + gradient (lambda 0.5) on consecutive
+    waveforms of the batch until the budget is spent: iterations per second."""
+    import oracle as O
+    from oracle import _native
+    from paper_2506_22935_amd import workloads as W
+    done, t_all = 0, 0.0
+    while t_all < budget_s and (done + 1) * n <= len(phases):
+        s = O.to_c64_exact(W.unimodular(phases[done * n:(done + 1) * n]))
+        t0 = time.perf_counter()
+        O.experiment_loss_and_grad(s, n, 0.5, periodic=True)
+        t_all += time.perf_counter() - t0
+        done += 1
+    return dict(value=done / t_all, unit="waveform-iterations/s", cores=_native.threads(), kind="oracle",
+                sample="experiment loss + gradient (lambda 0.5, periodic N=M=256) of the first %d waveforms, %.1f s"
+                       % (done, t_all))
+
+
 def bench_copy(args, torch):
     """Plain device copy of known size (counter calibration)."""
     nbytes = 1 << 30
@@ -442,7 +532,7 @@ def bench_copy(args, torch):
 
 
 WORKLOADS = {"single": bench_single, "uneven": bench_uneven, "large": bench_large, "proposal": bench_proposal,
-             "periodic": bench_periodic, "copy": bench_copy}
+             "periodic": bench_periodic, "experiment": bench_experiment, "copy": bench_copy}
 
 
 def main():

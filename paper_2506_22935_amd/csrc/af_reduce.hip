@@ -134,8 +134,14 @@ __global__ __launch_bounds__(256) void extra_kernel(ExtraArgs a) {
     if (a.spec) {
         float ps = 0.f;
         for (int j = t; j < N; j += 256) {
+            // X_j = sum_n s[n] w_N^{j n}: the twiddle index j n mod N advances by j
             float2 x = make_float2(0.f, 0.f);
-            for (int n = 0; n < N; ++n) x = cadd(x, cmul(sv[n], twn[(int)(((int64_t)j * n) % N)]));
+            int r = 0;
+            for (int n = 0; n < N; ++n) {
+                x = cadd(x, cmul(sv[n], twn[r]));
+                r += j;
+                r = r >= N ? r - N : r;
+            }
             cx[j] = x;
             ps += cabs2(x);
         }
@@ -183,7 +189,12 @@ __global__ __launch_bounds__(256) void extra_kernel(ExtraArgs a) {
             }
             if (a.spec) {
                 float2 x = make_float2(0.f, 0.f);
-                for (int j = 0; j < N; ++j) x = cadd(x, cmulc(cx[j], twn[(int)(((int64_t)j * p) % N)]));
+                int r = 0;  // j p mod N
+                for (int j = 0; j < N; ++j) {
+                    x = cadd(x, cmulc(cx[j], twn[r]));
+                    r += p;
+                    r = r >= N ? r - N : r;
+                }
                 g = cadd(g, cscale(x, a.w_spec));
             }
             a.g_extra[w.s_off + p] = g;
