@@ -288,7 +288,7 @@ def bench_large(args, torch):
     g = torch.empty(n, dtype=torch.complex64, device="cuda")
     best = None
     for store in (1, 2):
-        plan = af.Plan([n], [m], [T], eps=1e-12, store_mode=store, budget_bytes=16 << 30)
+        plan = af.Plan([n], [m], [T], eps=1e-12, store_mode=store, budget_bytes=16 << 30, variant=args.variant)
         ws = plan.workspace
 
         def step():
@@ -302,15 +302,16 @@ def bench_large(args, torch):
         bwd = timed(lambda: plan.backward(s, ga, ws=ws, out=g), args.steps, torch)
         log("large store=%d: %.3f ms/step (forward %.3f, backward %.3f)" % (store, ms, fwd, bwd))
         if best is None or ms < best[0]:
-            best = (ms, fwd, bwd, store)
-    ms, fwd, bwd, store = best
+            best = (ms, fwd, bwd, store, plan.summary()["variant"])
+    ms, fwd, bwd, store = best[:4]
     dom_ms = max(fwd, bwd)
     nbytes = 4.0 * cells  # forward writes the a grid; backward reads the dL/da grid
     ach = nbytes / (dom_ms * 1e-3) / 1e9
     out = dict(value=cells / (ms * 1e-3), ms_per_step=ms,
                config=dict(workload="large: N=16384 LFM (BT=1000) + 0.3 rad phase noise, |tau|<=2048 x M=32768, "
                                     "materialised fwd+bwd, 16 GB budget",
-                           cells=cells, store=bool(store == 1), forward_ms=round(fwd, 4), backward_ms=round(bwd, 4),
+                           cells=cells, store=bool(store == 1), variant=best[4], forward_ms=round(fwd, 4),
+                           backward_ms=round(bwd, 4),
                            hbm_frac_8B_per_cell=round(8.0 * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
                roofline=dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                              frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,

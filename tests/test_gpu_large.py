@@ -92,3 +92,31 @@ def test_budget_decides_store_or_recompute(setup):
     with pytest.raises(_lib.AfError) as ei:
         af.Plan([N], [M], [T], eps=EPS, store_mode=1, budget_bytes=store_bytes // 2)
     assert ei.value.code == -3
+
+
+@pytest.mark.parametrize("variant", [2])
+@pytest.mark.parametrize("n,m,T", [(6000, 16384, 300), (N, M, 200)])
+def test_halves_in_turn_variants(setup, variant, n, m, T):
+    # the halves-in-turn variant at both of its sizes with random-phase codes
+    # and small windows: sampled forward rows against the direct sums, the
+    # magnitude backward against the oracle's FFT-step route
+    say("halves in turn", variant, n, m, T)
+    af = setup["af"]
+    s = W.random_code(n, seed=40 + n)
+    sr = O.to_c64_exact(s)
+    sd = torch.from_numpy(s).cuda()
+    plan = af.Plan([n], [m], [T], eps=EPS, store_mode=2, variant=variant)
+    assert plan.summary()["variant"] == variant
+    ws = plan.new_workspace()
+    mag, _, _ = plan.forward(sd, mag=True, ws=ws)
+    E = O.energy(sr)
+    taus = [0, 1, -1, T, -T, T // 2]
+    ref = O.magnitude(O.chi_rows(sr, m, taus), E, EPS)
+    grid = plan.grid(mag, 0).cpu().numpy()
+    for i, tau in enumerate(taus):
+        assert np.max(np.abs(grid[tau + T] - ref[i])) <= 1e-5, tau
+    a = O.magnitude(O.chi_rows_fft(sr, m, range(-T, T + 1)), E, EPS)
+    up = (np.random.default_rng(n).standard_normal(a.shape) * a).astype(np.float32)
+    g = plan.backward(sd, torch.from_numpy(up.ravel()).cuda(), ws=ws).cpu().numpy().astype(np.complex128)
+    gref = O.magnitude_backward_fft(sr, m, T, up.astype(np.float64), EPS)
+    assert np.max(np.abs(g - gref)) <= 1e-4 * np.max(np.abs(gref))
