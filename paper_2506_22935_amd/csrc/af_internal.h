@@ -1,5 +1,5 @@
-// Types shared by the host planner (af_api.hip) and the kernels
-// (af_kernels.hip).  Not part of the public C-ABI.
+// Types shared by the host planner (af_api.hip) and the kernels (af_segment.h
+// via af_variant.hip, af_reduce.hip).  Not part of the public C-ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -150,7 +150,7 @@ struct ExtraArgs {
 };
 hipError_t launch_extra(const ExtraArgs& a, int batch, int max_n, hipStream_t st);
 
-// launchers (af_kernels.hip)
+// launchers (af_reduce.hip)
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_reduce_adam(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_phase_to_signal(const float* phi, float2* s, int64_t count, hipStream_t st);

@@ -562,12 +562,15 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // One straight-line copy per loss configuration (shift rule,
             // banded weights, mainlobe complement, soft-PSL on/off): every
             // condition left inside is per lane and becomes a select.
-            auto epilogue = [&](auto fixed_c, auto banded_c, auto compl_c, auto psl_c, auto hard_c) {
+            // MAIN: the lag may hold mainlobe cells (tau <= h_tau); without
+            // them every mainlobe test is compiled out
+            auto epilogue = [&](auto fixed_c, auto banded_c, auto compl_c, auto psl_c, auto hard_c, auto main_c) {
                 constexpr bool FIXED = decltype(fixed_c)::value;
                 constexpr bool BANDED = decltype(banded_c)::value;
                 constexpr bool COMPL = decltype(compl_c)::value;
                 constexpr bool PSL = decltype(psl_c)::value;
                 constexpr bool HARD = decltype(hard_c)::value;  // record the hard-PSL maximum
+                constexpr bool MAIN = decltype(main_c)::value;
                 const float c_main = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
@@ -583,7 +586,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     const float xa = pw + a.eps;
                     const float ia = NEED_IA ? __builtin_amdgcn_rsqf(xa) : 0.f;
                     const float av = NEED_IA ? xa * ia : __builtin_amdgcn_sqrtf(xa);
-                    const bool main_cell = active && main_tau && kc <= w.h_k;
+                    const bool main_cell = MAIN && active && main_tau && kc <= w.h_k;
                     const bool sd = active && !main_cell;
                     if constexpr (HARD) {
                         // largest power, then the smallest cell index
@@ -665,40 +668,48 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             };
             using T_ = std::integral_constant<bool, true>;
             using F_ = std::integral_constant<bool, false>;
-            auto by_loss = [&](auto fixed_c, auto psl_c, auto hard_c) {
-                if (banded)
-                    epilogue(fixed_c, T_{}, F_{}, psl_c, hard_c);
-                else if (compl_isl)
-                    epilogue(fixed_c, F_{}, T_{}, psl_c, hard_c);
-                else
-                    epilogue(fixed_c, F_{}, F_{}, psl_c, hard_c);
-            };
-            if constexpr (MODE == MODE_FWD) {
-                if (!want_lse && a.psl_hard)
+            auto dispatch = [&](auto main_c) {
+                auto by_loss = [&](auto fixed_c, auto psl_c, auto hard_c) {
+                    if (banded)
+                        epilogue(fixed_c, T_{}, F_{}, psl_c, hard_c, main_c);
+                    else if (compl_isl)
+                        epilogue(fixed_c, F_{}, T_{}, psl_c, hard_c, main_c);
+                    else
+                        epilogue(fixed_c, F_{}, F_{}, psl_c, hard_c, main_c);
+                };
+                if constexpr (MODE == MODE_FWD) {
+                    if (!want_lse && a.psl_hard)
+                        by_loss(T_{}, F_{}, T_{});
+                    else if (!want_lse)
+                        by_loss(T_{}, F_{}, F_{});
+                    else if (lse_fixed)
+                        by_loss(T_{}, T_{}, F_{});
+                    else
+                        by_loss(F_{}, T_{}, F_{});
+                } else if constexpr (MODE == MODE_BWD_LOSS) {
+                    if (a.w_psl != 0.f)
+                        by_loss(T_{}, T_{}, F_{});
+                    else
+                        by_loss(T_{}, F_{}, F_{});
+                } else if constexpr (MODE == MODE_BWD_MAG) {
+                    epilogue(T_{}, F_{}, F_{}, F_{}, F_{}, main_c);
+                } else if constexpr (MODE == MODE_LOSS) {
+                    if (compl_isl)
+                        epilogue(T_{}, F_{}, T_{}, T_{}, F_{}, main_c);
+                    else
+                        epilogue(T_{}, F_{}, F_{}, T_{}, F_{}, main_c);
+                } else if (a.psl_hard) {
                     by_loss(T_{}, F_{}, T_{});
-                else if (!want_lse)
+                } else {
                     by_loss(T_{}, F_{}, F_{});
-                else if (lse_fixed)
-                    by_loss(T_{}, T_{}, F_{});
-                else
-                    by_loss(F_{}, T_{}, F_{});
-            } else if constexpr (MODE == MODE_BWD_LOSS) {
-                if (a.w_psl != 0.f)
-                    by_loss(T_{}, T_{}, F_{});
-                else
-                    by_loss(T_{}, F_{}, F_{});
-            } else if constexpr (MODE == MODE_BWD_MAG) {
-                epilogue(T_{}, F_{}, F_{}, F_{}, F_{});
-            } else if constexpr (MODE == MODE_LOSS) {
-                if (compl_isl)
-                    epilogue(T_{}, F_{}, T_{}, T_{}, F_{});
-                else
-                    epilogue(T_{}, F_{}, F_{}, T_{}, F_{});
-            } else if (a.psl_hard) {
-                by_loss(T_{}, F_{}, T_{});
-            } else {
-                by_loss(T_{}, F_{}, F_{});
-            }
+                }
+            };
+            // the mainlobe lags (tau <= h_tau) are a few of the N; BWD_MAG has
+            // no mainlobe logic
+            if (MODE != MODE_BWD_MAG && main_tau)
+                dispatch(T_{});
+            else
+                dispatch(F_{});
             isl += (double)(mult * isl_f);
             dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f);
             if (FWD_SUMS && want_lse && (lse_fixed || MODE == MODE_LOSS)) {
