@@ -117,14 +117,19 @@ def isl_weights(n, m, max_lag, h_tau, h_k, u=None, v=None):
 
 
 class LossParams:
-    """L = w_isl * ISL + w_psl * softPSL over the sidelobe region.
+    """L = w_isl * ISL + w_psl * softPSL + w_match * Match over the grid.
 
     ISL = sum_{Omega_s} W p                         (Eq. 19, weighted)
     softPSL = T log sum_{Omega_s} exp(a / T)        (smooth stand-in for Eq. 18)
+    Match = sum over every cell of (p - p_target)^2 (L_match of Sec. 5.2 with
+            the AF in power, as the paper's chi, against a target surface
+            p_target laid out like the grid)
     """
 
     def __init__(self, w_isl=1.0, w_psl=0.0, temp=0.05, h_tau=1, h_k=1,
-                 u=None, v=None, eps=1e-12):
+                 u=None, v=None, eps=1e-12, match=None, w_match=0.0):
+        self.match = None if match is None else np.asarray(match, dtype=np.float64)
+        self.w_match = float(w_match)
         self.w_isl, self.w_psl, self.temp = float(w_isl), float(w_psl), float(temp)
         self.h_tau, self.h_k = int(h_tau), int(h_k)
         self.u = None if u is None else np.asarray(u, dtype=np.float64)
@@ -150,8 +155,9 @@ def _loss_terms_on(c, E, params, side, W):
     mx = float(av.max())
     S = float(np.sum(np.exp((av - mx) / params.temp)))
     soft = mx + params.temp * math.log(S)
-    loss = params.w_isl * isl + params.w_psl * soft
-    return dict(loss=loss, isl=isl, softpsl=soft, psl_db=psl_db(p, side),
+    match = float(np.sum((p - params.match) ** 2)) if params.match is not None else 0.0
+    loss = params.w_isl * isl + params.w_psl * soft + params.w_match * match
+    return dict(loss=loss, isl=isl, softpsl=soft, match=match, psl_db=psl_db(p, side),
                 p=p, a=a, side=side, W=W, lse_max=mx, lse_sum=S)
 
 
@@ -187,9 +193,14 @@ def _cell_upstream(t, c, E, params):
     q = np.zeros_like(a)
     q[side] = np.exp((a[side] - t["lse_max"]) / params.temp) / t["lse_sum"]
     coef = params.w_isl * W / (E * E) + params.w_psl * q / (2.0 * E * E * a)
-    G = coef * c
     dLdE = (-2.0 * params.w_isl * t["isl"] / E
             - params.w_psl * float(np.sum(q * p / (E * a))))
+    if params.match is not None and params.w_match != 0.0:
+        # d/d conj(chi) of (p - p_t)^2 = 2 (p - p_t) chi / E^2; dp/dE = -2 p / E
+        d = p - params.match
+        coef = coef + params.w_match * 2.0 * d / (E * E)
+        dLdE += params.w_match * float(np.sum(2.0 * d * (-2.0 * p / E)))
+    G = coef * c
     return G, dLdE
 
 

@@ -617,3 +617,31 @@ def test_experiment_loss_finite_differences(periodic, n, m, lam):
     assert top[1] - top[0] > 1e-6  # a unique maximum up to its twin cell
     fd = _fd_grad(f, s, h=1e-7)
     assert np.max(np.abs(r["g"] - fd)) <= 1e-5 * max(1.0, np.max(np.abs(fd)))
+
+
+# --------------------------------------------------------------------------
+# L_match of the composite loss (Sec. 5.2): sum (p - p_target)^2
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m,T", [(8, 16, 7), (13, 32, 4)])
+def test_match_loss_finite_differences(n, m, T):
+    rng = np.random.default_rng(n + T)
+    target = rng.uniform(0, 0.2, (2 * T + 1, m))
+    params = O.LossParams(w_isl=0.3, w_match=2.0, match=target)
+    s = rand_complex(n, 120 + n)
+    g = O.loss_and_grad(s, m, T, params)["g"]
+    fd = _fd_grad(lambda x: _loss_value(x, m, T, params), s)
+    assert np.max(np.abs(g - fd)) <= 1e-6 * max(1.0, np.max(np.abs(fd)))
+
+
+def test_match_loss_is_zero_at_its_own_surface():
+    # the target surface of the waveform itself is the minimum: L = 0, g = 0,
+    # and a scaled or phase-rotated copy of s matches as well
+    n, m = 16, 32
+    s = rand_complex(n, 130)
+    p = O.power(O.chi(s, m), O.energy(s))
+    params = O.LossParams(w_isl=0.0, w_match=1.0, match=p)
+    r = O.loss_and_grad(s, m, n - 1, params)
+    assert r["match"] <= 1e-28 and np.max(np.abs(r["g"])) <= 1e-12
+    r2 = O.loss_and_grad(2.5j * s, m, n - 1, params)
+    assert r2["match"] <= 1e-26
