@@ -107,8 +107,14 @@ typedef struct af_plan af_plan;
  * variance of Sec. 7.1.1, var_j(P_j / sum P) with P = |DFT_N(s)|^2 (the
  * N-point spectrum, population variance; N <= 4096).  The experiment loss
  * PSL + lambda * alpha * SpectralVariance is w_psl = 1, psl_hard = 1,
- * w_spec = lambda * alpha.  Zero-initialise the struct: psl_hard = 0 and
- * w_spec = 0 give the soft-PSL losses above. */
+ * w_spec = lambda * alpha.  w_match weights L_match of the composite loss
+ * (Sec. 5.2), the squared Frobenius distance between the AF in power,
+ * p = |chi|^2 / E^2, and match_target over every cell of the grid; it
+ * combines with ISL and the hard PSL, not with the soft PSL
+ * (AF_ERR_UNSUPPORTED).  The hard PSL and L_match need plans whose size
+ * classes run split variants (M <= 8192, or a periodic N <= 4096);
+ * AF_ERR_UNSUPPORTED otherwise.  Zero-initialise the struct: psl_hard = 0, w_spec = 0
+ * and w_match = 0 give the soft-PSL losses above. */
 typedef struct {
     float w_isl;
     float w_psl;
@@ -116,6 +122,8 @@ typedef struct {
     const float* band_w;
     int32_t psl_hard; /* 0 or 1 */
     float w_spec;
+    const float* match_target; /* device float grid of target powers p_t, laid out like the a grid */
+    float w_match;             /* weight of L_match = sum over every cell of (p - p_t)^2 */
 } af_loss_params;
 
 /* Adam settings for af_optim_step (Kingma & Ba; eps outside the square root). */

@@ -33,7 +33,8 @@ class AfPlanOpts(ctypes.Structure):
 
 class AfLossParams(ctypes.Structure):
     _fields_ = [("w_isl", ctypes.c_float), ("w_psl", ctypes.c_float), ("psl_temp", ctypes.c_float),
-                ("band_w", ctypes.c_void_p), ("psl_hard", ctypes.c_int32), ("w_spec", ctypes.c_float)]
+                ("band_w", ctypes.c_void_p), ("psl_hard", ctypes.c_int32), ("w_spec", ctypes.c_float),
+                ("match_target", ctypes.c_void_p), ("w_match", ctypes.c_float)]
 
 
 class AfAdamParams(ctypes.Structure):

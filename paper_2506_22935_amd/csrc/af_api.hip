@@ -451,11 +451,22 @@ af_status check_common(const af_plan* p, const void* s, void* ws, size_t ws_byte
     return AF_OK;
 }
 
+bool hard_psl_or_match(const af_loss_params* lp) {
+    return (lp->psl_hard != 0 && lp->w_psl != 0.f) || lp->w_match != 0.f;
+}
+
 af_status check_loss(const af_plan* p, const af_loss_params* lp) {
     if (!lp) return AF_ERR_INVALID_ARG;
     if (!(lp->psl_temp > 0.f) || !std::isfinite(lp->w_isl) || !std::isfinite(lp->w_psl) || !std::isfinite(lp->w_spec))
         return AF_ERR_INVALID_ARG;
     if (lp->psl_hard != 0 && lp->psl_hard != 1) return AF_ERR_INVALID_ARG;
+    if (!std::isfinite(lp->w_match) || (lp->w_match != 0.f && !lp->match_target)) return AF_ERR_INVALID_ARG;
+    // L_match runs in the forward and fused ISL passes: not with the soft PSL
+    if (lp->w_match != 0.f && lp->w_psl != 0.f && !lp->psl_hard) return AF_ERR_UNSUPPORTED;
+    // the hard PSL and L_match run in the split variants (M <= 8192)
+    if (hard_psl_or_match(lp))
+        for (const af_plan::Class& k : p->classes)
+            if (!graf::variant_info(k.variant, k.lg).split) return AF_ERR_UNSUPPORTED;
     if (lp->w_spec != 0.f && p->max_n > kMaxSpecN) return AF_ERR_UNSUPPORTED;
     return AF_OK;
 }
@@ -472,7 +483,8 @@ bool needs_extra(const af_loss_params* lp) { return hard_psl(lp) || lp->w_spec !
 // uniform ISL weights with full lag windows (the ISL gradient then lives on
 // the mainlobe cells) and variants that split the two half transforms.
 bool fused_loss_ok(const af_plan* p, const af_loss_params* lp) {
-    if (p->loss_passes_opt == 1 || lp->w_psl == 0.f || lp->psl_hard || lp->band_w != nullptr) return false;
+    if (p->loss_passes_opt == 1 || lp->w_psl == 0.f || lp->psl_hard || lp->band_w != nullptr || lp->w_match != 0.f)
+        return false;
     const float inv_t2 = 1.4426950408889634f / lp->psl_temp;
     if (!(std::sqrt(1.f + p->eps) * inv_t2 < 100.f)) return false;
     for (const af_plan::Class& k : p->classes)
@@ -493,6 +505,10 @@ AfArgs loss_args(const af_plan* p, const void* s, const af_loss_params* lp, floa
     a.band_w = lp->band_w;
     a.mag = mag;
     a.psl_hard = hard_psl(lp) ? 1 : 0;
+    if (lp->w_match != 0.f) {
+        a.match_t = lp->match_target;
+        a.w_match = lp->w_match;
+    }
     return a;
 }
 
@@ -500,8 +516,14 @@ AfArgs loss_args(const af_plan* p, const void* s, const af_loss_params* lp, floa
 // none)?  The hard PSL without ISL needs only the forward pass.
 bool loss_writes_slabs(const af_loss_params* lp, bool want_grad) {
     if (!want_grad) return false;
-    if (lp->psl_hard) return lp->w_isl != 0.f;
+    if (lp->psl_hard) return lp->w_isl != 0.f || lp->w_match != 0.f;
     return true;
+}
+
+// Is the forward pass alone enough for this loss (no per-cell gradient:
+// only the hard PSL, whose gradient is one cell's)?
+bool forward_only(const af_loss_params* lp, bool want_grad) {
+    return !want_grad || (lp->psl_hard && lp->w_isl == 0.f && lp->w_match == 0.f);
 }
 
 // The experiment loss's per-waveform kernel (after the AF pass: it reads the
@@ -530,7 +552,7 @@ af_status loss_passes(const af_plan* p, const void* s, const af_loss_params* lp,
                       const WsView& v, hipStream_t st, int only_class = -1) {
     AfArgs a = loss_args(p, s, lp, mag, v);
     af_status rc;
-    if (!want_grad || (lp->psl_hard && lp->w_isl == 0.f)) {
+    if (forward_only(lp, want_grad)) {
         rc = launch(p, graf::MODE_FWD, a, st, only_class);
     } else if (a.w_psl == 0.f) {
         rc = launch(p, graf::MODE_FUSED_ISL, a, st, only_class);
@@ -560,6 +582,7 @@ ReduceArgs loss_reduce_args(const af_plan* p, const void* s, const af_loss_param
     r.psl_scaled = want_grad && fused_loss_ok(p, lp);
     r.psl_hard = hard_psl(lp) ? 1 : 0;
     r.w_spec = lp->w_spec;
+    r.w_match = lp->match_target ? lp->w_match : 0.f;
     r.vals = v.vals;
     r.g_extra = (want_grad && needs_extra(lp)) ? v.extra : nullptr;
     return r;
@@ -725,7 +748,7 @@ af_status af_loss_stage(const af_plan* p, int32_t stage, const void* s, const af
     const WsView v = ws_view(p, ws);
     AfArgs a = loss_args(p, s, lp, mag, v);
     const bool grad = grad_s != nullptr;
-    const bool fwd_only = !grad || (lp->psl_hard && lp->w_isl == 0.f);
+    const bool fwd_only = forward_only(lp, grad);
     const bool fused = !fwd_only && a.w_psl == 0.f;
     const bool fused_loss = !fwd_only && !fused && fused_loss_ok(p, lp);
     switch (stage) {

@@ -42,6 +42,7 @@ struct Part {
     double isl;
     double lse_s;
     double dle;
+    double match;  // sum of (p - p_target)^2 over the segment's cells
     float lse_m;
     float psl_p;
     int psl_i;
@@ -82,6 +83,8 @@ struct AfArgs {
     float2* slabs2;       // [sum isl_segs*N] ISL part of MODE_LOSS
     float* energy;        // [B], written by the segment holding lag 0
     int psl_hard;         // MODE_FWD / MODE_FUSED_ISL: record the hard-PSL maximum
+    const float* match_t; // target power grid of L_match (MODE_FWD / MODE_FUSED_ISL), nullable
+    float w_match;
 };
 
 // The slab reduction runs 256-thread blocks over (256 >> sg_log) samples of
@@ -123,6 +126,7 @@ struct ReduceArgs {
     int* step;            // device step counter (1-based after increment)
     float lr, beta1, beta2, adam_eps;
     // the experiment loss: hard PSL and spectral variance, from extra_kernel
+    float w_match;        // weight of L_match (sum of the segment records' match)
     int psl_hard;         // the PSL term is the hard maximum (vals[2b])
     float w_spec;         // weight of the spectral variance (vals[2b + 1])
     const float2* g_extra;  // their gradient, packed like s; nullable

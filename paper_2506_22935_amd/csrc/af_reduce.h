@@ -28,7 +28,7 @@ __device__ __forceinline__ double wave_sum_d(double v) { return wave_allsum(v); 
 __device__ __forceinline__ void wave_lse_r(float& m, double& s, float inv_t2) { wave_lse_pair(m, s, inv_t2); }
 
 struct WaveTotals {
-    double isl_raw, lse_s, dle;
+    double isl_raw, lse_s, dle, match;
     float lse_m;
 };
 
@@ -36,16 +36,18 @@ struct WaveTotals {
 // a fixed order (thread-strided, wavefront butterflies, waves in order).
 __device__ WaveTotals wave_totals(const ReduceArgs& a, const WaveDesc& w, double* sh) {
     const float inv_t2 = kLog2eR / a.temp;
-    double isl = 0.0, s = 0.0, dle = 0.0;
+    double isl = 0.0, s = 0.0, dle = 0.0, mt = 0.0;
     float m = -INFINITY;
     for (int j = threadIdx.x; j < w.seg_count; j += 256) {
         const Part pr = a.parts[w.seg_begin + j];
         isl += pr.isl;
         dle += pr.dle;
+        mt += pr.match;
         lse_merge_r(m, s, pr.lse_m, pr.lse_s, inv_t2);
     }
     isl = wave_sum_d(isl);
     dle = wave_sum_d(dle);
+    if (a.w_match != 0.f) mt = wave_sum_d(mt);
     wave_lse_r(m, s, inv_t2);
     const int wv = threadIdx.x >> 6;
     __syncthreads();
@@ -54,12 +56,14 @@ __device__ WaveTotals wave_totals(const ReduceArgs& a, const WaveDesc& w, double
         sh[4 * wv + 1] = dle;
         sh[4 * wv + 2] = (double)m;
         sh[4 * wv + 3] = s;
+        sh[16 + wv] = mt;
     }
     __syncthreads();
-    WaveTotals t{0.0, 0.0, 0.0, -INFINITY};
+    WaveTotals t{0.0, 0.0, 0.0, 0.0, -INFINITY};
     for (int i = 0; i < 4; ++i) {
         t.isl_raw += sh[4 * i + 0];
         t.dle += sh[4 * i + 1];
+        t.match += sh[16 + i];
         lse_merge_r(t.lse_m, t.lse_s, (float)sh[4 * i + 2], sh[4 * i + 3], inv_t2);
     }
     return t;
@@ -125,6 +129,7 @@ __device__ __forceinline__ float4 loss_terms(const ReduceArgs& a, const WaveDesc
                                  : ((t.lse_s > 0.0) ? (float)((double)t.lse_m + (double)a.temp * log(t.lse_s)) : 0.f);
     double loss = (double)a.w_isl * isl + (a.w_psl != 0.f ? (double)a.w_psl * (double)psl : 0.0);
     if (a.w_spec != 0.f) loss += (double)a.w_spec * (double)a.vals[2 * wave + 1];
+    if (a.w_match != 0.f) loss += (double)a.w_match * t.match;
     return make_float4((float)loss, (float)isl, psl, E);
 }
 

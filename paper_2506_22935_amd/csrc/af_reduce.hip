@@ -5,7 +5,7 @@
 namespace graf {
 
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
-    __shared__ double sh[16];
+    __shared__ double sh[20];
     __shared__ float2 sh2[256];
     reduce_chunk<false>(a, (int)blockIdx.x, 0, sh, sh2);
 }
@@ -15,7 +15,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
 // every block bumps would serialise thousands of device-scope atomics and
 // cache write-backs on one address).
 __global__ __launch_bounds__(256) void reduce_adam_kernel(ReduceArgs a) {
-    __shared__ double sh[16];
+    __shared__ double sh[20];
     __shared__ float2 sh2[256];
     reduce_chunk<true>(a, (int)blockIdx.x, *a.step, sh, sh2);
 }

@@ -275,6 +275,12 @@ __device__ void stage_split_twiddles(const AfArgs& a, float2* hi, float2* lo, in
 // transform gives rows tau and N - tau of the [N][N] grid (tau = 0 and
 // tau = N/2 give one row each), and the lag product and its adjoint index
 // samples modulo N.
+// modes that take L_match and the hard PSL (forward, fused ISL)
+template <int MODE>
+constexpr bool HARD_MODE_MATCH() {
+    return MODE == MODE_FWD || MODE == MODE_FUSED_ISL;
+}
+
 template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, bool CIRC, typename Tw>
 __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, const Tw& twl,
                                                 const float2* s_lds, bool s_in_lds, double* scratch,
@@ -417,7 +423,13 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         for (int p = tid; p < N; p += WGS) slab2[p] = make_float2(0.f, 0.f);
     }
     float2* const mlb = reinterpret_cast<float2*>(scratch);
-    double isl = 0.0, ls = 0.0, dle = 0.0;
+    double isl = 0.0, ls = 0.0, dle = 0.0, mt = 0.0;
+    // L_match against a target power grid and the hard-PSL maximum (forward
+    // and fused ISL modes; the extended epilogue copy)
+    // (split variants only: the halves-in-turn variant keeps its registers)
+    const bool match = SPLIT && HARD_MODE_MATCH<MODE>() && a.match_t != nullptr;
+    const bool hard_rt = SPLIT && HARD_MODE_MATCH<MODE>() && a.psl_hard != 0;
+    const bool ext_rt = match || hard_rt;
     // hard PSL: this lane's largest sidelobe power and its cell (tau >= 0 row)
     constexpr bool HARD_MODE = MODE == MODE_FWD || MODE == MODE_FUSED_ISL;
     float hp = -1.f;
@@ -497,7 +509,10 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         const int64_t row_p = CIRC ? w.grid_off + (int64_t)tz * RL : w.grid_off + (int64_t)(T + tz) * M;
         const int64_t row_n = CIRC ? w.grid_off + (int64_t)(tz ? N - tz : 0) * RL : w.grid_off + (int64_t)(T - tz) * M;
         // rows tau and -tau of the halves-in-turn epilogue (empty when inactive)
-        const unsigned row_bytes = active ? (unsigned)M * 4u : 0u;
+        const unsigned row_bytes = active ? (unsigned)RL * 4u : 0u;
+        // target rows of L_match (the -tau row is read only with a distinct partner)
+        const Rsrc mt_p = make_rsrc(match ? a.match_t + row_p : nullptr, match ? row_bytes : 0u);
+        const Rsrc mt_n = make_rsrc(match ? a.match_t + row_n : nullptr, (match && two_rows) ? row_bytes : 0u);
         const Rsrc mag_p = make_rsrc(HAS_MAG_OUT && a.mag ? a.mag + row_p : nullptr, HAS_MAG_OUT && a.mag ? row_bytes : 0u);
         const Rsrc mag_n = make_rsrc(HAS_MAG_OUT && a.mag ? a.mag + row_n : nullptr, HAS_MAG_OUT && a.mag ? row_bytes : 0u);
         const Rsrc gm_p = make_rsrc(MODE == MODE_BWD_MAG ? a.grad_mag + row_p : nullptr, MODE == MODE_BWD_MAG ? row_bytes : 0u);
@@ -558,19 +573,22 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // weight are symmetric under (tau, k) -> (-tau, -k).  Sums over
             // the lane's bins run in float, then fold into float64.
             float isl_f = 0.f, dle_f = 0.f, mloc = -INFINITY, sl_f = 0.f;
+            float mt_f = 0.f, dlm_f = 0.f;  // L_match: both cells of the pair explicitly
             float avs[(MODE == MODE_FWD) ? P : 1];
             // One straight-line copy per loss configuration (shift rule,
             // banded weights, mainlobe complement, soft-PSL on/off): every
             // condition left inside is per lane and becomes a select.
             // MAIN: the lag may hold mainlobe cells (tau <= h_tau); without
             // them every mainlobe test is compiled out
-            auto epilogue = [&](auto fixed_c, auto banded_c, auto compl_c, auto psl_c, auto hard_c, auto main_c) {
+            // EXT: the rarely used extensions (hard-PSL maximum, L_match) in one
+            // copy, each behind a uniform runtime test
+            auto epilogue = [&](auto fixed_c, auto banded_c, auto compl_c, auto psl_c, auto main_c, auto ext_c) {
                 constexpr bool FIXED = decltype(fixed_c)::value;
                 constexpr bool BANDED = decltype(banded_c)::value;
                 constexpr bool COMPL = decltype(compl_c)::value;
                 constexpr bool PSL = decltype(psl_c)::value;
-                constexpr bool HARD = decltype(hard_c)::value;  // record the hard-PSL maximum
                 constexpr bool MAIN = decltype(main_c)::value;
+                constexpr bool EXT = decltype(ext_c)::value;
                 const float c_main = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
@@ -588,7 +606,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     const float av = NEED_IA ? xa * ia : __builtin_amdgcn_sqrtf(xa);
                     const bool main_cell = MAIN && active && main_tau && kc <= w.h_k;
                     const bool sd = active && !main_cell;
-                    if constexpr (HARD) {
+                    if (EXT && hard_rt) {
                         // largest power, then the smallest cell index
                         const int ci = tau * RL + k;
                         const bool better = sd && (pw > hp || (pw == hp && ci < hi));
@@ -623,6 +641,19 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         } else {
                             avs[q] = sd ? av : -INFINITY;
                             mloc = fmaxf(mloc, avs[q]);
+                        }
+                    }
+                    // L_match: (p - p_t)^2 for the cell (tau, k) and, with a
+                    // distinct partner, (-tau, -k); coefficient and energy
+                    // term per cell, not through the pair multiplier
+                    float cm = 0.f;
+                    if (EXT && match) {
+                        const float dp = active ? pw - buf_load1(mt_p, k * 4) : 0.f;
+                        const float dn = (active && two_rows) ? pw - buf_load1(mt_n, kn * 4) : 0.f;
+                        mt_f = fmaf(dp, dp, fmaf(dn, dn, mt_f));
+                        if constexpr (NEEDS_INV) {
+                            cm = 2.f * a.w_match * (dp + dn) * invE2;
+                            dlm_f = fmaf(-4.f * a.w_match * pw * invE, dp + dn, dlm_f);
                         }
                     }
                     if constexpr (NEEDS_INV) {
@@ -662,56 +693,61 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                             else
                                 c = sd ? mult * a.w_isl * wt * invE2 : 0.f;
                         }
-                        v[q] = cscale(v[q], c);
+                        v[q] = cscale(v[q], c + cm);
                     }
                 }
             };
             using T_ = std::integral_constant<bool, true>;
             using F_ = std::integral_constant<bool, false>;
-            auto dispatch = [&](auto main_c) {
-                auto by_loss = [&](auto fixed_c, auto psl_c, auto hard_c) {
-                    if (banded)
-                        epilogue(fixed_c, T_{}, F_{}, psl_c, hard_c, main_c);
-                    else if (compl_isl)
-                        epilogue(fixed_c, F_{}, T_{}, psl_c, hard_c, main_c);
-                    else
-                        epilogue(fixed_c, F_{}, F_{}, psl_c, hard_c, main_c);
-                };
-                if constexpr (MODE == MODE_FWD) {
-                    if (!want_lse && a.psl_hard)
-                        by_loss(T_{}, F_{}, T_{});
-                    else if (!want_lse)
-                        by_loss(T_{}, F_{}, F_{});
-                    else if (lse_fixed)
-                        by_loss(T_{}, T_{}, F_{});
-                    else
-                        by_loss(F_{}, T_{}, F_{});
-                } else if constexpr (MODE == MODE_BWD_LOSS) {
-                    if (a.w_psl != 0.f)
-                        by_loss(T_{}, T_{}, F_{});
-                    else
-                        by_loss(T_{}, F_{}, F_{});
-                } else if constexpr (MODE == MODE_BWD_MAG) {
-                    epilogue(T_{}, F_{}, F_{}, F_{}, F_{}, main_c);
-                } else if constexpr (MODE == MODE_LOSS) {
-                    if (compl_isl)
-                        epilogue(T_{}, F_{}, T_{}, T_{}, F_{}, main_c);
-                    else
-                        epilogue(T_{}, F_{}, F_{}, T_{}, F_{}, main_c);
-                } else if (a.psl_hard) {
-                    by_loss(T_{}, F_{}, T_{});
-                } else {
-                    by_loss(T_{}, F_{}, F_{});
-                }
+            auto by_loss = [&](auto fixed_c, auto psl_c, auto main_c, auto ext_c) {
+                if (banded)
+                    epilogue(fixed_c, T_{}, F_{}, psl_c, main_c, ext_c);
+                else if (compl_isl)
+                    epilogue(fixed_c, F_{}, T_{}, psl_c, main_c, ext_c);
+                else
+                    epilogue(fixed_c, F_{}, F_{}, psl_c, main_c, ext_c);
             };
-            // the mainlobe lags (tau <= h_tau) are a few of the N; BWD_MAG has
-            // no mainlobe logic
-            if (MODE != MODE_BWD_MAG && main_tau)
-                dispatch(T_{});
-            else
-                dispatch(F_{});
+            // the hot fused passes also get a copy without mainlobe logic for
+            // the lags beyond the mainlobe (tau > h_tau: all but a few)
+            // the extended copy exists in split variants only
+            auto ext_copy = [&]() {
+                if constexpr (SPLIT) by_loss(T_{}, F_{}, T_{}, T_{});
+            };
+            if constexpr (MODE == MODE_FWD) {
+                if (!want_lse && ext_rt)
+                    ext_copy();
+                else if (!want_lse)
+                    by_loss(T_{}, F_{}, T_{}, F_{});
+                else if (lse_fixed)
+                    by_loss(T_{}, T_{}, T_{}, F_{});
+                else
+                    by_loss(F_{}, T_{}, T_{}, F_{});
+            } else if constexpr (MODE == MODE_BWD_LOSS) {
+                if (a.w_psl != 0.f)
+                    by_loss(T_{}, T_{}, T_{}, F_{});
+                else
+                    by_loss(T_{}, F_{}, T_{}, F_{});
+            } else if constexpr (MODE == MODE_BWD_MAG) {
+                epilogue(T_{}, F_{}, F_{}, F_{}, F_{}, F_{});
+            } else if constexpr (MODE == MODE_LOSS) {
+                if (compl_isl && main_tau)
+                    epilogue(T_{}, F_{}, T_{}, T_{}, T_{}, F_{});
+                else if (compl_isl)
+                    epilogue(T_{}, F_{}, T_{}, T_{}, F_{}, F_{});
+                else if (main_tau)
+                    epilogue(T_{}, F_{}, F_{}, T_{}, T_{}, F_{});
+                else
+                    epilogue(T_{}, F_{}, F_{}, T_{}, F_{}, F_{});
+            } else if (ext_rt) {
+                ext_copy();
+            } else if (main_tau) {
+                by_loss(T_{}, F_{}, T_{}, F_{});
+            } else {
+                by_loss(T_{}, F_{}, F_{}, F_{});
+            }
             isl += (double)(mult * isl_f);
-            dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f);
+            dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f + dlm_f);
+            mt += (double)mt_f;
             if (FWD_SUMS && want_lse && (lse_fixed || MODE == MODE_LOSS)) {
                 ls += (double)(mult * sl_f);
             } else if (MODE == MODE_FWD && want_lse && mloc > -INFINITY) {
@@ -886,8 +922,9 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
     isl = (double)wave_sum((float)isl);
     if (MODE != MODE_FWD) dle = (double)wave_sum((float)dle);
+    if (match) mt = (double)wave_sum((float)mt);
     // hard PSL: the wavefront's largest power, then its smallest cell index
-    const bool hard = HARD_MODE && a.psl_hard;
+    const bool hard = SPLIT && HARD_MODE && a.psl_hard;
     if (hard) {
         const float wmx = wave_allmax(hp);
         hi = wave_allmin_int(hp == wmx ? hi : 0x7fffffff);
@@ -903,6 +940,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             scratch[64 + 2 * (tid >> 6)] = (double)hp;
             scratch[65 + 2 * (tid >> 6)] = (double)hi;
         }
+        scratch[96 + (tid >> 6)] = mt;
     }
     __syncthreads();
     if (tid == 0) {
@@ -911,6 +949,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         pr.lse_s = 0.0;
         pr.dle = 0.0;
         pr.lse_m = -INFINITY;
+        pr.match = 0.0;
         pr.psl_p = -1.f;
         pr.psl_i = 0;
         pr.pad = 0;
@@ -918,6 +957,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             pr.isl += scratch[4 * i + 0];
             if (FWD_SUMS) lse_merge(pr.lse_m, pr.lse_s, (float)scratch[4 * i + 1], scratch[4 * i + 2], inv_t2);
             pr.dle += scratch[4 * i + 3];
+            pr.match += scratch[96 + i];
             if (hard) {
                 // waves in order: larger power, then the smaller cell index
                 const float p = (float)scratch[64 + 2 * i];
@@ -984,8 +1024,9 @@ template <int MODE, typename V, int LG, bool CIRC = false>
 __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     static_assert(!CIRC || (V::SPLIT && V::S_LDS), "periodic AF: split variants with samples in LDS");
     extern __shared__ float2 dyn[];
-    // block reductions; [64, 96) holds the per-wave hard-PSL records
-    __shared__ double scratch[96];
+    // block reductions; [64, 96) holds the per-wave hard-PSL records,
+    // [96, 112) the per-wave L_match sums
+    __shared__ double scratch[112];
     constexpr int MH = 1 << LG;
     float2* lds = dyn;
     float2* s_lds = V::S_LDS ? dyn + V::fft_lds_bytes(LG) / 8 : nullptr;
