@@ -24,7 +24,8 @@ from . import _native
 __all__ = [
     "to_c64_exact", "energy", "chi", "chi_rows", "magnitude", "power",
     "centred_bins", "mainlobe_mask", "isl_weights", "LossParams", "loss_terms",
-    "loss_and_grad", "loss_grad_from_chi", "magnitude_backward", "grad_from_upstream", "phase_grad",
+    "loss_and_grad", "loss_grad_from_chi", "sigmoid", "soft_mainlobe_width", "modulus_variance",
+    "phase_smoothness", "spectral_projection", "magnitude_backward", "grad_from_upstream", "phase_grad",
     "adam_step", "bf16_round", "gelu", "gelu_grad", "mlp_forward",
     "mlp_backward", "psl_db", "chi_rows_fft", "magnitude_backward_fft",
     "chi_circular", "chi_circular_rows", "circular_lag_distance", "circular_mainlobe_mask", "circular_isl_weights",
@@ -117,19 +118,28 @@ def isl_weights(n, m, max_lag, h_tau, h_k, u=None, v=None):
 
 
 class LossParams:
-    """L = w_isl * ISL + w_psl * softPSL + w_match * Match over the grid.
+    """L = w_isl ISL + w_psl softPSL + w_match Match + w_width Width
+         + w_const Const + w_smooth Smooth.
 
     ISL = sum_{Omega_s} W p                         (Eq. 19, weighted)
     softPSL = T log sum_{Omega_s} exp(a / T)        (smooth stand-in for Eq. 18)
     Match = sum over every cell of (p - p_target)^2 (L_match of Sec. 5.2 with
             the AF in power, as the paper's chi, against a target surface
             p_target laid out like the grid)
+    Width = sum over the lag rows of |tau| sigma(gamma (p(tau, 0) - p(0, 0)/2))
+            (Eq. 21 on the power-normalised AF, whose half-power level is
+            the -3 dB level of Eq. 20; |tau|_c on the periodic AF)
+    Const = var(|s|)                                (L_const of Sec. 5.2)
+    Smooth = sum_n |s[n+1] - s[n]|^2 / E            (phase continuity, Sec. 6.2)
     """
 
     def __init__(self, w_isl=1.0, w_psl=0.0, temp=0.05, h_tau=1, h_k=1,
-                 u=None, v=None, eps=1e-12, match=None, w_match=0.0):
+                 u=None, v=None, eps=1e-12, match=None, w_match=0.0,
+                 w_width=0.0, gamma=10.0, w_const=0.0, w_smooth=0.0):
         self.match = None if match is None else np.asarray(match, dtype=np.float64)
         self.w_match = float(w_match)
+        self.w_width, self.gamma = float(w_width), float(gamma)
+        self.w_const, self.w_smooth = float(w_const), float(w_smooth)
         self.w_isl, self.w_psl, self.temp = float(w_isl), float(w_psl), float(temp)
         self.h_tau, self.h_k = int(h_tau), int(h_k)
         self.u = None if u is None else np.asarray(u, dtype=np.float64)
@@ -138,16 +148,30 @@ class LossParams:
 
 
 def loss_terms(c, E, n, params):
-    """Loss value and its pieces from a complex grid c (no gradient)."""
+    """Loss value and its pieces from a complex grid c (no gradient; the
+    waveform-only terms Const and Smooth are not grid terms and are left out)."""
     T = (c.shape[0] - 1) // 2
     m = c.shape[1]
     side = ~mainlobe_mask(m, T, params.h_tau, params.h_k)
     W = isl_weights(n, m, T, params.h_tau, params.h_k, params.u, params.v)
-    return _loss_terms_on(c, E, params, side, W)
+    return _loss_terms_on(c, E, params, side, W, np.abs(np.arange(-T, T + 1)).astype(np.float64))
 
 
-def _loss_terms_on(c, E, params, side, W):
-    """The loss pieces of a grid c with its sidelobe region and ISL weights."""
+def sigmoid(z):
+    return 0.5 * (1.0 + np.tanh(0.5 * np.asarray(z, dtype=np.float64)))
+
+
+def soft_mainlobe_width(p, lagd, gamma):
+    """Eq. 21 on a power grid p: sum over the rows of lagd * sigma(gamma
+    (p[row, 0] - p[origin, 0] / 2)), the origin being the row with lagd 0."""
+    r0 = int(np.argmin(lagd))
+    z = gamma * (p[:, 0] - 0.5 * p[r0, 0])
+    return float(np.sum(lagd * sigmoid(z)))
+
+
+def _loss_terms_on(c, E, params, side, W, lagd):
+    """The loss pieces of a grid c with its sidelobe region, ISL weights and
+    the lag distance |tau| of each row."""
     p = power(c, E)
     a = np.sqrt(p + params.eps)
     isl = float(np.sum(W * p))
@@ -156,9 +180,61 @@ def _loss_terms_on(c, E, params, side, W):
     S = float(np.sum(np.exp((av - mx) / params.temp)))
     soft = mx + params.temp * math.log(S)
     match = float(np.sum((p - params.match) ** 2)) if params.match is not None else 0.0
-    loss = params.w_isl * isl + params.w_psl * soft + params.w_match * match
-    return dict(loss=loss, isl=isl, softpsl=soft, match=match, psl_db=psl_db(p, side),
-                p=p, a=a, side=side, W=W, lse_max=mx, lse_sum=S)
+    width = soft_mainlobe_width(p, lagd, params.gamma)
+    loss = params.w_isl * isl + params.w_psl * soft + params.w_match * match + params.w_width * width
+    return dict(loss=loss, isl=isl, softpsl=soft, match=match, width=width, psl_db=psl_db(p, side),
+                p=p, a=a, side=side, W=W, lagd=lagd, lse_max=mx, lse_sum=S)
+
+
+def modulus_variance(s):
+    """L_const = var(|s|) (Sec. 5.2), the population variance, with its
+    gradient (|s[n]| - mean|s|) s[n] / (N |s[n]|) (0 where s[n] = 0)."""
+    s = np.asarray(s, dtype=np.complex128)
+    r = np.abs(s)
+    mu = float(r.mean())
+    v = float(np.mean((r - mu) ** 2))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        u = np.where(r > 0, s / np.where(r > 0, r, 1.0), 0.0)
+    return v, (r - mu) * u / len(s)
+
+
+def phase_smoothness(s):
+    """Smooth = sum_{n < N-1} |s[n+1] - s[n]|^2 / E with its gradient
+    (d[n-1] - d[n]) / E - Smooth s[n] / E, d[n] = s[n+1] - s[n] (zero outside
+    [0, N-1)).  For a unit-modulus code it is 2/N sum (1 - cos(phase step))."""
+    s = np.asarray(s, dtype=np.complex128)
+    E = energy(s)
+    d = s[1:] - s[:-1]
+    D = float(np.sum(np.abs(d) ** 2))
+    g = np.zeros_like(s)
+    g[1:] += d
+    g[:-1] -= d
+    return D / E, g / E - (D / (E * E)) * s
+
+
+def _add_waveform_terms(t, s, params):
+    """Const and Smooth, which depend on s alone, added to t's loss and g."""
+    vc, gc = modulus_variance(s)
+    vs, gs = phase_smoothness(s)
+    t["const"], t["smooth"] = vc, vs
+    t["loss"] += params.w_const * vc + params.w_smooth * vs
+    t["g"] = t["g"] + params.w_const * gc + params.w_smooth * gs
+    return t
+
+
+def spectral_projection(s, mask, unit=False):
+    """Bandwidth limit of Sec. 6.2's projected descent: the N-point DFT of s
+    times a real mask per bin, transformed back (inverse DFT with 1/N); with
+    unit, then s / |s| onto the unit circle (1 where the result is 0)."""
+    s = np.asarray(s, dtype=np.complex128)
+    n = s.shape[0]
+    k = np.arange(n)
+    F = np.exp(-2j * np.pi * np.outer(k, k) / n)
+    y = (np.conj(F).T @ (np.asarray(mask, dtype=np.float64) * (F @ s))) / n
+    if unit:
+        r = np.abs(y)
+        y = np.where(r > 0, y / np.where(r > 0, r, 1.0), 1.0 + 0j)
+    return y
 
 
 def loss_and_grad(s, m, max_lag, params):
@@ -184,7 +260,7 @@ def loss_grad_from_chi(s, m, T, c, params):
     G, dLdE = _cell_upstream(t, c, E, params)
     g = grad_from_upstream(s, m, T, G, dLdE)
     t.update(g=g, G=G, dLdE=dLdE, chi=c, E=E)
-    return t
+    return _add_waveform_terms(t, s, params)
 
 
 def _cell_upstream(t, c, E, params):
@@ -200,6 +276,17 @@ def _cell_upstream(t, c, E, params):
         d = p - params.match
         coef = coef + params.w_match * 2.0 * d / (E * E)
         dLdE += params.w_match * float(np.sum(2.0 * d * (-2.0 * p / E)))
+    if params.w_width != 0.0:
+        # Eq. 21: dWidth/dp(tau, 0) = |tau| gamma sigma'(z_tau); the origin
+        # cell also carries -gamma/2 sum |tau| sigma'(z_tau)
+        lagd = t["lagd"]
+        r0 = int(np.argmin(lagd))
+        sg = sigmoid(params.gamma * (p[:, 0] - 0.5 * p[r0, 0]))
+        u = lagd * params.gamma * sg * (1.0 - sg)  # zero on the origin row (lagd 0)
+        u[r0] = -0.5 * float(np.sum(u))
+        coef = np.array(coef, dtype=np.float64)
+        coef[:, 0] += params.w_width * u / (E * E)
+        dLdE += params.w_width * float(np.sum(u * (-2.0 * p[:, 0] / E)))
     G = coef * c
     return G, dLdE
 
@@ -297,11 +384,11 @@ def loss_and_grad_circular(s, params):
     c = chi_circular(s)
     side = ~circular_mainlobe_mask(n, params.h_tau, params.h_k)
     W = circular_isl_weights(n, params.h_tau, params.h_k, params.u, params.v)
-    t = _loss_terms_on(c, E, params, side, W)
+    t = _loss_terms_on(c, E, params, side, W, circular_lag_distance(n).astype(np.float64))
     G, dLdE = _cell_upstream(t, c, E, params)
     g = _native.adjoint_circ(s, G) + dLdE * s
     t.update(g=g, G=G, dLdE=dLdE, chi=c, E=E)
-    return t
+    return _add_waveform_terms(t, s, params)
 
 
 def magnitude_backward_circular(s, grad_mag, eps):

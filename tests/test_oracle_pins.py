@@ -645,3 +645,100 @@ def test_match_loss_is_zero_at_its_own_surface():
     assert r["match"] <= 1e-28 and np.max(np.abs(r["g"])) <= 1e-12
     r2 = O.loss_and_grad(2.5j * s, m, n - 1, params)
     assert r2["match"] <= 1e-26
+
+
+# ---- remaining composite terms: soft mainlobe width (Eq. 21), var(|s|),
+# phase smoothness, and the spectral-mask projection (Sec. 6.2)
+
+def test_soft_width_sharp_limit_rectangular_pulse():
+    # s = 1: p(tau, 0) = ((N - |tau|) / N)^2, above one half for tau <= 18 at
+    # N = 64 (p(18) = 0.517, p(19) = 0.494): with a sharp sigmoid Eq. 21 counts
+    # |tau| over those lags, 2 (1 + ... + 18) = 342
+    n = 64
+    s = np.ones(n, dtype=np.complex128)
+    t = O.loss_and_grad(s, 128, n - 1, O.LossParams(w_isl=0.0, w_width=1.0, gamma=1e4))
+    assert abs(t["width"] - 342.0) < 1e-9
+    assert abs(t["loss"] - 342.0) < 1e-9
+    # at gamma = 0 every row weighs one half: sum |tau| / 2 = N (N - 1) / 2
+    t0 = O.loss_and_grad(s, 128, n - 1, O.LossParams(w_isl=0.0, w_width=1.0, gamma=0.0))
+    assert abs(t0["width"] - n * (n - 1) / 2.0) < 1e-9
+
+
+def test_soft_width_periodic_constant_code():
+    # the periodic autocorrelation of a constant is N at every lag: p(tau, 0) = 1
+    # and every row sits at sigma(gamma / 2); sum_tau |tau|_c = N^2 / 4
+    n = 64
+    s = np.full(n, 0.5 - 0.25j)
+    for gamma in (0.5, 3.0):
+        t = O.loss_and_grad_circular(s, O.LossParams(w_isl=0.0, w_width=1.0, gamma=gamma))
+        assert abs(t["width"] - n * n / 4.0 / (1.0 + math.exp(-gamma / 2.0))) < 1e-9
+
+
+def test_modulus_variance_and_smoothness_closed_forms():
+    n = 40
+    phi = np.random.default_rng(3).uniform(-np.pi, np.pi, n)
+    s = np.exp(1j * phi)
+    v, g = O.modulus_variance(s)
+    assert v < 1e-28 and np.max(np.abs(g)) < 1e-15
+    # two amplitude levels a, b in equal numbers: var = ((a - b) / 2)^2
+    r = np.where(np.arange(n) % 2 == 0, 1.5, 0.25)
+    v, _ = O.modulus_variance(r * s)
+    assert abs(v - (1.25 / 2) ** 2) < 1e-14
+    # linear phase step theta: (N - 1) |e^{j theta} - 1|^2 / N = (N - 1)(2 - 2 cos theta) / N
+    theta = 0.3
+    sm, _ = O.phase_smoothness(np.exp(1j * theta * np.arange(n)))
+    assert abs(sm - (n - 1) * (2 - 2 * math.cos(theta)) / n) < 1e-14
+    sm, g = O.phase_smoothness(np.full(n, 2.0 - 1.0j))
+    assert sm == 0.0 and np.max(np.abs(g)) < 1e-15
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_width_const_smooth_finite_differences(periodic):
+    n = 32
+    s = rand_complex(n, 44) * (1.0 + 0.3 * np.cos(np.arange(n)))
+    params = O.LossParams(w_isl=0.3, w_width=0.7, gamma=6.0, w_const=1.3, w_smooth=0.9)
+    if periodic:
+        f = lambda x: O.loss_and_grad_circular(x, params)["loss"]
+        t = O.loss_and_grad_circular(s, params)
+    else:
+        f = lambda x: O.loss_and_grad(x, 64, n - 1, params)["loss"]
+        t = O.loss_and_grad(s, 64, n - 1, params)
+    g = _fd_grad(f, s)
+    assert np.max(np.abs(t["g"] - g)) < 1e-6 * np.max(np.abs(g))
+    # the pieces add up with their weights
+    base = O.LossParams(w_isl=0.3)
+    b = O.loss_and_grad_circular(s, base) if periodic else O.loss_and_grad(s, 64, n - 1, base)
+    assert abs(t["loss"] - (b["loss"] + 0.7 * t["width"] + 1.3 * t["const"] + 0.9 * t["smooth"])) < 1e-9
+
+
+def test_width_gradient_isolated_finite_differences():
+    # the width term alone, including the origin-cell term, on a lag window
+    n, m, T = 24, 64, 9
+    s = rand_complex(n, 45)
+    params = O.LossParams(w_isl=0.0, w_width=1.0, gamma=4.0)
+    t = O.loss_and_grad(s, m, T, params)
+    g = _fd_grad(lambda x: O.loss_and_grad(x, m, T, params)["loss"], s)
+    assert np.max(np.abs(t["g"] - g)) < 1e-6 * np.max(np.abs(g))
+
+
+def test_spectral_projection_two_tones():
+    n = 48
+    k = np.arange(n)
+    a, b = 0.8 - 0.3j, -0.2 + 1.1j
+    s = a * np.exp(2j * np.pi * 5 * k / n) + b * np.exp(2j * np.pi * 31 * k / n)
+    mask = np.zeros(n)
+    mask[5] = 1.0
+    y = O.spectral_projection(s, mask)
+    assert np.max(np.abs(y - a * np.exp(2j * np.pi * 5 * k / n))) < 1e-13
+    # all-pass mask: identity; a 0/1 mask: idempotent; unit: on the circle
+    assert np.max(np.abs(O.spectral_projection(s, np.ones(n)) - s)) < 1e-13
+    s2 = rand_complex(n, 46)
+    band = (np.abs(np.where(k < n // 2, k, k - n)) <= 10).astype(np.float64)
+    y1 = O.spectral_projection(s2, band)
+    assert np.max(np.abs(O.spectral_projection(y1, band) - y1)) < 1e-13
+    yu = O.spectral_projection(s2, band, unit=True)
+    assert np.max(np.abs(np.abs(yu) - 1.0)) < 1e-14
+    assert np.max(np.abs(np.angle(yu * np.conj(y1)))) < 1e-12
+    # a half-weight mask scales a tone by one half
+    mask[5] = 0.5
+    assert np.max(np.abs(O.spectral_projection(s, mask) - 0.5 * a * np.exp(2j * np.pi * 5 * k / n))) < 1e-13
