@@ -111,10 +111,20 @@ typedef struct af_plan af_plan;
  * (Sec. 5.2), the squared Frobenius distance between the AF in power,
  * p = |chi|^2 / E^2, and match_target over every cell of the grid; it
  * combines with ISL and the hard PSL, not with the soft PSL
- * (AF_ERR_UNSUPPORTED).  The hard PSL and L_match need plans whose size
+ * (AF_ERR_UNSUPPORTED).  w_width weights the soft mainlobe width of
+ * Eq. 21 on the AF in power, sum over the lag rows of |tau| sigma(gamma
+ * (p(tau, 0) - 1/2)) (p(0, 0) = 1 for every waveform, so half of it is the
+ * -3 dB level of Eq. 20; |tau| is min(tau, N - tau) on the periodic AF);
+ * gamma >= 0 sets the sharpness; like L_match it does not combine with the
+ * soft PSL.  The hard PSL, L_match and the width need plans whose size
  * classes run split variants (M <= 8192, or a periodic N <= 4096);
- * AF_ERR_UNSUPPORTED otherwise.  Zero-initialise the struct: psl_hard = 0, w_spec = 0
- * and w_match = 0 give the soft-PSL losses above. */
+ * AF_ERR_UNSUPPORTED otherwise.  w_const weights var(|s|) (L_const of
+ * Sec. 5.2, population variance; its gradient is taken as 0 at s[n] = 0),
+ * w_smooth a phase-continuity term (Sec. 6.2), sum_{n < N-1} |s[n+1] -
+ * s[n]|^2 / E, which for a unit-modulus code is (2/N) sum (1 - cos of the
+ * phase steps); both combine with every other term.  Zero-initialise the
+ * struct: psl_hard = 0 and zero weights for the terms after it give the
+ * soft-PSL losses above. */
 typedef struct {
     float w_isl;
     float w_psl;
@@ -124,6 +134,10 @@ typedef struct {
     float w_spec;
     const float* match_target; /* device float grid of target powers p_t, laid out like the a grid */
     float w_match;             /* weight of L_match = sum over every cell of (p - p_t)^2 */
+    float w_width;             /* weight of the soft mainlobe width (Eq. 21) */
+    float gamma;               /* its sharpness, >= 0 */
+    float w_const;             /* weight of var(|s|) */
+    float w_smooth;            /* weight of sum |s[n+1] - s[n]|^2 / E */
 } af_loss_params;
 
 /* Adam settings for af_optim_step (Kingma & Ba; eps outside the square root). */
@@ -200,6 +214,15 @@ af_status af_loss_stage(const af_plan* plan, int32_t stage, const void* s, const
  * s (overwritten).  Every waveform must have N <= 4096 (AF_ERR_UNSUPPORTED). */
 af_status af_spectral_variance(const af_plan* plan, const void* s, float* value, void* grad_s, void* ws,
                                size_t ws_bytes, void* stream);
+
+/* Projection step of projected descent (Sec. 6.2), per waveform of the plan:
+ * with mask (device float, one real weight per bin of the N-point DFT, packed
+ * like s) out = IDFT_N(mask * DFT_N(s)) (inverse with 1/N), which needs
+ * N <= 4096 (AF_ERR_UNSUPPORTED otherwise); then, with unit = 1, out /= |out|
+ * onto the unit circle (1 where out is 0).  mask NULL: only the unit-circle
+ * projection (any N).  s, out: device complex64 packed like the plan's input;
+ * out may equal s (in place).  unit must be 0 or 1; mask NULL with unit 0 copies. */
+af_status af_project(const af_plan* plan, const void* s, const float* mask, int32_t unit, void* out, void* stream);
 
 /* s[i] = exp(j phi[i]) for i < count (device arrays). */
 af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream);

@@ -159,7 +159,7 @@ class Plan:
 
     @staticmethod
     def loss_params(w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, psl_hard=False, w_spec=0.0, match=None,
-                    w_match=0.0):
+                    w_match=0.0, w_width=0.0, gamma=10.0, w_const=0.0, w_smooth=0.0):
         if band_w is not None:
             _need(band_w, torch.float32, "band_w")
         if match is not None:
@@ -167,21 +167,25 @@ class Plan:
         p = L.AfLossParams(w_isl=float(w_isl), w_psl=float(w_psl), psl_temp=float(temp),
                            band_w=None if band_w is None else band_w.data_ptr(), psl_hard=1 if psl_hard else 0,
                            w_spec=float(w_spec), match_target=None if match is None else match.data_ptr(),
-                           w_match=float(w_match))
+                           w_match=float(w_match), w_width=float(w_width), gamma=float(gamma),
+                           w_const=float(w_const), w_smooth=float(w_smooth))
         p._keep = (band_w, match)  # keep the tensors alive while the struct is in use
         return p
 
     def loss(self, s, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, grad=True, mag=False, ws=None,
-             out_terms=None, out_grad=None, psl_hard=False, w_spec=0.0, match=None, w_match=0.0):
+             out_terms=None, out_grad=None, psl_hard=False, w_spec=0.0, match=None, w_match=0.0, w_width=0.0,
+             gamma=10.0, w_const=0.0, w_smooth=0.0):
         """Built-in loss.  Returns (terms float32[B,4] = (L, ISL, PSL term, E),
         dL/d conj(s) or None, a grids or None).  psl_hard: the hard PSL
         (power ratio) instead of the soft one; w_spec: weight of the spectral
         variance (the experiment loss: w_psl=1, psl_hard=True,
         w_spec=lambda*alpha); match, w_match: L_match against a target power
-        grid laid out like the a grid."""
+        grid laid out like the a grid; w_width, gamma: the soft mainlobe
+        width; w_const: var(|s|); w_smooth: the phase-smoothness term."""
         _need(s, torch.complex64, "s")
         ws = self.workspace if ws is None else ws
-        lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match)
+        lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match, w_width, gamma,
+                              w_const, w_smooth)
         t = out_terms if out_terms is not None else torch.empty(self.batch, 4, dtype=torch.float32, device=_DEV)
         g = None
         if grad:
@@ -193,19 +197,23 @@ class Plan:
         return t, g, m
 
     def loss_stage(self, stage, s, terms, grad, mag, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, ws=None,
-                   psl_hard=False, w_spec=0.0, match=None, w_match=0.0):
+                   psl_hard=False, w_spec=0.0, match=None, w_match=0.0, w_width=0.0, gamma=10.0, w_const=0.0,
+                   w_smooth=0.0):
         """Run one stage (0 forward, 1 backward and the per-waveform terms, 2
         reduce) of loss(); for timing."""
         ws = self.workspace if ws is None else ws
-        lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match)
+        lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match, w_width, gamma,
+                              w_const, w_smooth)
         L.check("af_loss_stage", L.lib().af_loss_stage(self._h, int(stage), _ptr(s), ctypes.byref(lp), _ptr(terms),
                                                        _ptr(mag), _ptr(grad), _ptr(ws), ws.numel(), _stream()))
 
     def optim_step(self, state, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, lr=0.01, betas=(0.9, 0.999),
-                   eps=1e-8, ws=None, terms=None, psl_hard=False, w_spec=0.0, match=None, w_match=0.0):
+                   eps=1e-8, ws=None, terms=None, psl_hard=False, w_spec=0.0, match=None, w_match=0.0,
+                   w_width=0.0, gamma=10.0, w_const=0.0, w_smooth=0.0):
         """One Adam step on the phases held in `state` (see PhaseState)."""
         ws = self.workspace if ws is None else ws
-        lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match)
+        lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match, w_width, gamma,
+                              w_const, w_smooth)
         ad = L.AfAdamParams(lr=float(lr), beta1=float(betas[0]), beta2=float(betas[1]), eps=float(eps))
         L.check("af_optim_step", L.lib().af_optim_step(
             self._h, _ptr(state.phi), _ptr(state.m), _ptr(state.v), _ptr(state.s), _ptr(state.step),
@@ -222,6 +230,19 @@ class Plan:
         L.check("af_spectral_variance", L.lib().af_spectral_variance(self._h, _ptr(s), _ptr(v), _ptr(g), _ptr(ws),
                                                                      ws.numel(), _stream()))
         return v, g
+
+    def project(self, s, mask=None, unit=False, out=None):
+        """Projection step of projected descent (Sec. 6.2): with mask (float32,
+        one weight per bin of each waveform's N-point DFT, packed like s) the
+        masked spectrum transformed back; with unit, then onto the unit
+        circle.  out may be s (in place).  Returns out."""
+        _need(s, torch.complex64, "s")
+        if mask is not None:
+            _need(mask, torch.float32, "mask")
+        out = torch.empty_like(s) if out is None else out
+        L.check("af_project", L.lib().af_project(self._h, _ptr(s), _ptr(mask), 1 if unit else 0, _ptr(out),
+                                                 _stream()))
+        return out
 
 
 class PhaseState:

@@ -166,6 +166,10 @@ af_status build_schedule(af_plan* p) {
         k.dyn_lds = vi.fft_lds + (vi.s_lds ? 8 * (2 << k.lg) : 0);  // samples zero-padded to M
         for (int mode = 0; mode < graf::kNumModes; ++mode) {
             const int r = graf::variant_max_resident(mode, v, k.lg, k.circ, k.dyn_lds);
+            if (r <= 0 && mode == graf::MODE_FUSED_EXT && !vi.split) {
+                k.grid[mode] = 0;  // no extended instance: those terms are refused
+                continue;
+            }
             if (r <= 0) return AF_ERR_UNSUPPORTED;
             k.grid[mode] = r * p->cus;  // capped by the segment count below
         }
@@ -274,7 +278,7 @@ af_status build_schedule(af_plan* p) {
     int64_t s_extent = 0;
     for (const af_wave& w : p->waves) s_extent = std::max<int64_t>(s_extent, w.s_off + w.n);
     const size_t extra_b = align256((size_t)s_extent * sizeof(float2));
-    const size_t vals_b = align256((size_t)B * 2 * sizeof(float));
+    const size_t vals_b = align256((size_t)B * 4 * sizeof(float));
     const size_t base = parts_b + energy_b + slabs_b + slabs2_b + extra_b + vals_b;
     bool stores;
     if (p->store_mode == 1)
@@ -451,8 +455,10 @@ af_status check_common(const af_plan* p, const void* s, void* ws, size_t ws_byte
     return AF_OK;
 }
 
-bool hard_psl_or_match(const af_loss_params* lp) {
-    return (lp->psl_hard != 0 && lp->w_psl != 0.f) || lp->w_match != 0.f;
+// terms of the extended epilogue copy (split variants, forward and fused
+// ISL passes): the hard PSL, L_match, the soft mainlobe width
+bool extended_terms(const af_loss_params* lp) {
+    return (lp->psl_hard != 0 && lp->w_psl != 0.f) || lp->w_match != 0.f || lp->w_width != 0.f;
 }
 
 af_status check_loss(const af_plan* p, const af_loss_params* lp) {
@@ -461,20 +467,25 @@ af_status check_loss(const af_plan* p, const af_loss_params* lp) {
         return AF_ERR_INVALID_ARG;
     if (lp->psl_hard != 0 && lp->psl_hard != 1) return AF_ERR_INVALID_ARG;
     if (!std::isfinite(lp->w_match) || (lp->w_match != 0.f && !lp->match_target)) return AF_ERR_INVALID_ARG;
-    // L_match runs in the forward and fused ISL passes: not with the soft PSL
-    if (lp->w_match != 0.f && lp->w_psl != 0.f && !lp->psl_hard) return AF_ERR_UNSUPPORTED;
-    // the hard PSL and L_match run in the split variants (M <= 8192)
-    if (hard_psl_or_match(lp))
+    if (!std::isfinite(lp->w_width) || !std::isfinite(lp->gamma) || !(lp->gamma >= 0.f) ||
+        !std::isfinite(lp->w_const) || !std::isfinite(lp->w_smooth))
+        return AF_ERR_INVALID_ARG;
+    // L_match and the width run in the forward and fused ISL passes: not with the soft PSL
+    if ((lp->w_match != 0.f || lp->w_width != 0.f) && lp->w_psl != 0.f && !lp->psl_hard) return AF_ERR_UNSUPPORTED;
+    // the hard PSL, L_match and the width run in the split variants (M <= 8192)
+    if (extended_terms(lp))
         for (const af_plan::Class& k : p->classes)
             if (!graf::variant_info(k.variant, k.lg).split) return AF_ERR_UNSUPPORTED;
     if (lp->w_spec != 0.f && p->max_n > kMaxSpecN) return AF_ERR_UNSUPPORTED;
     return AF_OK;
 }
 
-// Does the loss take the hard PSL or the spectral variance (the experiment
-// loss's per-waveform kernel)?
+// Does the loss take a per-waveform term (the hard PSL, the spectral
+// variance, var(|s|), the smoothness term: the per-waveform kernel)?
 bool hard_psl(const af_loss_params* lp) { return lp->psl_hard != 0 && lp->w_psl != 0.f; }
-bool needs_extra(const af_loss_params* lp) { return hard_psl(lp) || lp->w_spec != 0.f; }
+bool needs_extra(const af_loss_params* lp) {
+    return hard_psl(lp) || lp->w_spec != 0.f || lp->w_const != 0.f || lp->w_smooth != 0.f;
+}
 
 // loss forward/backward into slabs and parts (no reduce)
 // Can ISL + soft-PSL forward and backward run as one pass (MODE_LOSS)?  The
@@ -483,7 +494,8 @@ bool needs_extra(const af_loss_params* lp) { return hard_psl(lp) || lp->w_spec !
 // uniform ISL weights with full lag windows (the ISL gradient then lives on
 // the mainlobe cells) and variants that split the two half transforms.
 bool fused_loss_ok(const af_plan* p, const af_loss_params* lp) {
-    if (p->loss_passes_opt == 1 || lp->w_psl == 0.f || lp->psl_hard || lp->band_w != nullptr || lp->w_match != 0.f)
+    if (p->loss_passes_opt == 1 || lp->w_psl == 0.f || lp->psl_hard || lp->band_w != nullptr || lp->w_match != 0.f ||
+        lp->w_width != 0.f)
         return false;
     const float inv_t2 = 1.4426950408889634f / lp->psl_temp;
     if (!(std::sqrt(1.f + p->eps) * inv_t2 < 100.f)) return false;
@@ -509,22 +521,21 @@ AfArgs loss_args(const af_plan* p, const void* s, const af_loss_params* lp, floa
         a.match_t = lp->match_target;
         a.w_match = lp->w_match;
     }
+    a.w_width = lp->w_width;
+    a.gamma = lp->gamma;
     return a;
 }
 
-// Do the passes of this loss leave gradient slabs (else the reduction reads
-// none)?  The hard PSL without ISL needs only the forward pass.
-bool loss_writes_slabs(const af_loss_params* lp, bool want_grad) {
-    if (!want_grad) return false;
-    if (lp->psl_hard) return lp->w_isl != 0.f || lp->w_match != 0.f;
-    return true;
+// Does a term take a gradient over the cells of the grid?  Else the forward
+// pass alone serves: the hard PSL's gradient lives on one cell, and the
+// waveform-only terms take none through the AF.
+bool grid_gradient(const af_loss_params* lp) {
+    return lp->w_isl != 0.f || (lp->w_psl != 0.f && !lp->psl_hard) || lp->w_match != 0.f || lp->w_width != 0.f;
 }
-
-// Is the forward pass alone enough for this loss (no per-cell gradient:
-// only the hard PSL, whose gradient is one cell's)?
-bool forward_only(const af_loss_params* lp, bool want_grad) {
-    return !want_grad || (lp->psl_hard && lp->w_isl == 0.f && lp->w_match == 0.f);
-}
+// Do the passes of this loss leave gradient slabs (else the reduction reads none)?
+bool loss_writes_slabs(const af_loss_params* lp, bool want_grad) { return want_grad && grid_gradient(lp); }
+// Is the forward pass alone enough for this loss?
+bool forward_only(const af_loss_params* lp, bool want_grad) { return !want_grad || !grid_gradient(lp); }
 
 // The experiment loss's per-waveform kernel (after the AF pass: it reads the
 // segment records and E)
@@ -543,6 +554,9 @@ af_status launch_extra(const af_plan* p, const void* s, const af_loss_params* lp
     e.w_psl = lp->w_psl;
     e.spec = lp->w_spec != 0.f ? 1 : 0;
     e.w_spec = lp->w_spec;
+    e.wterms = (lp->w_const != 0.f || lp->w_smooth != 0.f) ? 1 : 0;
+    e.w_const = lp->w_const;
+    e.w_smooth = lp->w_smooth;
     e.g_extra = want_grad ? v.extra : nullptr;
     e.vals = v.vals;
     return graf::launch_extra(e, p->batch, p->max_n, st) == hipSuccess ? AF_OK : AF_ERR_HIP;
@@ -555,7 +569,7 @@ af_status loss_passes(const af_plan* p, const void* s, const af_loss_params* lp,
     if (forward_only(lp, want_grad)) {
         rc = launch(p, graf::MODE_FWD, a, st, only_class);
     } else if (a.w_psl == 0.f) {
-        rc = launch(p, graf::MODE_FUSED_ISL, a, st, only_class);
+        rc = launch(p, extended_terms(lp) ? graf::MODE_FUSED_EXT : graf::MODE_FUSED_ISL, a, st, only_class);
     } else if (fused_loss_ok(p, lp)) {
         rc = launch(p, graf::MODE_LOSS, a, st, only_class);
     } else {
@@ -582,7 +596,9 @@ ReduceArgs loss_reduce_args(const af_plan* p, const void* s, const af_loss_param
     r.psl_scaled = want_grad && fused_loss_ok(p, lp);
     r.psl_hard = hard_psl(lp) ? 1 : 0;
     r.w_spec = lp->w_spec;
-    r.w_match = lp->match_target ? lp->w_match : 0.f;
+    r.w_const = lp->w_const;
+    r.w_smooth = lp->w_smooth;
+    r.ext_cells = ((lp->match_target && lp->w_match != 0.f) || lp->w_width != 0.f) ? 1 : 0;
     r.vals = v.vals;
     r.g_extra = (want_grad && needs_extra(lp)) ? v.extra : nullptr;
     return r;
@@ -753,7 +769,7 @@ af_status af_loss_stage(const af_plan* p, int32_t stage, const void* s, const af
     const bool fused_loss = !fwd_only && !fused && fused_loss_ok(p, lp);
     switch (stage) {
         case 0:
-            if (fused) return launch(p, graf::MODE_FUSED_ISL, a, st);
+            if (fused) return launch(p, extended_terms(lp) ? graf::MODE_FUSED_EXT : graf::MODE_FUSED_ISL, a, st);
             if (fused_loss) return launch(p, graf::MODE_LOSS, a, st);
             a.ystore = fwd_only ? nullptr : v.store;
             return launch(p, graf::MODE_FWD, a, st);
@@ -796,6 +812,19 @@ af_status af_spectral_variance(const af_plan* p, const void* s, float* value, vo
     e.vals = v.vals;
     e.spec_out = value;
     return graf::launch_extra(e, p->batch, p->max_n, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
+}
+
+af_status af_project(const af_plan* p, const void* s, const float* mask, int32_t unit, void* out, void* stream) {
+    if (!p || !s || !out || (unit != 0 && unit != 1)) return AF_ERR_INVALID_ARG;
+    if (!aligned(s, 8) || !aligned(out, 8) || !aligned(mask, 4)) return AF_ERR_INVALID_ARG;
+    if (mask && p->max_n > kMaxSpecN) return AF_ERR_UNSUPPORTED;
+    graf::ProjectArgs a;
+    a.s = (const float2*)s;
+    a.waves = p->d_waves;
+    a.mask = mask;
+    a.unit = unit;
+    a.out = (float2*)out;
+    return graf::launch_project(a, p->batch, p->max_n, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
 }
 
 af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream) {

@@ -42,7 +42,8 @@ struct Part {
     double isl;
     double lse_s;
     double dle;
-    double match;  // sum of (p - p_target)^2 over the segment's cells
+    double ext;    // weighted cell-wise extension terms over the segment's cells:
+                   // w_match (p - p_target)^2 + w_width |tau| sigma(gamma (p(tau, 0) - 1/2))
     float lse_m;
     float psl_p;
     int psl_i;
@@ -54,11 +55,15 @@ enum Mode : int {
     MODE_BWD_MAG = 1,   // upstream dL/da grid -> gradient slabs
     MODE_BWD_LOSS = 2,  // ISL + soft-PSL loss -> gradient slabs (needs MODE_FWD parts)
     MODE_FUSED_ISL = 3, // ISL loss forward and backward in one pass
-    MODE_LOSS = 4       // ISL (mainlobe complement) + soft-PSL (fixed shift) loss,
+    MODE_LOSS = 4,      // ISL (mainlobe complement) + soft-PSL (fixed shift) loss,
                         // forward and backward in one pass; the soft-PSL
                         // gradient is left unnormalised for the reduction
+    MODE_FUSED_EXT = 5  // launch id only: the MODE_FUSED_ISL pass in its own
+                        // instance with the extended epilogue terms (hard-PSL
+                        // maximum, L_match, mainlobe width; split variants), so
+                        // that the plain fused pass keeps its registers
 };
-constexpr int kNumModes = 5;
+constexpr int kNumModes = 6;
 
 struct AfArgs {
     WaveDesc w0;          // the waveform of a one-waveform class (single != 0)
@@ -82,9 +87,10 @@ struct AfArgs {
     float2* slabs;        // [sum segs*N]
     float2* slabs2;       // [sum isl_segs*N] ISL part of MODE_LOSS
     float* energy;        // [B], written by the segment holding lag 0
-    int psl_hard;         // MODE_FWD / MODE_FUSED_ISL: record the hard-PSL maximum
-    const float* match_t; // target power grid of L_match (MODE_FWD / MODE_FUSED_ISL), nullable
+    int psl_hard;         // MODE_FWD / MODE_FUSED_EXT: record the hard-PSL maximum
+    const float* match_t; // target power grid of L_match (MODE_FWD / MODE_FUSED_EXT), nullable
     float w_match;
+    float w_width, gamma; // soft mainlobe width on the k = 0 column (MODE_FWD / MODE_FUSED_EXT)
 };
 
 // The slab reduction runs 256-thread blocks over (256 >> sg_log) samples of
@@ -125,18 +131,21 @@ struct ReduceArgs {
     float2* s_next;       // exp(j phi_new)
     int* step;            // device step counter (1-based after increment)
     float lr, beta1, beta2, adam_eps;
-    // the experiment loss: hard PSL and spectral variance, from extra_kernel
-    float w_match;        // weight of L_match (sum of the segment records' match)
-    int psl_hard;         // the PSL term is the hard maximum (vals[2b])
-    float w_spec;         // weight of the spectral variance (vals[2b + 1])
+    // per-waveform terms from extra_kernel and the cell-wise extension terms
+    int ext_cells;        // add the segment records' ext (already weighted)
+    int psl_hard;         // the PSL term is the hard maximum (vals[4b])
+    float w_spec;         // weight of the spectral variance (vals[4b + 1])
+    float w_const;        // weight of var(|s|) (vals[4b + 2])
+    float w_smooth;       // weight of the phase-smoothness term (vals[4b + 3])
     const float2* g_extra;  // their gradient, packed like s; nullable
-    const float* vals;    // [B][2] = hard PSL, spectral variance
+    const float* vals;    // [B][4] = hard PSL, spectral variance, var(|s|), smoothness
 };
 
-// Per-waveform terms of the experiment loss (Sec. 7.1.1): the hard-PSL
-// maximum from the segment records, chi at that cell and its single-cell
-// adjoint, and the spectral variance of the N-point spectrum with its
-// gradient; one 256-thread block per waveform.
+// Per-waveform terms: the hard-PSL maximum of the experiment loss
+// (Sec. 7.1.1) from the segment records, chi at that cell and its
+// single-cell adjoint; the spectral variance of the N-point spectrum with
+// its gradient; var(|s|) and the phase-smoothness term of the composite loss
+// (Sec. 5.2); one 256-thread block per waveform.
 struct ExtraArgs {
     const float2* s;
     const WaveDesc* waves;
@@ -148,11 +157,24 @@ struct ExtraArgs {
     float w_psl;
     int spec;             // compute the spectral part
     float w_spec;
-    float2* g_extra;      // gradient out (w_psl * psl part + w_spec * spectral part); nullable
-    float* vals;          // [B][2] out
+    int wterms;           // compute var(|s|) and the smoothness term
+    float w_const, w_smooth;
+    float2* g_extra;      // gradient out (the weighted sum of the parts); nullable
+    float* vals;          // [B][4] out
     float* spec_out;      // [B] spectral variance out (nullable)
 };
 hipError_t launch_extra(const ExtraArgs& a, int batch, int max_n, hipStream_t st);
+// Spectral-mask projection (Sec. 6.2): out = IDFT_N(mask . DFT_N(s)), then,
+// with unit, out / |out|; mask null: only the unit-circle projection.  One
+// 256-thread block per waveform; out may alias s.
+struct ProjectArgs {
+    const float2* s;
+    const WaveDesc* waves;
+    const float* mask;    // packed like s, nullable
+    int unit;
+    float2* out;
+};
+hipError_t launch_project(const ProjectArgs& a, int batch, int max_n, hipStream_t st);
 
 // launchers (af_reduce.hip)
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);

@@ -28,7 +28,7 @@ __device__ __forceinline__ double wave_sum_d(double v) { return wave_allsum(v); 
 __device__ __forceinline__ void wave_lse_r(float& m, double& s, float inv_t2) { wave_lse_pair(m, s, inv_t2); }
 
 struct WaveTotals {
-    double isl_raw, lse_s, dle, match;
+    double isl_raw, lse_s, dle, ext;
     float lse_m;
 };
 
@@ -42,12 +42,12 @@ __device__ WaveTotals wave_totals(const ReduceArgs& a, const WaveDesc& w, double
         const Part pr = a.parts[w.seg_begin + j];
         isl += pr.isl;
         dle += pr.dle;
-        mt += pr.match;
+        mt += pr.ext;
         lse_merge_r(m, s, pr.lse_m, pr.lse_s, inv_t2);
     }
     isl = wave_sum_d(isl);
     dle = wave_sum_d(dle);
-    if (a.w_match != 0.f) mt = wave_sum_d(mt);
+    if (a.ext_cells) mt = wave_sum_d(mt);
     wave_lse_r(m, s, inv_t2);
     const int wv = threadIdx.x >> 6;
     __syncthreads();
@@ -63,7 +63,7 @@ __device__ WaveTotals wave_totals(const ReduceArgs& a, const WaveDesc& w, double
     for (int i = 0; i < 4; ++i) {
         t.isl_raw += sh[4 * i + 0];
         t.dle += sh[4 * i + 1];
-        t.match += sh[16 + i];
+        t.ext += sh[16 + i];
         lse_merge_r(t.lse_m, t.lse_s, (float)sh[4 * i + 2], sh[4 * i + 3], inv_t2);
     }
     return t;
@@ -118,18 +118,21 @@ __device__ __forceinline__ float total_dlde(const ReduceArgs& a, const WaveTotal
     return (float)(-2.0 * (double)a.w_isl * t.isl_raw / (double)E + t.dle);
 }
 // the loss terms (one thread per waveform writes them): (L, ISL, PSL term,
-// E) with the soft PSL, or the hard PSL and the spectral variance of the
-// experiment loss from vals
+// E) with the soft PSL, or the hard PSL from vals; the spectral variance,
+// var(|s|) and the smoothness term from vals, the cell-wise extension terms
+// from the records
 __device__ __forceinline__ float4 loss_terms(const ReduceArgs& a, const WaveDesc& w, int wave, const WaveTotals& t,
                                              float E) {
     // complement waveforms carry ISL - M (Moyal: the full grid holds M E^2;
     // N E^2 for the periodic AF)
     const double isl = t.isl_raw + ((a.uniform_w && w.full_window) ? (double)w.moyal : 0.0);
-    const float psl = a.psl_hard ? a.vals[2 * wave]
+    const float psl = a.psl_hard ? a.vals[4 * wave]
                                  : ((t.lse_s > 0.0) ? (float)((double)t.lse_m + (double)a.temp * log(t.lse_s)) : 0.f);
     double loss = (double)a.w_isl * isl + (a.w_psl != 0.f ? (double)a.w_psl * (double)psl : 0.0);
-    if (a.w_spec != 0.f) loss += (double)a.w_spec * (double)a.vals[2 * wave + 1];
-    if (a.w_match != 0.f) loss += (double)a.w_match * t.match;
+    if (a.w_spec != 0.f) loss += (double)a.w_spec * (double)a.vals[4 * wave + 1];
+    if (a.w_const != 0.f) loss += (double)a.w_const * (double)a.vals[4 * wave + 2];
+    if (a.w_smooth != 0.f) loss += (double)a.w_smooth * (double)a.vals[4 * wave + 3];
+    if (a.ext_cells) loss += t.ext;
     return make_float4((float)loss, (float)isl, psl, E);
 }
 

@@ -48,8 +48,13 @@ __device__ float block_sum256(float v, float* sh) {
 // through the single-cell lag-product adjoint; and the spectral variance
 // V = var(P / sum P) of the N-point spectrum X of s with
 // dV/d conj(s[n]) = sum_j c_j X_j e^{+j 2 pi j n / N},
-// c_j = 2 (x_j - sum x^2) / (N S).  Dynamic LDS: samples, the N twiddles
-// and c_j X_j (3 N complex64).
+// c_j = 2 (x_j - sum x^2) / (N S).  The waveform-only terms of the
+// composite loss (Sec. 5.2): var(|s|) with gradient (|s[n]| - mu) s[n] /
+// (N |s[n]|), and the smoothness sum |s[n+1] - s[n]|^2 / E with gradient
+// (d[n-1] - d[n]) / E - (smoothness) s[n] / E, d[n] = s[n+1] - s[n]; they
+// read s from global memory.  Dynamic LDS: the samples for the hard PSL and
+// the spectral part, the N twiddles and c_j X_j for the spectral part
+// (up to 3 N complex64).
 __global__ __launch_bounds__(256) void extra_kernel(ExtraArgs a) {
     extern __shared__ float2 xs[];
     __shared__ float sh[4];
@@ -62,7 +67,8 @@ __global__ __launch_bounds__(256) void extra_kernel(ExtraArgs a) {
     float2* sv = xs;
     float2* twn = xs + N;
     float2* cx = xs + 2 * N;
-    for (int p = t; p < N; p += 256) sv[p] = s[p];
+    if (a.psl || a.spec)
+        for (int p = t; p < N; p += 256) sv[p] = s[p];
     if (a.spec) {
         for (int r = t; r < N; r += 256) {
             float sn, cs;
@@ -163,7 +169,31 @@ __global__ __launch_bounds__(256) void extra_kernel(ExtraArgs a) {
         __syncthreads();
     }
 
+    // ---- var(|s|) and the smoothness term: mean modulus, energy and the
+    // sum of squared steps, then the squared deviations from the mean
+    float mu = 0.f, Es = 1.f, varc = 0.f, smooth = 0.f;
+    if (a.wterms) {
+        float r1 = 0.f, e1 = 0.f, d1 = 0.f;
+        for (int p = t; p < N; p += 256) {
+            const float2 x = s[p];
+            const float q = cabs2(x);
+            r1 += __builtin_amdgcn_sqrtf(q);
+            e1 += q;
+            if (p + 1 < N) d1 += cabs2(csub(s[p + 1], x));
+        }
+        mu = block_sum256(r1, sh) / (float)N;
+        Es = block_sum256(e1, sh);
+        smooth = block_sum256(d1, sh) / Es;
+        float v1 = 0.f;
+        for (int p = t; p < N; p += 256) {
+            const float d = __builtin_amdgcn_sqrtf(cabs2(s[p])) - mu;
+            v1 = fmaf(d, d, v1);
+        }
+        varc = block_sum256(v1, sh) / (float)N;
+    }
+
     // ---- gradient: w_psl (single-cell adjoint + energy term) + w_spec dV/d conj(s)
+    // + w_const dvar/d conj(s) + w_smooth dSmooth/d conj(s)
     if (a.g_extra) {
         for (int p = t; p < N; p += 256) {
             float2 g = make_float2(0.f, 0.f);
@@ -197,15 +227,82 @@ __global__ __launch_bounds__(256) void extra_kernel(ExtraArgs a) {
                 }
                 g = cadd(g, cscale(x, a.w_spec));
             }
+            if (a.wterms) {
+                const float2 x = s[p];
+                const float r = __builtin_amdgcn_sqrtf(cabs2(x));
+                const float cc = r > 0.f ? a.w_const * (r - mu) / ((float)N * r) : 0.f;
+                const float invE = 1.f / Es;
+                float2 ds = cscale(x, -smooth * invE);
+                if (p > 0) ds = cadd(ds, cscale(csub(x, s[p - 1]), invE));
+                if (p + 1 < N) ds = csub(ds, cscale(csub(s[p + 1], x), invE));
+                g = cadd(g, cadd(cscale(x, cc), cscale(ds, a.w_smooth)));
+            }
             a.g_extra[w.s_off + p] = g;
         }
     }
     if (t == 0) {
         if (a.vals) {
-            a.vals[2 * b] = a.psl ? pmax : 0.f;
-            a.vals[2 * b + 1] = V;
+            a.vals[4 * b] = a.psl ? pmax : 0.f;
+            a.vals[4 * b + 1] = V;
+            a.vals[4 * b + 2] = varc;
+            a.vals[4 * b + 3] = smooth;
         }
         if (a.spec_out) a.spec_out[b] = V;
+    }
+}
+
+// Spectral-mask projection of projected descent (Sec. 6.2): X = DFT_N(s)
+// by its definition (the twiddle index j n mod N advances by j), Y = mask X,
+// out = IDFT_N(Y) / N; with unit, out / |out| (1 where it is 0).  Without a
+// mask only the unit-circle projection runs.  Dynamic LDS: samples, the N
+// twiddles and Y (3 N complex64).  Every sample is read into LDS before the
+// first store, so out may alias s.
+__global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
+    extern __shared__ float2 xs[];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const WaveDesc w = a.waves[b];
+    const int N = w.n;
+    const float2* s = a.s + w.s_off;  // may alias out
+    float2* out = a.out + w.s_off;
+    auto unit = [&](float2 y) {
+        const float r2 = cabs2(y);
+        return r2 > 0.f ? cscale(y, __builtin_amdgcn_rsqf(r2)) : make_float2(1.f, 0.f);
+    };
+    if (!a.mask) {
+        for (int p = t; p < N; p += 256) out[p] = a.unit ? unit(s[p]) : s[p];
+        return;
+    }
+    const float* __restrict__ mask = a.mask + w.s_off;
+    float2* sv = xs;
+    float2* twn = xs + N;
+    float2* yv = xs + 2 * N;
+    for (int p = t; p < N; p += 256) {
+        sv[p] = s[p];
+        float sn, cs;
+        sincospif(2.f * (float)p / (float)N, &sn, &cs);
+        twn[p] = make_float2(cs, -sn);  // exp(-j 2 pi p / N)
+    }
+    __syncthreads();
+    for (int j = t; j < N; j += 256) {
+        float2 x = make_float2(0.f, 0.f);
+        int r = 0;
+        for (int n = 0; n < N; ++n) {
+            x = cadd(x, cmul(sv[n], twn[r]));
+            r += j;
+            r = r >= N ? r - N : r;
+        }
+        yv[j] = cscale(x, mask[j] / (float)N);
+    }
+    __syncthreads();
+    for (int p = t; p < N; p += 256) {
+        float2 y = make_float2(0.f, 0.f);
+        int r = 0;  // j p mod N
+        for (int j = 0; j < N; ++j) {
+            y = cadd(y, cmulc(yv[j], twn[r]));
+            r += p;
+            r = r >= N ? r - N : r;
+        }
+        out[p] = a.unit ? unit(y) : y;
     }
 }
 
@@ -283,7 +380,7 @@ hipError_t launch_reduce_adam(const ReduceArgs& a, hipStream_t st) {
 
 hipError_t launch_extra(const ExtraArgs& a, int batch, int max_n, hipStream_t st) {
     if (batch <= 0) return hipSuccess;
-    const int lds = 3 * max_n * (int)sizeof(float2);
+    const int lds = (a.spec ? 3 : (a.psl ? 1 : 0)) * max_n * (int)sizeof(float2);
     static bool attr = false;
     if (!attr) {
         const hipError_t e = hipFuncSetAttribute((const void*)extra_kernel,
@@ -292,6 +389,20 @@ hipError_t launch_extra(const ExtraArgs& a, int batch, int max_n, hipStream_t st
         attr = true;
     }
     hipLaunchKernelGGL(extra_kernel, dim3(batch), dim3(256), (size_t)lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const ProjectArgs& a, int batch, int max_n, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    const int lds = a.mask ? 3 * max_n * (int)sizeof(float2) : 0;
+    static bool attr = false;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute((const void*)project_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 3 * 4096 * 8);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(project_kernel, dim3(batch), dim3(256), (size_t)lds, st, a);
     return hipGetLastError();
 }
 

@@ -275,13 +275,15 @@ __device__ void stage_split_twiddles(const AfArgs& a, float2* hi, float2* lo, in
 // transform gives rows tau and N - tau of the [N][N] grid (tau = 0 and
 // tau = N/2 give one row each), and the lag product and its adjoint index
 // samples modulo N.
-// modes that take L_match and the hard PSL (forward, fused ISL)
-template <int MODE>
-constexpr bool HARD_MODE_MATCH() {
-    return MODE == MODE_FWD || MODE == MODE_FUSED_ISL;
+// instances that take the extended epilogue terms (hard-PSL maximum,
+// L_match, mainlobe width): the forward pass, and the fused ISL pass built
+// with EXTK (split variants)
+template <int MODE, bool EXTK>
+constexpr bool EXT_MODE() {
+    return MODE == MODE_FWD || (MODE == MODE_FUSED_ISL && EXTK);
 }
 
-template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, bool CIRC, typename Tw>
+template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, bool CIRC, bool EXTK, typename Tw>
 __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, const Tw& twl,
                                                 const float2* s_lds, bool s_in_lds, double* scratch,
                                                 const WaveState& ws) {
@@ -424,14 +426,15 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
     float2* const mlb = reinterpret_cast<float2*>(scratch);
     double isl = 0.0, ls = 0.0, dle = 0.0, mt = 0.0;
-    // L_match against a target power grid and the hard-PSL maximum (forward
-    // and fused ISL modes; the extended epilogue copy)
-    // (split variants only: the halves-in-turn variant keeps its registers)
-    const bool match = SPLIT && HARD_MODE_MATCH<MODE>() && a.match_t != nullptr;
-    const bool hard_rt = SPLIT && HARD_MODE_MATCH<MODE>() && a.psl_hard != 0;
-    const bool ext_rt = match || hard_rt;
+    // L_match against a target power grid, the soft mainlobe width and the
+    // hard-PSL maximum (forward and fused ISL modes; the extended epilogue
+    // copy; split variants only: the halves-in-turn variant keeps its registers)
+    constexpr bool EXT_OK = SPLIT && EXT_MODE<MODE, EXTK>();
+    const bool match = EXT_OK && a.match_t != nullptr;
+    const bool width = EXT_OK && a.w_width != 0.f;
+    const bool hard_rt = EXT_OK && a.psl_hard != 0;
+    const bool ext_rt = match || width || hard_rt;
     // hard PSL: this lane's largest sidelobe power and its cell (tau >= 0 row)
-    constexpr bool HARD_MODE = MODE == MODE_FWD || MODE == MODE_FUSED_ISL;
     float hp = -1.f;
     int hi = 0;
     float lm = (want_lse && (lse_fixed || MODE == MODE_LOSS)) ? lse_ref(a.eps) : -INFINITY;
@@ -510,9 +513,6 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         const int64_t row_n = CIRC ? w.grid_off + (int64_t)(tz ? N - tz : 0) * RL : w.grid_off + (int64_t)(T - tz) * M;
         // rows tau and -tau of the halves-in-turn epilogue (empty when inactive)
         const unsigned row_bytes = active ? (unsigned)RL * 4u : 0u;
-        // target rows of L_match (the -tau row is read only with a distinct partner)
-        const Rsrc mt_p = make_rsrc(match ? a.match_t + row_p : nullptr, match ? row_bytes : 0u);
-        const Rsrc mt_n = make_rsrc(match ? a.match_t + row_n : nullptr, (match && two_rows) ? row_bytes : 0u);
         const Rsrc mag_p = make_rsrc(HAS_MAG_OUT && a.mag ? a.mag + row_p : nullptr, HAS_MAG_OUT && a.mag ? row_bytes : 0u);
         const Rsrc mag_n = make_rsrc(HAS_MAG_OUT && a.mag ? a.mag + row_n : nullptr, HAS_MAG_OUT && a.mag ? row_bytes : 0u);
         const Rsrc gm_p = make_rsrc(MODE == MODE_BWD_MAG ? a.grad_mag + row_p : nullptr, MODE == MODE_BWD_MAG ? row_bytes : 0u);
@@ -574,6 +574,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // the lane's bins run in float, then fold into float64.
             float isl_f = 0.f, dle_f = 0.f, mloc = -INFINITY, sl_f = 0.f;
             float mt_f = 0.f, dlm_f = 0.f;  // L_match: both cells of the pair explicitly
+            float wd_f = 0.f;               // soft mainlobe width
             float avs[(MODE == MODE_FWD) ? P : 1];
             // One straight-line copy per loss configuration (shift rule,
             // banded weights, mainlobe complement, soft-PSL on/off): every
@@ -647,12 +648,29 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     // distinct partner, (-tau, -k); coefficient and energy
                     // term per cell, not through the pair multiplier
                     float cm = 0.f;
+                    // Eq. 21: the k = 0 cells of rows tau and -tau (equal
+                    // powers) weigh |tau| sigma(gamma (p - 1/2)), since
+                    // p(0, 0) = 1 for every waveform; upstream
+                    // |tau| gamma sigma' per cell, energy term -2 p / E
+                    if (EXT && width && k == 0) {
+                        const float ld = (float)(CIRC ? min(tau, N - tau) : tau);
+                        const float sg = 1.f / (1.f + fast_exp2(-kLog2e * a.gamma * (pw - 0.5f)));
+                        wd_f += active ? mult * ld * sg : 0.f;
+                        if constexpr (NEEDS_INV) {
+                            const float u = active ? mult * a.w_width * ld * a.gamma * sg * (1.f - sg) : 0.f;
+                            cm += u * invE2;
+                            dlm_f = fmaf(-2.f * u * pw, invE, dlm_f);
+                        }
+                    }
                     if (EXT && match) {
-                        const float dp = active ? pw - buf_load1(mt_p, k * 4) : 0.f;
-                        const float dn = (active && two_rows) ? pw - buf_load1(mt_n, kn * 4) : 0.f;
+                        // target rows (the -tau row is read only with a distinct
+                        // partner) through plain per-lane pointers: the lag, and
+                        // so the row, differs between the lane groups of a wavefront
+                        const float dp = active ? pw - a.match_t[row_p + k] : 0.f;
+                        const float dn = (active && two_rows) ? pw - a.match_t[row_n + kn] : 0.f;
                         mt_f = fmaf(dp, dp, fmaf(dn, dn, mt_f));
                         if constexpr (NEEDS_INV) {
-                            cm = 2.f * a.w_match * (dp + dn) * invE2;
+                            cm += 2.f * a.w_match * (dp + dn) * invE2;
                             dlm_f = fmaf(-4.f * a.w_match * pw * invE, dp + dn, dlm_f);
                         }
                     }
@@ -738,7 +756,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     epilogue(T_{}, F_{}, F_{}, T_{}, T_{}, F_{});
                 else
                     epilogue(T_{}, F_{}, F_{}, T_{}, F_{}, F_{});
-            } else if (ext_rt) {
+            } else if constexpr (EXTK) {
                 ext_copy();
             } else if (main_tau) {
                 by_loss(T_{}, F_{}, T_{}, F_{});
@@ -747,7 +765,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             }
             isl += (double)(mult * isl_f);
             dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f + dlm_f);
-            mt += (double)mt_f;
+            if (match || width) mt += (double)fmaf(a.w_match, mt_f, a.w_width * wd_f);
             if (FWD_SUMS && want_lse && (lse_fixed || MODE == MODE_LOSS)) {
                 ls += (double)(mult * sl_f);
             } else if (MODE == MODE_FWD && want_lse && mloc > -INFINITY) {
@@ -922,9 +940,9 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
     isl = (double)wave_sum((float)isl);
     if (MODE != MODE_FWD) dle = (double)wave_sum((float)dle);
-    if (match) mt = (double)wave_sum((float)mt);
+    if (match || width) mt = (double)wave_sum((float)mt);
     // hard PSL: the wavefront's largest power, then its smallest cell index
-    const bool hard = SPLIT && HARD_MODE && a.psl_hard;
+    const bool hard = hard_rt;
     if (hard) {
         const float wmx = wave_allmax(hp);
         hi = wave_allmin_int(hp == wmx ? hi : 0x7fffffff);
@@ -949,7 +967,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         pr.lse_s = 0.0;
         pr.dle = 0.0;
         pr.lse_m = -INFINITY;
-        pr.match = 0.0;
+        pr.ext = 0.0;
         pr.psl_p = -1.f;
         pr.psl_i = 0;
         pr.pad = 0;
@@ -957,7 +975,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             pr.isl += scratch[4 * i + 0];
             if (FWD_SUMS) lse_merge(pr.lse_m, pr.lse_s, (float)scratch[4 * i + 1], scratch[4 * i + 2], inv_t2);
             pr.dle += scratch[4 * i + 3];
-            pr.match += scratch[96 + i];
+            pr.ext += scratch[96 + i];
             if (hard) {
                 // waves in order: larger power, then the smaller cell index
                 const float p = (float)scratch[64 + 2 * i];
@@ -1020,7 +1038,7 @@ using V5 = Variant<32, 1, 256, 1, 12, 12, 1, 0>; // M 8192: 32 points per lane, 
 // Persistent kernel over one size class: work group g runs items g, g + grid,
 // g + 2 grid, ... of the class's list, which the planner sorted longest first
 // (a static, deterministic assignment).
-template <int MODE, typename V, int LG, bool CIRC = false>
+template <int MODE, typename V, int LG, bool CIRC = false, bool EXTK = false>
 __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     static_assert(!CIRC || (V::SPLIT && V::S_LDS), "periodic AF: split variants with samples in LDS");
     extern __shared__ float2 dyn[];
@@ -1067,9 +1085,8 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
             const WaveDesc w = a.single ? a.w0 : a.waves[sg.wave];
             stage_wave<MODE, V::WGS, MH, CIRC>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st, nullptr, 0);
         }
-        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG), CIRC>(a, sg, lds, twl, s_lds, V::S_LDS != 0,
-                                                                            scratch,
-                                                                      st);
+        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG), CIRC, EXTK>(a, sg, lds, twl, s_lds,
+                                                                                  V::S_LDS != 0, scratch, st);
     }
 }
 

@@ -12,17 +12,17 @@ namespace graf {
 #define GRAF_CAT(a, b) GRAF_CAT2(a, b)
 using VSel = GRAF_CAT(V, GRAF_VARIANT);
 
-template <int MODE, int LG, bool CIRC>
+template <int MODE, int LG, bool CIRC, bool EXTK = false>
 static void* pick_lg(int lg) {
     if constexpr (LG > 15) {
         return nullptr;
     } else {
         if (lg == LG) {
             if constexpr (VSel::fits(LG) && (!CIRC || (VSel::SPLIT && VSel::S_LDS)))
-                return (void*)af_kernel<MODE, VSel, LG, CIRC>;
+                return (void*)af_kernel<MODE, VSel, LG, CIRC, EXTK>;
             return nullptr;
         }
-        return pick_lg<MODE, LG + 1, CIRC>(lg);
+        return pick_lg<MODE, LG + 1, CIRC, EXTK>(lg);
     }
 }
 
@@ -34,6 +34,9 @@ static void* pick_mode(int mode, int lg) {
         case MODE_BWD_LOSS: return pick_lg<MODE_BWD_LOSS, 1, CIRC>(lg);
         case MODE_FUSED_ISL: return pick_lg<MODE_FUSED_ISL, 1, CIRC>(lg);
         case MODE_LOSS: return pick_lg<MODE_LOSS, 1, CIRC>(lg);
+        case MODE_FUSED_EXT:
+            if constexpr (VSel::SPLIT) return pick_lg<MODE_FUSED_ISL, 1, CIRC, true>(lg);
+            return nullptr;
     }
     return nullptr;
 }

@@ -103,3 +103,149 @@ def test_match_at_its_own_surface_and_rejections(af):
     with pytest.raises(_lib.AfError) as ei:
         big.loss(to_dev(W.random_code(9000, seed=1)), w_isl=0.0, w_psl=1.0, psl_hard=True)
     assert ei.value.code == -2
+
+
+def rand_c64(n, seed, modulated=True):
+    rng = np.random.default_rng(seed)
+    s = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    if not modulated:
+        s = np.exp(1j * np.angle(s))
+    return O.to_c64_exact(s / np.sqrt(2.0))
+
+
+@pytest.mark.parametrize("n,m,T,periodic", [(100, 256, -1, False), (300, 1024, 40, False), (128, 128, -1, True),
+                                            (1024, 2048, -1, False), (256, 256, -1, True)])
+@pytest.mark.parametrize("w_isl", [0.0, 1.0])
+def test_soft_width_loss_and_gradient(af, n, m, T, periodic, w_isl):
+    say("width", n, m, T, periodic, w_isl)
+    s = rand_c64(n, 1300 + n)
+    Tn = n - 1 if T < 0 else T
+    plan = af.Plan([n], [m], [T], eps=EPS, periodic=periodic)
+    terms, g, _ = plan.loss(to_dev(s), w_isl=w_isl, w_psl=0.0, w_width=0.5, gamma=8.0)
+    terms0, _, _ = plan.loss(to_dev(s), w_isl=w_isl, w_psl=0.0, w_width=0.5, gamma=8.0, grad=False)
+    torch.cuda.synchronize()
+    params = O.LossParams(w_isl=w_isl, eps=EPS, w_width=0.5, gamma=8.0)
+    ref = O.loss_and_grad_circular(s, params) if periodic else O.loss_and_grad(s, m, Tn, params)
+    for tt in (terms, terms0):
+        assert abs(tt[0, 0].item() - ref["loss"]) <= 1e-4 * ref["loss"], (tt[0, 0].item(), ref["loss"])
+    check_grad(g.cpu().numpy().astype(np.complex128), ref["g"], "width %d %d" % (n, m))
+
+
+@pytest.mark.parametrize("n,m,T,periodic", [(200, 512, -1, False), (256, 256, -1, True)])
+def test_every_composite_term_together(af, n, m, T, periodic):
+    say("all terms", n, m, periodic)
+    s = rand_c64(n, 1400 + n)
+    Tn = n - 1
+    rows = n if periodic else 2 * Tn + 1
+    target = np.random.default_rng(7).uniform(0.0, 0.02, (rows, m)).astype(np.float32)
+    plan = af.Plan([n], [m], [T], eps=EPS, periodic=periodic)
+    kw = dict(w_isl=0.3, w_psl=1.0, psl_hard=True, match=torch.from_numpy(target.ravel()).cuda(), w_match=2.0,
+              w_width=0.25, gamma=5.0, w_const=1.5, w_smooth=0.75)
+    terms, g, _ = plan.loss(to_dev(s), **kw)
+    torch.cuda.synchronize()
+    params = O.LossParams(w_isl=0.3, eps=EPS, match=target.astype(np.float64), w_match=2.0, w_width=0.25,
+                          gamma=5.0, w_const=1.5, w_smooth=0.75)
+    base = O.loss_and_grad_circular(s, params) if periodic else O.loss_and_grad(s, m, Tn, params)
+    ex = O.experiment_loss_and_grad(s, m, 0.0, h_tau=1, h_k=1, periodic=periodic, eps=EPS)
+    want = base["loss"] + ex["psl"]
+    assert abs(terms[0, 0].item() - want) <= 1e-4 * want, (terms[0, 0].item(), want)
+    check_grad(g.cpu().numpy().astype(np.complex128), base["g"] + ex["g_psl"], "all terms")
+
+
+@pytest.mark.parametrize("sizes,ms,Ts", [([100, 37, 512], [256, 128, 1024], [-1, -1, 60]),
+                                         ([9000], [32768], [100])])
+def test_waveform_terms_any_class(af, sizes, ms, Ts):
+    # var(|s|) and the smoothness term alone: no AF gradient, any size class
+    # (the N = 9000 plan runs the halves-in-turn variant)
+    say("const + smooth", sizes)
+    ss = [rand_c64(n, 1500 + n) for n in sizes]
+    plan = af.Plan(sizes, ms, Ts, eps=EPS)
+    terms, g, _ = plan.loss(to_dev(np.concatenate(ss)), w_isl=0.0, w_const=1.5, w_smooth=0.75)
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy().astype(np.complex128)
+    off = 0
+    for b, s in enumerate(ss):
+        vc, gc = O.modulus_variance(s)
+        vs, gs = O.phase_smoothness(s)
+        want = 1.5 * vc + 0.75 * vs
+        assert abs(terms[b, 0].item() - want) <= 1e-4 * want, (b, terms[b, 0].item(), want)
+        check_grad(gg[off:off + len(s)], 1.5 * gc + 0.75 * gs, "const+smooth %d" % len(s))
+        off += len(s)
+
+
+def test_waveform_terms_in_the_adam_step(af):
+    # one Adam step on the phases of the ISL + smoothness loss against the
+    # oracle's gradient through phi and its Adam step
+    say("adam smooth")
+    n, m = 128, 256
+    phi = np.random.default_rng(9).uniform(-np.pi, np.pi, n).astype(np.float32)
+    plan = af.Plan([n], [m], eps=EPS)
+    st = af.PhaseState(torch.from_numpy(phi).cuda())
+    plan.optim_step(st, w_isl=1.0, w_smooth=2.0, lr=0.01)
+    torch.cuda.synchronize()
+    s = np.exp(1j * phi.astype(np.float64))
+    ref = O.loss_and_grad(s, m, n - 1, O.LossParams(w_isl=1.0, eps=EPS, w_smooth=2.0))
+    gphi = O.phase_grad(s, ref["g"])
+    want, _, _ = O.adam_step(phi.astype(np.float64), gphi, np.zeros(n), np.zeros(n), 1)
+    # the first Adam step moves each phase by lr sign(g) (up to eps): compare
+    # where the gradient is clear of zero, and bound the step everywhere
+    got = st.phi.cpu().numpy().astype(np.float64)
+    clear = np.abs(gphi) > 1e-3 * np.max(np.abs(gphi))
+    assert clear.sum() > n // 2
+    assert np.max(np.abs(got - want)[clear]) < 1e-5
+    assert np.max(np.abs(got - phi)) <= 0.01 * (1 + 1e-4)
+
+
+@pytest.mark.parametrize("unit", [False, True])
+def test_spectral_projection(af, unit):
+    say("projection", unit)
+    sizes = [100, 37, 512, 1]
+    ss = [rand_c64(n, 1600 + n) for n in sizes]
+    masks = []
+    for n in sizes:
+        k = np.arange(n)
+        kc = np.abs(np.where(k < (n + 1) // 2, k, k - n))
+        masks.append(np.where(kc <= n // 5, 1.0, np.where(kc <= n // 4, 0.5, 0.0)).astype(np.float32))
+    plan = af.Plan(sizes, [256, 128, 1024, 128], eps=EPS)
+    sd = to_dev(np.concatenate(ss))
+    md = torch.from_numpy(np.concatenate(masks)).cuda()
+    out = plan.project(sd, md, unit=unit)
+    inplace = sd.clone()
+    plan.project(inplace, md, unit=unit, out=inplace)
+    uonly = plan.project(sd, None, unit=True)
+    torch.cuda.synchronize()
+    o, ip, uo = (x.cpu().numpy().astype(np.complex128) for x in (out, inplace, uonly))
+    assert np.array_equal(o, ip)
+    off = 0
+    for s, mk in zip(ss, masks):
+        y = O.spectral_projection(s, mk.astype(np.float64))
+        got = o[off:off + len(s)]
+        if unit:
+            # directions agree where the projected sample is clear of zero
+            clear = np.abs(y) > 1e-2 * np.max(np.abs(y))
+            assert np.max(np.abs(np.abs(got) - 1.0)) < 1e-6
+            assert np.max(np.abs(got[clear] - y[clear] / np.abs(y[clear]))) < 1e-4, len(s)
+        else:
+            assert np.max(np.abs(got - y)) <= 1e-5 * np.max(np.abs(y)), len(s)
+        assert np.max(np.abs(uo[off:off + len(s)] - s / np.abs(s))) < 1e-6
+        off += len(s)
+
+
+def test_new_terms_rejections(af):
+    from paper_2506_22935_amd import _lib
+    n, m = 128, 256
+    plan = af.Plan([n], [m], eps=EPS)
+    s = to_dev(rand_c64(n, 1))
+    with pytest.raises(_lib.AfError) as ei:
+        plan.loss(s, w_isl=0.0, w_psl=1.0, w_width=1.0)  # the width with the soft PSL
+    assert ei.value.code == -2
+    with pytest.raises(_lib.AfError) as ei:
+        plan.loss(s, w_isl=1.0, w_width=1.0, gamma=-1.0)
+    assert ei.value.code == -1
+    big = af.Plan([5000], [16384], [100], eps=EPS)
+    with pytest.raises(_lib.AfError) as ei:
+        big.loss(to_dev(rand_c64(5000, 2)), w_isl=1.0, w_width=1.0)  # halves-in-turn variant
+    assert ei.value.code == -2
+    with pytest.raises(_lib.AfError) as ei:
+        big.project(to_dev(rand_c64(5000, 2)), torch.ones(5000, device="cuda"))  # mask beyond N = 4096
+    assert ei.value.code == -2
