@@ -25,7 +25,7 @@ __all__ = [
     "to_c64_exact", "energy", "chi", "chi_rows", "magnitude", "power",
     "centred_bins", "mainlobe_mask", "isl_weights", "LossParams", "loss_terms",
     "loss_and_grad", "loss_grad_from_chi", "sigmoid", "soft_mainlobe_width", "modulus_variance",
-    "phase_smoothness", "spectral_projection", "magnitude_backward", "grad_from_upstream", "phase_grad",
+    "phase_smoothness", "spectral_projection", "cross_chi", "cross_magnitude_backward", "magnitude_backward", "grad_from_upstream", "phase_grad",
     "adam_step", "bf16_round", "gelu", "gelu_grad", "mlp_forward",
     "mlp_backward", "psl_db", "chi_rows_fft", "magnitude_backward_fft",
     "chi_circular", "chi_circular_rows", "circular_lag_distance", "circular_mainlobe_mask", "circular_isl_weights",
@@ -461,6 +461,73 @@ def experiment_loss_and_grad(s, m, lam, alpha=2000.0, h_tau=0, h_k=0, periodic=F
     V, gv = spectral_variance(s)
     return dict(loss=psl + lam * alpha * V, psl=psl, cell=cell, spec_var=V, g=gp + lam * alpha * gv,
                 g_psl=gp, g_spec=gv, chi=c, E=E, a=magnitude(c, E, eps), side=side)
+
+
+# ----------------------------------------------------------------------------
+# cross-ambiguity of two waveforms (the cross-AF/MIMO extension the paper's
+# limitations name): chi_su[tau, k] = sum_n s[n] conj(u[n - tau]) exp(-j 2 pi
+# k n / M), equal to chi when u = s; normalised power p = |chi_su|^2 /
+# (E_s E_u) <= 1 by Cauchy-Schwarz, a = sqrt(p + eps)
+# ----------------------------------------------------------------------------
+
+def _cross_products(s, u, max_lag):
+    """Rows tau = -T..T of the lag products x_tau[n] = s[n] conj(u[n - tau])
+    (zero where n - tau leaves [0, N))."""
+    n = s.shape[0]
+    X = np.zeros((2 * max_lag + 1, n), dtype=np.complex128)
+    idx = np.arange(n)
+    for i, tau in enumerate(range(-max_lag, max_lag + 1)):
+        j = idx - tau
+        ok = (j >= 0) & (j < n)
+        X[i, ok] = s[ok] * np.conj(u[j[ok]])
+    return X
+
+
+def _dft_matrix(n, m):
+    """F[n, k] = exp(-j 2 pi k n / M), from the integer product k n mod M."""
+    kn = np.outer(np.arange(n, dtype=np.int64), np.arange(m, dtype=np.int64)) % m
+    return np.exp(-2j * np.pi * kn / m)
+
+
+def cross_chi(s, u, m, max_lag=None):
+    """The cross-AF grid [2T+1, M] by its defining sum (a product matrix
+    times the DFT matrix)."""
+    s = np.asarray(s, dtype=np.complex128)
+    u = np.asarray(u, dtype=np.complex128)
+    n = s.shape[0]
+    T = n - 1 if max_lag is None or max_lag < 0 else int(max_lag)
+    return _cross_products(s, u, T) @ _dft_matrix(n, m)
+
+
+def cross_magnitude_backward(s, u, m, max_lag, grad_mag, eps):
+    """(dL/d conj(s), dL/d conj(u)) for an upstream dL/da on the cross-AF
+    magnitude grid.  Per cell G = g_a chi / (2 E_s E_u a); Q_tau[n] =
+    sum_k G[tau, k] exp(+j 2 pi k n / M); then dL/d conj(s[n]) = sum_tau
+    u[n - tau] Q_tau[n] and dL/d conj(u[m]) = sum_tau s[m + tau]
+    conj(Q_tau[m + tau]); the energies add dL/dE_s s and dL/dE_u u with
+    dL/dE_s = -sum g_a p / (2 a E_s) (and E_u alike)."""
+    s = np.asarray(s, dtype=np.complex128)
+    u = np.asarray(u, dtype=np.complex128)
+    n = s.shape[0]
+    T = n - 1 if max_lag is None or max_lag < 0 else int(max_lag)
+    F = _dft_matrix(n, m)
+    c = _cross_products(s, u, T) @ F
+    Es, Eu = energy(s), energy(u)
+    p = (c.real ** 2 + c.imag ** 2) / (Es * Eu)
+    a = np.sqrt(p + eps)
+    ga = np.asarray(grad_mag, dtype=np.float64)
+    G = ga * c / (2.0 * Es * Eu * a)
+    Q = G @ np.conj(F).T
+    gs = np.zeros(n, dtype=np.complex128)
+    gu = np.zeros(n, dtype=np.complex128)
+    idx = np.arange(n)
+    for i, tau in enumerate(range(-T, T + 1)):
+        j = idx - tau
+        ok = (j >= 0) & (j < n)
+        gs[ok] += u[j[ok]] * Q[i, ok]
+        np.add.at(gu, j[ok], s[ok] * np.conj(Q[i, ok]))
+    q = float(np.sum(ga * p / a))
+    return gs - q / (2.0 * Es) * s, gu - q / (2.0 * Eu) * u
 
 
 # ----------------------------------------------------------------------------

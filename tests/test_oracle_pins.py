@@ -742,3 +742,64 @@ def test_spectral_projection_two_tones():
     # a half-weight mask scales a tone by one half
     mask[5] = 0.5
     assert np.max(np.abs(O.spectral_projection(s, mask) - 0.5 * a * np.exp(2j * np.pi * 5 * k / n))) < 1e-13
+
+
+# ---- cross-ambiguity (two waveforms)
+
+def test_cross_af_with_itself_is_the_af():
+    n, m, T = 40, 128, 17
+    s = rand_complex(n, 50)
+    c = O.cross_chi(s, s, m, T)
+    ref = O.chi(s, m, T)
+    assert np.max(np.abs(c - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_cross_af_swap_delay_and_volume():
+    n, m = 48, 128
+    s = rand_complex(n, 51)
+    u = rand_complex(n, 52)
+    c_su = O.cross_chi(s, u, m)
+    c_us = O.cross_chi(u, s, m)
+    T = n - 1
+    tau = np.arange(-T, T + 1)[:, None]
+    k = np.arange(m)[None, :]
+    # chi_us(tau, k) = exp(-j 2 pi k tau / M) conj(chi_su(-tau, -k))
+    flip = np.conj(c_su[::-1][:, (-np.arange(m)) % m])
+    assert np.max(np.abs(c_us - np.exp(-2j * np.pi * k * tau / m) * flip)) < 1e-10 * np.max(np.abs(c_su))
+    # cross Moyal volume: sum over the full grid of |chi_su|^2 = M E_s E_u
+    vol = float(np.sum(np.abs(c_su) ** 2))
+    assert abs(vol - m * O.energy(s) * O.energy(u)) < 1e-10 * vol
+    # a delayed copy u[n] = s[n - d] moves the lag: chi_su(tau) = chi_ss(tau + d)
+    d = 5
+    s2 = s.copy()
+    s2[n - d:] = 0.0
+    u2 = np.zeros(n, dtype=np.complex128)
+    u2[d:] = s2[:n - d]
+    c = O.cross_chi(s2, u2, m)
+    a = O.chi(s2, m, T)
+    assert np.max(np.abs(c[:2 * T + 1 - d] - a[d:])) < 1e-10 * np.max(np.abs(a))
+    # Cauchy-Schwarz: |chi_su|^2 <= E_s E_u
+    assert np.max(np.abs(c_su) ** 2) <= O.energy(s) * O.energy(u) * (1 + 1e-12)
+
+
+def test_cross_magnitude_backward_finite_differences():
+    n, m, T = 14, 32, 9
+    s = rand_complex(n, 53)
+    u = rand_complex(n, 54)
+    w = np.random.default_rng(55).standard_normal((2 * T + 1, m))
+    eps = 1e-9
+
+    def f(x, y):
+        c = O.cross_chi(x, y, m, T)
+        p = np.abs(c) ** 2 / (O.energy(x) * O.energy(y))
+        return float(np.sum(w * np.sqrt(p + eps)))
+
+    gs, gu = O.cross_magnitude_backward(s, u, m, T, w, eps)
+    fs = _fd_grad(lambda x: f(x, u), s)
+    fu = _fd_grad(lambda y: f(s, y), u)
+    assert np.max(np.abs(gs - fs)) < 1e-6 * np.max(np.abs(fs))
+    assert np.max(np.abs(gu - fu)) < 1e-6 * np.max(np.abs(fu))
+    # with u = s the two gradients add up to the AF's magnitude backward
+    ga, gb = O.cross_magnitude_backward(s, s, m, T, w, eps)
+    ref = O.magnitude_backward(s, m, T, w, eps)
+    assert np.max(np.abs(ga + gb - ref)) < 1e-9 * np.max(np.abs(ref))
