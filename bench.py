@@ -532,8 +532,78 @@ def bench_copy(args, torch):
                 config=dict(workload="copy: 1 GiB device-to-device"), unit="GB/s")
 
 
+def bench_cross(args, torch):
+    """Cross-ambiguity of waveform pairs (the cross-AF / MIMO extension): 64
+    pairs of independent random-phase codes, N = 1024, M = 2048, full lag
+    window; a step is the a grid forward and the backward of both inputs from
+    an upstream dL/da grid (the gradient of sum a), inputs in HBM."""
+    import numpy as np
+    from paper_2506_22935_amd import af, workloads as W
+    B, n, m = 64, 1024, 2048
+    T = n - 1
+    rows = 2 * T + 1
+    s = torch.from_numpy(W.unimodular(W.random_phases(B * n, seed=args.seed + 21))).cuda()
+    u = torch.from_numpy(W.unimodular(W.random_phases(B * n, seed=args.seed + 22))).cuda()
+    plan = af.Plan([n] * B, [m] * B, eps=1e-12)
+    cells = B * rows * m
+    g_up = torch.ones(cells, dtype=torch.float32, device="cuda")
+    ws = plan.cross_workspace()
+    log("cross: %d pairs N=%d M=%d, %.3g cells, %d segments" % (B, n, m, cells, plan.summary()["segments"]))
+
+    def step():
+        plan.cross_forward(s, u, mag=True)
+        plan.cross_backward(s, u, g_up, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    ms = timed(step, args.steps, torch)
+    fwd_ms = timed(lambda: plan.cross_forward(s, u, mag=True), 20, torch)
+    bwd_ms = timed(lambda: plan.cross_backward(s, u, g_up, ws=ws), 20, torch)
+    # per row: two M/2-point transforms forward, and as many inverse in the backward
+    half = fft_flops(2 * rows * B, m // 2)
+    flops_bwd = 2.0 * half
+    ach = flops_bwd / (bwd_ms * 1e-3) / 1e12
+    log("cross: %.4f ms/step (forward %.4f, backward %.4f)" % (ms, fwd_ms, bwd_ms))
+    out = dict(value=cells / (ms * 1e-3), ms_per_step=ms,
+               config=dict(workload="cross: 64 pairs of random-phase codes, N=1024, M=2048, full window, "
+                                    "a forward + backward of both inputs from dL/da",
+                           pairs=B, n=n, m=m, cells=cells,
+                           stage_ms=dict(forward=round(fwd_ms, 5), backward=round(bwd_ms, 5))),
+               roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                             frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
+                             kernel="cross-AF backward (forward + inverse transforms, two-output gather)",
+                             kernel_ms=round(bwd_ms, 5), flops_per_launch=flops_bwd))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_cross(n, m, args.seed, budget_s=10.0)
+    return out
+
+
+def cpu_baseline_cross(n, m, seed, budget_s=10.0):
+    """The oracle's cross-AF magnitude and its backward on one pair, repeated
+    until the budget is spent."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    import oracle as O
+    from paper_2506_22935_amd import workloads as W
+    blas = [p["num_threads"] for p in threadpool_info() if p.get("user_api") == "blas"]
+    s = O.to_c64_exact(W.unimodular(W.random_phases(n, seed=seed + 21)))
+    u = O.to_c64_exact(W.unimodular(W.random_phases(n, seed=seed + 22)))
+    T = n - 1
+    ones = np.ones((2 * T + 1, m))
+    done, t_all = 0, 0.0
+    while t_all < budget_s:
+        t0 = time.perf_counter()
+        c = O.cross_chi(s, u, m, T)
+        np.sqrt(np.abs(c) ** 2 / (O.energy(s) * O.energy(u)) + 1e-12)
+        O.cross_magnitude_backward(s, u, m, T, ones, 1e-12)
+        t_all += time.perf_counter() - t0
+        done += 1
+    return dict(value=done * (2 * T + 1) * m / t_all, unit="cells/s", cores=max(blas) if blas else 1, kind="oracle",
+                sample="cross-AF a grid + backward of one pair (N=%d, M=%d), %d repeats, %.1f s" % (n, m, done, t_all))
+
+
 WORKLOADS = {"single": bench_single, "uneven": bench_uneven, "large": bench_large, "proposal": bench_proposal,
-             "periodic": bench_periodic, "experiment": bench_experiment, "copy": bench_copy}
+             "periodic": bench_periodic, "experiment": bench_experiment, "copy": bench_copy, "cross": bench_cross}
 
 
 def main():

@@ -224,6 +224,27 @@ af_status af_spectral_variance(const af_plan* plan, const void* s, float* value,
  * out may equal s (in place).  unit must be 0 or 1; mask NULL with unit 0 copies. */
 af_status af_project(const af_plan* plan, const void* s, const float* mask, int32_t unit, void* out, void* stream);
 
+/* Cross-ambiguity of two waveforms (the cross-AF / MIMO extension that the
+ * limitations section names): per waveform b of the plan, s and u are
+ * device complex64 arrays packed like the plan's input (u[b] has the same N
+ * as s[b]) and
+ *   chi_su[tau, k] = sum_n s[n] conj(u[n - tau]) exp(-j 2 pi k n / M),
+ * on the plan's grids ([2T+1][M], row tau + T), with a = sqrt(|chi_su|^2 /
+ * (E_s E_u) + eps) (|chi_su|^2 <= E_s E_u; chi_su = chi when u = s).  Plans
+ * whose classes are aperiodic with M <= 8192 (N <= 4096) only;
+ * AF_ERR_UNSUPPORTED otherwise.
+ * af_cross_forward: mag (a grids), chi (chi_su grids) and energy (device
+ * float[batch][2] = E_s, E_u) are each nullable; no workspace.
+ * af_cross_backward: grad_mag holds dL/da on the grids; grad_s and grad_u
+ * receive dL/d conj(s) and dL/d conj(u) (overwritten, packed like s); ws is
+ * device memory of af_cross_workspace_size bytes, 256-byte aligned
+ * (AF_ERR_WORKSPACE when smaller).  Deterministic: no atomics. */
+af_status af_cross_workspace_size(const af_plan* plan, size_t* bytes);
+af_status af_cross_forward(const af_plan* plan, const void* s, const void* u, float* mag, void* chi, float* energy,
+                           void* stream);
+af_status af_cross_backward(const af_plan* plan, const void* s, const void* u, const float* grad_mag, void* grad_s,
+                            void* grad_u, void* ws, size_t ws_bytes, void* stream);
+
 /* s[i] = exp(j phi[i]) for i < count (device arrays). */
 af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream);
 

@@ -483,20 +483,22 @@ def _cross_products(s, u, max_lag):
     return X
 
 
-def _dft_matrix(n, m):
-    """F[n, k] = exp(-j 2 pi k n / M), from the integer product k n mod M."""
-    kn = np.outer(np.arange(n, dtype=np.int64), np.arange(m, dtype=np.int64)) % m
+def _dft_matrix(n, m, bins=None):
+    """F[n, k] = exp(-j 2 pi k n / M) for the bins k (all M by default), from
+    the integer product k n mod M."""
+    k = np.arange(m, dtype=np.int64) if bins is None else np.asarray(bins, dtype=np.int64)
+    kn = np.outer(np.arange(n, dtype=np.int64), k) % m
     return np.exp(-2j * np.pi * kn / m)
 
 
-def cross_chi(s, u, m, max_lag=None):
+def cross_chi(s, u, m, max_lag=None, bins=None):
     """The cross-AF grid [2T+1, M] by its defining sum (a product matrix
-    times the DFT matrix)."""
+    times the DFT matrix); with bins, only those columns."""
     s = np.asarray(s, dtype=np.complex128)
     u = np.asarray(u, dtype=np.complex128)
     n = s.shape[0]
     T = n - 1 if max_lag is None or max_lag < 0 else int(max_lag)
-    return _cross_products(s, u, T) @ _dft_matrix(n, m)
+    return _cross_products(s, u, T) @ _dft_matrix(n, m, bins)
 
 
 def cross_magnitude_backward(s, u, m, max_lag, grad_mag, eps):

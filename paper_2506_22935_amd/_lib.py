@@ -67,6 +67,9 @@ SIGNATURES = {
     "af_phase_to_signal": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "af_spectral_variance": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "af_project": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP, _VP]),
+    "af_cross_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
+    "af_cross_forward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "af_cross_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "af_optim_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(AfLossParams),
                                      ctypes.POINTER(AfAdamParams), _VP, _VP, _SZ, _VP]),
     "af_gemm_config": (ctypes.c_int, [_I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),

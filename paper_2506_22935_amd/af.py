@@ -245,6 +245,39 @@ class Plan:
         return out
 
 
+    def cross_workspace(self):
+        """Device workspace for cross_backward (allocated once per plan)."""
+        if getattr(self, "_cross_ws", None) is None:
+            n = ctypes.c_size_t(0)
+            L.check("af_cross_workspace_size", L.lib().af_cross_workspace_size(self._h, ctypes.byref(n)))
+            self._cross_ws = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device=_DEV)
+        return self._cross_ws
+
+    def cross_forward(self, s, u, mag=True, chi=False):
+        """Cross-ambiguity of s and u (packed like the plan's input): returns
+        (a grids or None, chi_su grids or None, float32[B, 2] = E_s, E_u)."""
+        _need(s, torch.complex64, "s")
+        _need(u, torch.complex64, "u")
+        m = torch.empty(self.total_cells, dtype=torch.float32, device=_DEV) if mag else None
+        c = torch.empty(self.total_cells, dtype=torch.complex64, device=_DEV) if chi else None
+        e = torch.empty(self.batch, 2, dtype=torch.float32, device=_DEV)
+        L.check("af_cross_forward", L.lib().af_cross_forward(self._h, _ptr(s), _ptr(u), _ptr(m), _ptr(c), _ptr(e),
+                                                             _stream()))
+        return m, c, e
+
+    def cross_backward(self, s, u, grad_mag, ws=None):
+        """(dL/d conj(s), dL/d conj(u)) for the upstream dL/da grid."""
+        _need(s, torch.complex64, "s")
+        _need(u, torch.complex64, "u")
+        _need(grad_mag, torch.float32, "grad_mag")
+        ws = self.cross_workspace() if ws is None else ws
+        gs = torch.empty_like(s)
+        gu = torch.empty_like(u)
+        L.check("af_cross_backward", L.lib().af_cross_backward(self._h, _ptr(s), _ptr(u), _ptr(grad_mag), _ptr(gs),
+                                                               _ptr(gu), _ptr(ws), ws.numel(), _stream()))
+        return gs, gu
+
+
 class PhaseState:
     """Phases, Adam moments, the device step counter and s = exp(j phi)."""
 

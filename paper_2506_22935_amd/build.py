@@ -27,7 +27,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 def _units():
     units = [("af_api.hip", [], "af_api.o"),
              ("af_reduce.hip", [], "af_reduce.o"),
-             ("mlp_kernels.hip", [], "mlp_kernels.o")]
+             ("mlp_kernels.hip", [], "mlp_kernels.o"),
+             ("af_cross.hip", [], "af_cross.o")]
     for v in range(N_VARIANTS):
         units.append(("af_variant.hip", ["-DGRAF_VARIANT=%d" % v], "af_variant%d.o" % v))
     return [u for u in units if os.path.exists(os.path.join(CSRC, u[0]))]

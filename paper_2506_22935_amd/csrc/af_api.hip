@@ -74,6 +74,7 @@ struct af_plan {
     int64_t cells = 0, store_bytes = 0;
     size_t off_parts = 0, off_energy = 0, off_slabs = 0, off_slabs2 = 0, off_extra = 0, off_vals = 0, off_store = 0,
            ws_total = 0;
+    int64_t slab_elems = 0;  // complex64 per slab set ([segs][N] per waveform)
 
     // plan-owned device tables
     WaveDesc* d_waves = nullptr;
@@ -272,9 +273,10 @@ af_status build_schedule(af_plan* p) {
     const size_t parts_b = align256(segs.size() * sizeof(graf::Part));
     const size_t energy_b = align256((size_t)B * sizeof(float));
     const size_t slabs_b = align256((size_t)slab_elems * sizeof(float2));
+    p->slab_elems = slab_elems;
     const size_t slabs2_b = align256((size_t)slab2_elems * sizeof(float2));
     const size_t store_b = align256((size_t)store_elems * sizeof(float2));
-    // the experiment loss's gradient (packed like s) and its [B][2] values
+    // the per-waveform terms' gradient (packed like s) and their [B][4] values
     int64_t s_extent = 0;
     for (const af_wave& w : p->waves) s_extent = std::max<int64_t>(s_extent, w.s_off + w.n);
     const size_t extra_b = align256((size_t)s_extent * sizeof(float2));
@@ -825,6 +827,81 @@ af_status af_project(const af_plan* p, const void* s, const float* mask, int32_t
     a.unit = unit;
     a.out = (float2*)out;
     return graf::launch_project(a, p->batch, p->max_n, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
+}
+
+// ------------------------------------------------------- cross-AF --
+namespace {
+af_status check_cross(const af_plan* p, const void* s, const void* u) {
+    if (!p || !s || !u || !aligned(s, 8) || !aligned(u, 8)) return AF_ERR_INVALID_ARG;
+    for (const af_plan::Class& k : p->classes)
+        if (k.circ || !graf::cross_lg_supported(k.lg)) return AF_ERR_UNSUPPORTED;
+    return AF_OK;
+}
+size_t cross_slab_bytes(const af_plan* p) { return align256((size_t)p->slab_elems * sizeof(float2)); }
+size_t cross_ws_bytes(const af_plan* p) {
+    return 2 * cross_slab_bytes(p) + align256((size_t)p->n_segs * sizeof(double)) +
+           align256((size_t)p->batch * 2 * sizeof(float));
+}
+graf::CrossArgs cross_args(const af_plan* p, const void* s, const void* u) {
+    graf::CrossArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.s = (const float2*)s;
+    a.u = (const float2*)u;
+    a.waves = p->d_waves;
+    a.tw = p->d_tw;
+    a.log2_mmax = p->log2_mmax;
+    a.eps = p->eps;
+    return a;
+}
+af_status launch_cross_classes(const af_plan* p, int mode, graf::CrossArgs a, hipStream_t st) {
+    for (const af_plan::Class& k : p->classes) {
+        a.segs = p->d_segs + k.begin;
+        if (graf::launch_cross(mode, k.lg, a, k.count, st) != hipSuccess) return AF_ERR_HIP;
+    }
+    return AF_OK;
+}
+}  // namespace
+
+af_status af_cross_workspace_size(const af_plan* p, size_t* bytes) {
+    if (!p || !bytes) return AF_ERR_INVALID_ARG;
+    *bytes = cross_ws_bytes(p);
+    return AF_OK;
+}
+
+af_status af_cross_forward(const af_plan* p, const void* s, const void* u, float* mag, void* chi, float* energy,
+                           void* stream) {
+    af_status rc = check_cross(p, s, u);
+    if (rc != AF_OK) return rc;
+    if (!aligned(mag, 4) || !aligned(chi, 8) || !aligned(energy, 4)) return AF_ERR_INVALID_ARG;
+    graf::CrossArgs a = cross_args(p, s, u);
+    a.mag = mag;
+    a.chi = (float2*)chi;
+    a.energy = energy;
+    return launch_cross_classes(p, 0, a, (hipStream_t)stream);
+}
+
+af_status af_cross_backward(const af_plan* p, const void* s, const void* u, const float* grad_mag, void* grad_s,
+                            void* grad_u, void* ws, size_t ws_bytes, void* stream) {
+    af_status rc = check_cross(p, s, u);
+    if (rc != AF_OK) return rc;
+    if (!grad_mag || !grad_s || !grad_u || !ws || !aligned(grad_mag, 4) || !aligned(grad_s, 8) ||
+        !aligned(grad_u, 8) || !aligned(ws, 256))
+        return AF_ERR_INVALID_ARG;
+    if (ws_bytes < cross_ws_bytes(p)) return AF_ERR_WORKSPACE;
+    char* b = (char*)ws;
+    const size_t sb = cross_slab_bytes(p);
+    graf::CrossArgs a = cross_args(p, s, u);
+    a.grad_mag = grad_mag;
+    a.slab_s = (float2*)b;
+    a.slab_u = (float2*)(b + sb);
+    a.part = (double*)(b + 2 * sb);
+    a.energy = (float*)(b + 2 * sb + align256((size_t)p->n_segs * sizeof(double)));
+    a.grad_s = (float2*)grad_s;
+    a.grad_u = (float2*)grad_u;
+    hipStream_t st = (hipStream_t)stream;
+    rc = launch_cross_classes(p, 1, a, st);
+    if (rc != AF_OK) return rc;
+    return graf::launch_cross_reduce(a, p->batch, p->max_n, st) == hipSuccess ? AF_OK : AF_ERR_HIP;
 }
 
 af_status af_phase_to_signal(const float* phi, void* s, int64_t count, void* stream) {

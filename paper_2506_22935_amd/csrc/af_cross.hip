@@ -1,0 +1,260 @@
+// Cross-ambiguity of two waveforms s and u of one length N:
+//   chi_su[tau, k] = sum_n s[n] conj(u[n - tau]) e^{-j 2 pi k n / M},
+// the cross-AF / MIMO extension that the paper's limitations section names
+// (chi_su = chi when u = s), with the magnitude
+//   a = sqrt(|chi_su|^2 / (E_s E_u) + eps)   (|chi_su|^2 <= E_s E_u)
+// and the backward from an upstream dL/da for both inputs.
+//
+// One 256-thread work group per segment of the plan's lag list (lags
+// [tau_begin, tau_end), tau >= 0); each lag gives rows +tau and -tau.  Unlike
+// the auto-AF, the two rows are not conjugate mirrors, so every row is the
+// M-point DFT of its own lag product x[n] = s[n] conj(u[n - tau]) (n is the
+// absolute sample index: no phase correction), taken as the two MH-point
+// transforms of the even and odd bins (M = 2 MH >= 2N).  Lane groups of
+// MH/16 lanes take one row each per iteration, both halves in turn.
+//
+// Backward: per cell G = g_a chi / (2 E_s E_u a); Q[n] = sum_k G[k]
+// e^{+j 2 pi k n / M} is the inverse of the even half plus w_M^{-n} times the
+// inverse of the odd half, and the two halves land in the same lanes.  The
+// groups leave Q in LDS, and after a barrier every thread gathers, for the
+// samples it owns, dL/d conj(s[n]) += u[n - tau] Q[n] and
+// dL/d conj(u[n]) += s[n + tau] conj(Q[n + tau]) over the iteration's rows
+// (the gather splits into two outputs).  Per-segment slabs of both, and the
+// segment's sum of g_a p / a, are added in a fixed order by xreduce_kernel,
+// which applies dL/dE_s = -sum g_a p / (2 a E_s) (and E_u alike).
+#include "af_internal.h"
+#include "af_device.h"
+
+namespace graf {
+namespace {
+
+constexpr int XP = 16;     // points per lane
+constexpr int XWGS = 256;  // threads per work group
+
+__device__ float xblock_sum(float v, float* sh) {
+    v = wave_allsum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+template <int LG>
+struct XShape {
+    static constexpr int MH = 1 << LG;
+    static constexpr int L = MH / XP;    // lanes per group
+    static constexpr int G = XWGS / L;   // groups (rows per iteration)
+    static constexpr int BUF = LdsSize<MH>::value;
+    static constexpr int NJ = (MH + XWGS - 1) / XWGS;  // samples owned per thread
+    static constexpr int lds_bytes() { return (G * BUF + 2 * MH) * 8; }
+};
+
+template <int MODE, int LG>
+__global__ __launch_bounds__(XWGS) void xaf_kernel(CrossArgs a) {
+    using S = XShape<LG>;
+    constexpr int MH = S::MH, L = S::L, G = S::G, BUF = S::BUF, NJ = S::NJ;
+    static_assert(L >= 1 && G >= 1 && G * L == XWGS, "lane groups must tile the work group");
+    extern __shared__ float2 dyn[];
+    __shared__ float shf[8];
+    __shared__ double shd[4];
+    float2* sv = dyn + G * BUF;  // s, zero past N
+    float2* uv = sv + MH;        // u, zero past N
+
+    const SegDesc sg = a.segs[blockIdx.x];
+    const WaveDesc w = a.waves[sg.wave];
+    const int N = w.n, T = w.T;
+    constexpr int M = 2 * MH;
+    const int tid = threadIdx.x;
+    const int grp = tid / L;
+    const int l = tid - grp * L;
+    float2* buf = dyn + grp * BUF;
+    const TwTable twl{a.tw, a.log2_mmax - w.log2m};
+
+    float es = 0.f, eu = 0.f;
+    for (int i = tid; i < MH; i += XWGS) {
+        const float2 x = i < N ? a.s[w.s_off + i] : make_float2(0.f, 0.f);
+        const float2 y = i < N ? a.u[w.s_off + i] : make_float2(0.f, 0.f);
+        sv[i] = x;
+        uv[i] = y;
+        es += cabs2(x);
+        eu += cabs2(y);
+    }
+    const float Es = xblock_sum(es, shf);
+    const float Eu = xblock_sum(eu, shf + 4);
+    const float invEE = 1.f / (Es * Eu);
+    if (sg.tau_begin == 0 && tid == 0 && a.energy) {
+        a.energy[2 * sg.wave] = Es;
+        a.energy[2 * sg.wave + 1] = Eu;
+    }
+
+    float2 gs[NJ], gu[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) gs[j] = gu[j] = make_float2(0.f, 0.f);
+    float qsum = 0.f;
+    auto sync = []() { __syncthreads(); };
+    // job j of the segment: lag tau_begin + j/2, sign + (j even) or - (j odd)
+    auto job_tau = [&](int job, bool& active) {
+        const int lag = sg.tau_begin + (job >> 1);
+        const bool neg = (job & 1) != 0;
+        active = job < 2 * (sg.tau_end - sg.tau_begin) && !(neg && lag == 0);
+        return active ? (neg ? -lag : lag) : 0;
+    };
+
+    const int jobs = 2 * (sg.tau_end - sg.tau_begin);
+    for (int j0 = 0; j0 < jobs; j0 += G) {
+        bool active;
+        const int tau = job_tau(j0 + grp, active);
+        const int64_t row = w.grid_off + (int64_t)(T + tau) * M;
+        float2 qa[XP];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float2 v[XP];
+#pragma unroll
+            for (int r = 0; r < XP; ++r) {
+                const int n = l + r * L;
+                const int j = n - tau;
+                const bool in = active && n < N && j >= 0 && j < N;
+                float2 x = cmulc(sv[n], uv[in ? j : 0]);
+                x = in ? x : make_float2(0.f, 0.f);
+                if (h) x = cmul(x, twl(n));
+                v[r] = x;
+            }
+            fft_group<MH, XP, -1>(v, buf, l, twl, sync);
+#pragma unroll
+            for (int q = 0; q < XP; ++q) {
+                const int k = 2 * (l + q * L) + h;
+                const float pw = cabs2(v[q]) * invEE;
+                if constexpr (MODE == 0) {
+                    if (active) {
+                        if (a.mag) a.mag[row + k] = __builtin_amdgcn_sqrtf(pw + a.eps);
+                        if (a.chi) a.chi[row + k] = v[q];
+                    }
+                } else {
+                    const float g = active ? a.grad_mag[row + k] : 0.f;
+                    const float ia = __builtin_amdgcn_rsqf(pw + a.eps);
+                    qsum = fmaf(g * pw, ia, qsum);
+                    v[q] = cscale(v[q], 0.5f * g * invEE * ia);
+                }
+            }
+            if constexpr (MODE == 1) {
+                fft_group<MH, XP, +1>(v, buf, l, twl, sync);
+#pragma unroll
+                for (int q = 0; q < XP; ++q) {
+                    if (h) v[q] = cmulc(v[q], twl(l + q * L));
+                    qa[q] = h ? cadd(qa[q], v[q]) : v[q];
+                }
+            }
+        }
+        if constexpr (MODE == 1) {
+            // Q of every group's row into its buffer, natural order
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < XP; ++q) buf[lds_index(l + q * L)] = qa[q];
+            __syncthreads();
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                const int i = tid + jj * XWGS;
+                if (i >= N) continue;
+                for (int g = 0; g < G; ++g) {
+                    bool act;
+                    const int tg = job_tau(j0 + g, act);
+                    if (!act) continue;
+                    const float2* Q = dyn + g * BUF;
+                    const int jm = i - tg;
+                    if (jm >= 0 && jm < N) gs[jj] = cadd(gs[jj], cmul(uv[jm], Q[lds_index(i)]));
+                    const int jp = i + tg;
+                    if (jp >= 0 && jp < N) gu[jj] = cadd(gu[jj], cmulc(sv[jp], Q[lds_index(jp)]));
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    if constexpr (MODE == 1) {
+        const int64_t base = w.slab_off + (int64_t)(sg.rec - w.seg_begin) * N;
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int i = tid + jj * XWGS;
+            if (i < N) {
+                a.slab_s[base + i] = gs[jj];
+                a.slab_u[base + i] = gu[jj];
+            }
+        }
+        const double qw = wave_allsum((double)qsum);
+        if ((tid & 63) == 0) shd[tid >> 6] = qw;
+        __syncthreads();
+        if (tid == 0) a.part[sg.rec] = (shd[0] + shd[1]) + (shd[2] + shd[3]);
+    }
+}
+
+// dL/d conj(s) and dL/d conj(u): the waveform's slabs in segment order plus
+// the energy terms; one thread per sample, blockIdx.y the waveform.
+__global__ __launch_bounds__(256) void xreduce_kernel(CrossArgs a) {
+    const int b = blockIdx.y;
+    const WaveDesc w = a.waves[b];
+    __shared__ double qs;
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int j = 0; j < w.seg_count; ++j) t += a.part[w.seg_begin + j];
+        qs = t;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= w.n) return;
+    const float Es = a.energy[2 * b], Eu = a.energy[2 * b + 1];
+    float2 gs = make_float2(0.f, 0.f), gu = make_float2(0.f, 0.f);
+    for (int j = 0; j < w.seg_count; ++j) {
+        const int64_t o = w.slab_off + (int64_t)j * w.n + i;
+        gs = cadd(gs, a.slab_s[o]);
+        gu = cadd(gu, a.slab_u[o]);
+    }
+    const float q = (float)qs;
+    const float2 s = a.s[w.s_off + i], u = a.u[w.s_off + i];
+    a.grad_s[w.s_off + i] = cadd(gs, cscale(s, -q / (2.f * Es)));
+    a.grad_u[w.s_off + i] = cadd(gu, cscale(u, -q / (2.f * Eu)));
+}
+
+template <int MODE, int LG>
+hipError_t launch_lg(const CrossArgs& a, int grid, hipStream_t st) {
+    static bool attr = false;
+    const void* k = (const void*)xaf_kernel<MODE, LG>;
+    constexpr int lds = XShape<LG>::lds_bytes();
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((xaf_kernel<MODE, LG>), dim3(grid), dim3(XWGS), (size_t)lds, st, a);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_mode(int lg, const CrossArgs& a, int grid, hipStream_t st) {
+    switch (lg) {
+        case 6: return launch_lg<MODE, 6>(a, grid, st);
+        case 7: return launch_lg<MODE, 7>(a, grid, st);
+        case 8: return launch_lg<MODE, 8>(a, grid, st);
+        case 9: return launch_lg<MODE, 9>(a, grid, st);
+        case 10: return launch_lg<MODE, 10>(a, grid, st);
+        case 11: return launch_lg<MODE, 11>(a, grid, st);
+        case 12: return launch_lg<MODE, 12>(a, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool cross_lg_supported(int lg) { return lg >= 6 && lg <= 12; }
+
+hipError_t launch_cross(int mode, int lg, const CrossArgs& a, int grid, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    return mode == 0 ? launch_mode<0>(lg, a, grid, st) : launch_mode<1>(lg, a, grid, st);
+}
+
+hipError_t launch_cross_reduce(const CrossArgs& a, int batch, int max_n, hipStream_t st) {
+    if (batch <= 0 || max_n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(xreduce_kernel, dim3((unsigned)((max_n + 255) / 256), (unsigned)batch), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace graf

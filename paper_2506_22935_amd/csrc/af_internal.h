@@ -176,6 +176,30 @@ struct ProjectArgs {
 };
 hipError_t launch_project(const ProjectArgs& a, int batch, int max_n, hipStream_t st);
 
+// Cross-ambiguity of s and u (af_cross.hip), over the plan's segments of one
+// size class; slabs and records are laid out like the auto-AF's
+struct CrossArgs {
+    const float2* s;
+    const float2* u;
+    const WaveDesc* waves;
+    const SegDesc* segs;
+    const float2* tw;     // exp(-j 2 pi i / MMAX)
+    int log2_mmax;
+    float eps;
+    float* mag;           // forward: [grid] a, nullable
+    float2* chi;          // forward: [grid] chi_su, nullable
+    float* energy;        // [B][2] = E_s, E_u (written by the segment holding lag 0), nullable in the forward
+    const float* grad_mag;  // backward: [grid] dL/da
+    float2* slab_s;       // backward: per-segment dL/d conj(s) slabs
+    float2* slab_u;       // backward: per-segment dL/d conj(u) slabs
+    double* part;         // backward: per-segment sum of g_a p / a
+    float2* grad_s;       // reduction outputs, packed like s
+    float2* grad_u;
+};
+bool cross_lg_supported(int lg);
+hipError_t launch_cross(int mode, int lg, const CrossArgs& a, int grid, hipStream_t st);
+hipError_t launch_cross_reduce(const CrossArgs& a, int batch, int max_n, hipStream_t st);
+
 // launchers (af_reduce.hip)
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_reduce_adam(const ReduceArgs& a, hipStream_t st);

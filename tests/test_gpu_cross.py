@@ -1,0 +1,134 @@
+"""Cross-ambiguity of two waveforms on the HIP path against the oracle
+(GPU): the magnitude and chi_su grids, and the backward for both inputs, over
+one-waveform and uneven plans (the cross-AF extension of the paper's
+limitations section)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+EPS = 1e-12
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def af():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_22935_amd import af as afmod
+    return afmod
+
+
+def rand_c64(n, seed):
+    rng = np.random.default_rng(seed)
+    return O.to_c64_exact((rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2.0))
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.complex64))).cuda()
+
+
+@pytest.mark.parametrize("n,m,T", [(64, 128, -1), (100, 256, 30), (300, 1024, -1), (1000, 2048, 200),
+                                   (2048, 4096, 40), (4096, 8192, 12), (1, 128, -1)])
+def test_cross_forward(af, n, m, T):
+    say("cross forward", n, m, T)
+    s, u = rand_c64(n, 2000 + n), rand_c64(n, 3000 + n)
+    Tn = n - 1 if T < 0 else T
+    plan = af.Plan([n], [m], [T], eps=EPS)
+    mag, chi, e = plan.cross_forward(to_dev(s), to_dev(u), mag=True, chi=True)
+    torch.cuda.synchronize()
+    Es, Eu = O.energy(s), O.energy(u)
+    assert abs(e[0, 0].item() - Es) <= 1e-5 * Es and abs(e[0, 1].item() - Eu) <= 1e-5 * Eu
+    rows = 2 * Tn + 1
+    bins = None if n * m <= 2048 * 2048 else np.random.default_rng(n).choice(m, 256, replace=False)
+    ref = O.cross_chi(s, u, m, Tn, bins)
+    a_ref = np.sqrt(np.abs(ref) ** 2 / (Es * Eu) + EPS)
+    g_mag = mag.cpu().numpy().reshape(rows, m).astype(np.float64)
+    g_chi = chi.cpu().numpy().reshape(rows, m).astype(np.complex128)
+    if bins is not None:
+        g_mag, g_chi = g_mag[:, bins], g_chi[:, bins]
+    assert np.max(np.abs(g_mag - a_ref)) <= 1e-5
+    scale = np.sqrt(Es * Eu)
+    assert np.max(np.abs(g_chi - ref)) <= 1e-5 * scale
+
+
+def test_cross_with_itself_is_the_af(af):
+    say("cross u = s")
+    n, m = 200, 512
+    s = rand_c64(n, 5)
+    plan = af.Plan([n], [m], eps=EPS)
+    mag, _, _ = plan.cross_forward(to_dev(s), to_dev(s))
+    torch.cuda.synchronize()
+    ref = O.magnitude(O.chi(s, m, n - 1), O.energy(s), EPS)
+    assert np.max(np.abs(mag.cpu().numpy().reshape(ref.shape) - ref)) <= 1e-5
+
+
+@pytest.mark.parametrize("n,m,T", [(64, 128, -1), (100, 256, 30), (300, 1024, -1), (1000, 2048, 100),
+                                   (2048, 4096, 24), (4096, 8192, 6)])
+def test_cross_backward(af, n, m, T):
+    say("cross backward", n, m, T)
+    s, u = rand_c64(n, 4000 + n), rand_c64(n, 5000 + n)
+    Tn = n - 1 if T < 0 else T
+    w = np.random.default_rng(n + 1).standard_normal((2 * Tn + 1, m)).astype(np.float32)
+    plan = af.Plan([n], [m], [T], eps=EPS)
+    gs, gu = plan.cross_backward(to_dev(s), to_dev(u), torch.from_numpy(w.ravel()).cuda())
+    gs2, gu2 = plan.cross_backward(to_dev(s), to_dev(u), torch.from_numpy(w.ravel()).cuda())
+    torch.cuda.synchronize()
+    rs, ru = O.cross_magnitude_backward(s, u, m, Tn, w.astype(np.float64), EPS)
+    for g, r, name in ((gs, rs, "s"), (gu, ru, "u")):
+        err = np.max(np.abs(g.cpu().numpy().astype(np.complex128) - r))
+        assert err <= 1e-4 * np.max(np.abs(r)), (name, err, np.max(np.abs(r)))
+    # deterministic: no atomics
+    assert torch.equal(gs, gs2) and torch.equal(gu, gu2)
+
+
+def test_cross_uneven_batch(af):
+    say("cross uneven")
+    sizes, ms, Ts = [64, 100, 300, 37], [128, 256, 1024, 128], [-1, 20, 60, -1]
+    ss = [rand_c64(n, 6000 + n) for n in sizes]
+    us = [rand_c64(n, 7000 + n) for n in sizes]
+    plan = af.Plan(sizes, ms, Ts, eps=EPS)
+    rows = [2 * (n - 1 if T < 0 else T) + 1 for n, T in zip(sizes, Ts)]
+    ws_ = [np.random.default_rng(i).standard_normal((r, m)).astype(np.float32) for i, (r, m) in
+           enumerate(zip(rows, ms))]
+    sd, ud = to_dev(np.concatenate(ss)), to_dev(np.concatenate(us))
+    mag, _, _ = plan.cross_forward(sd, ud)
+    gs, gu = plan.cross_backward(sd, ud, torch.from_numpy(np.concatenate([w.ravel() for w in ws_])).cuda())
+    torch.cuda.synchronize()
+    mg, gsn, gun = mag.cpu().numpy(), gs.cpu().numpy(), gu.cpu().numpy()
+    go = so = 0
+    for s, u, n, m, T, r, w in zip(ss, us, sizes, ms, Ts, rows, ws_):
+        Tn = n - 1 if T < 0 else T
+        ref = np.sqrt(np.abs(O.cross_chi(s, u, m, Tn)) ** 2 / (O.energy(s) * O.energy(u)) + EPS)
+        assert np.max(np.abs(mg[go:go + r * m].reshape(r, m) - ref)) <= 1e-5, n
+        rs, ru = O.cross_magnitude_backward(s, u, m, Tn, w.astype(np.float64), EPS)
+        assert np.max(np.abs(gsn[so:so + n] - rs)) <= 1e-4 * np.max(np.abs(rs)), n
+        assert np.max(np.abs(gun[so:so + n] - ru)) <= 1e-4 * np.max(np.abs(ru)), n
+        go += r * m
+        so += n
+
+
+def test_cross_rejections(af):
+    from paper_2506_22935_amd import _lib
+    s = to_dev(rand_c64(128, 1))
+    per = af.Plan([128], [128], eps=EPS, periodic=True)
+    with pytest.raises(_lib.AfError) as ei:
+        per.cross_forward(s, s)
+    assert ei.value.code == -2
+    big = af.Plan([5000], [16384], [10], eps=EPS)
+    b = to_dev(rand_c64(5000, 2))
+    with pytest.raises(_lib.AfError) as ei:
+        big.cross_forward(b, b)
+    assert ei.value.code == -2
+    plan = af.Plan([128], [256], eps=EPS)
+    g = torch.zeros(255 * 256, dtype=torch.float32, device="cuda")
+    with pytest.raises(_lib.AfError) as ei:
+        plan.cross_backward(s, s, g, ws=torch.empty(256, dtype=torch.uint8, device="cuda"))
+    assert ei.value.code == -5
