@@ -25,7 +25,8 @@ __all__ = [
     "to_c64_exact", "energy", "chi", "chi_rows", "magnitude", "power",
     "centred_bins", "mainlobe_mask", "isl_weights", "LossParams", "loss_terms",
     "loss_and_grad", "loss_grad_from_chi", "sigmoid", "soft_mainlobe_width", "modulus_variance",
-    "phase_smoothness", "spectral_projection", "cross_chi", "cross_magnitude_backward", "magnitude_backward", "grad_from_upstream", "phase_grad",
+    "phase_smoothness", "spectral_projection", "cross_chi", "cross_magnitude_backward",
+    "multi_scenario_loss_and_grad", "combine_scenario_weights", "magnitude_backward", "grad_from_upstream", "phase_grad",
     "adam_step", "bf16_round", "gelu", "gelu_grad", "mlp_forward",
     "mlp_backward", "psl_db", "chi_rows_fft", "magnitude_backward_fft",
     "chi_circular", "chi_circular_rows", "circular_lag_distance", "circular_mainlobe_mask", "circular_isl_weights",
@@ -131,15 +132,19 @@ class LossParams:
             the -3 dB level of Eq. 20; |tau|_c on the periodic AF)
     Const = var(|s|)                                (L_const of Sec. 5.2)
     Smooth = sum_n |s[n+1] - s[n]|^2 / E            (phase continuity, Sec. 6.2)
+    Cell = sum over every cell of W_cell p          (a per-cell weight grid laid out
+            like the grid: the scenario profile of Eq. 24)
     """
 
     def __init__(self, w_isl=1.0, w_psl=0.0, temp=0.05, h_tau=1, h_k=1,
                  u=None, v=None, eps=1e-12, match=None, w_match=0.0,
-                 w_width=0.0, gamma=10.0, w_const=0.0, w_smooth=0.0):
+                 w_width=0.0, gamma=10.0, w_const=0.0, w_smooth=0.0, cell_w=None, w_cell=0.0):
         self.match = None if match is None else np.asarray(match, dtype=np.float64)
         self.w_match = float(w_match)
         self.w_width, self.gamma = float(w_width), float(gamma)
         self.w_const, self.w_smooth = float(w_const), float(w_smooth)
+        self.cell_w = None if cell_w is None else np.asarray(cell_w, dtype=np.float64)
+        self.w_cell = float(w_cell)
         self.w_isl, self.w_psl, self.temp = float(w_isl), float(w_psl), float(temp)
         self.h_tau, self.h_k = int(h_tau), int(h_k)
         self.u = None if u is None else np.asarray(u, dtype=np.float64)
@@ -181,8 +186,10 @@ def _loss_terms_on(c, E, params, side, W, lagd):
     soft = mx + params.temp * math.log(S)
     match = float(np.sum((p - params.match) ** 2)) if params.match is not None else 0.0
     width = soft_mainlobe_width(p, lagd, params.gamma)
-    loss = params.w_isl * isl + params.w_psl * soft + params.w_match * match + params.w_width * width
-    return dict(loss=loss, isl=isl, softpsl=soft, match=match, width=width, psl_db=psl_db(p, side),
+    cell = float(np.sum(params.cell_w * p)) if params.cell_w is not None else 0.0
+    loss = (params.w_isl * isl + params.w_psl * soft + params.w_match * match + params.w_width * width +
+            params.w_cell * cell)
+    return dict(loss=loss, isl=isl, softpsl=soft, match=match, width=width, cell=cell, psl_db=psl_db(p, side),
                 p=p, a=a, side=side, W=W, lagd=lagd, lse_max=mx, lse_sum=S)
 
 
@@ -276,6 +283,10 @@ def _cell_upstream(t, c, E, params):
         d = p - params.match
         coef = coef + params.w_match * 2.0 * d / (E * E)
         dLdE += params.w_match * float(np.sum(2.0 * d * (-2.0 * p / E)))
+    if params.cell_w is not None and params.w_cell != 0.0:
+        # d/d conj(chi) of W p = W chi / E^2; dp/dE = -2 p / E
+        coef = coef + params.w_cell * params.cell_w / (E * E)
+        dLdE += params.w_cell * float(np.sum(params.cell_w * (-2.0 * p / E)))
     if params.w_width != 0.0:
         # Eq. 21: dWidth/dp(tau, 0) = |tau| gamma sigma'(z_tau); the origin
         # cell also carries -gamma/2 sum |tau| sigma'(z_tau)
@@ -461,6 +472,30 @@ def experiment_loss_and_grad(s, m, lam, alpha=2000.0, h_tau=0, h_k=0, periodic=F
     V, gv = spectral_variance(s)
     return dict(loss=psl + lam * alpha * V, psl=psl, cell=cell, spec_var=V, g=gp + lam * alpha * gv,
                 g_psl=gp, g_spec=gv, chi=c, E=E, a=magnitude(c, E, eps), side=side)
+
+
+# ----------------------------------------------------------------------------
+# multi-scenario loss (Eq. 24): L_multi = sum_i lambda_i L_i(chi_s, scenario_i)
+# ----------------------------------------------------------------------------
+
+def multi_scenario_loss_and_grad(s, m, max_lag, scenarios, lambdas, periodic=False):
+    """Eq. 24 as written: each scenario's loss (its own LossParams) on the
+    same AF, weighted by lambda_i and summed, with the gradient likewise."""
+    total, g = 0.0, None
+    for params, lam in zip(scenarios, lambdas):
+        t = loss_and_grad_circular(s, params) if periodic else loss_and_grad(s, m, max_lag, params)
+        total += float(lam) * t["loss"]
+        g = float(lam) * t["g"] if g is None else g + float(lam) * t["g"]
+    return total, g
+
+
+def combine_scenario_weights(grids, lambdas):
+    """sum_i lambda_i W_i of per-cell weight grids (the linear scenario terms
+    of Eq. 24 folded into one grid)."""
+    out = np.zeros_like(np.asarray(grids[0], dtype=np.float64))
+    for w, lam in zip(grids, lambdas):
+        out = out + float(lam) * np.asarray(w, dtype=np.float64)
+    return out
 
 
 # ----------------------------------------------------------------------------

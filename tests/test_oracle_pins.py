@@ -803,3 +803,40 @@ def test_cross_magnitude_backward_finite_differences():
     ga, gb = O.cross_magnitude_backward(s, s, m, T, w, eps)
     ref = O.magnitude_backward(s, m, T, w, eps)
     assert np.max(np.abs(ga + gb - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+# ---- multi-scenario loss (Eq. 24) and per-cell weight grids
+
+def test_cell_weights_reduce_to_weighted_isl():
+    # a weight grid equal to the ISL weights (zero on the mainlobe) is the ISL
+    n, m, T = 24, 64, 23
+    s = rand_complex(n, 60)
+    W = O.isl_weights(n, m, T, 1, 1)
+    a = O.loss_and_grad(s, m, T, O.LossParams(w_isl=1.0))
+    b = O.loss_and_grad(s, m, T, O.LossParams(w_isl=0.0, cell_w=W, w_cell=1.0))
+    assert abs(a["loss"] - b["loss"]) < 1e-12 * a["loss"]
+    assert np.max(np.abs(a["g"] - b["g"])) < 1e-12 * np.max(np.abs(a["g"]))
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_multi_scenario_is_one_pass_with_combined_weights(periodic):
+    # Eq. 24 with weight-grid scenarios (target profiles), evaluated scenario
+    # by scenario, equals one loss with the combined grid; finite differences
+    n, m = 32, 64
+    T = n - 1
+    s = rand_complex(n, 61)
+    rows = n if periodic else 2 * T + 1
+    cols = n if periodic else m
+    rng = np.random.default_rng(62)
+    grids = [rng.uniform(0, 1, (rows, cols)) * (rng.uniform(0, 1, (rows, 1)) < 0.5) for _ in range(3)]
+    lams = [0.5, 2.0, 1.25]
+    scen = [O.LossParams(w_isl=0.0, cell_w=w, w_cell=1.0, w_smooth=0.1 * i) for i, w in enumerate(grids)]
+    L, g = O.multi_scenario_loss_and_grad(s, m, T, scen, lams, periodic=periodic)
+    one = O.LossParams(w_isl=0.0, cell_w=O.combine_scenario_weights(grids, lams), w_cell=1.0,
+                       w_smooth=0.1 * (0 * 0.5 + 1 * 2.0 + 2 * 1.25))
+    t = O.loss_and_grad_circular(s, one) if periodic else O.loss_and_grad(s, m, T, one)
+    assert abs(L - t["loss"]) < 1e-11 * abs(L)
+    assert np.max(np.abs(g - t["g"])) < 1e-11 * np.max(np.abs(g))
+    f = (lambda x: O.multi_scenario_loss_and_grad(x, m, T, scen, lams, periodic=periodic)[0])
+    gf = _fd_grad(f, s)
+    assert np.max(np.abs(g - gf)) < 1e-6 * np.max(np.abs(gf))
