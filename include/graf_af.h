@@ -122,7 +122,12 @@ typedef struct af_plan af_plan;
  * Sec. 5.2, population variance; its gradient is taken as 0 at s[n] = 0),
  * w_smooth a phase-continuity term (Sec. 6.2), sum_{n < N-1} |s[n+1] -
  * s[n]|^2 / E, which for a unit-modulus code is (2/N) sum (1 - cos of the
- * phase steps); both combine with every other term.  Zero-initialise the
+ * phase steps); both combine with every other term.  w_cell weights
+ * sum over every cell of cell_w * p, with cell_w a device float grid of
+ * per-cell weights laid out like the a grid (a target profile; the
+ * multi-scenario loss of Eq. 24 over such profiles is one pass with the
+ * combined grid, see af_scenario_combine); like L_match it needs split
+ * classes and does not combine with the soft PSL.  Zero-initialise the
  * struct: psl_hard = 0 and zero weights for the terms after it give the
  * soft-PSL losses above. */
 typedef struct {
@@ -138,6 +143,8 @@ typedef struct {
     float gamma;               /* its sharpness, >= 0 */
     float w_const;             /* weight of var(|s|) */
     float w_smooth;            /* weight of sum |s[n+1] - s[n]|^2 / E */
+    const float* cell_w;       /* device float per-cell weight grid, laid out like the a grid */
+    float w_cell;              /* weight of sum cell_w * p */
 } af_loss_params;
 
 /* Adam settings for af_optim_step (Kingma & Ba; eps outside the square root). */
@@ -223,6 +230,15 @@ af_status af_spectral_variance(const af_plan* plan, const void* s, float* value,
  * projection (any N).  s, out: device complex64 packed like the plan's input;
  * out may equal s (in place).  unit must be 0 or 1; mask NULL with unit 0 copies. */
 af_status af_project(const af_plan* plan, const void* s, const float* mask, int32_t unit, void* out, void* stream);
+
+/* Multi-scenario weights (Eq. 24): out = sum_s lambdas[s] * grids[s], in
+ * scenario order, over the plan's grid cells.  grids: device float
+ * [n_scen][cells] (each laid out like the a grids); lambdas: device
+ * float[n_scen]; out: device float[cells].  A loss that is linear in the
+ * power grid per scenario (cell-weighted ISL, target profiles) then runs as
+ * one pass with cell_w = out, whatever n_scen. */
+af_status af_scenario_combine(const af_plan* plan, int32_t n_scen, const float* grids, const float* lambdas,
+                              float* out, void* stream);
 
 /* Cross-ambiguity of two waveforms (the cross-AF / MIMO extension that the
  * limitations section names): per waveform b of the plan, s and u are

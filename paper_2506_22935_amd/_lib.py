@@ -35,7 +35,8 @@ class AfLossParams(ctypes.Structure):
     _fields_ = [("w_isl", ctypes.c_float), ("w_psl", ctypes.c_float), ("psl_temp", ctypes.c_float),
                 ("band_w", ctypes.c_void_p), ("psl_hard", ctypes.c_int32), ("w_spec", ctypes.c_float),
                 ("match_target", ctypes.c_void_p), ("w_match", ctypes.c_float), ("w_width", ctypes.c_float),
-                ("gamma", ctypes.c_float), ("w_const", ctypes.c_float), ("w_smooth", ctypes.c_float)]
+                ("gamma", ctypes.c_float), ("w_const", ctypes.c_float), ("w_smooth", ctypes.c_float),
+                ("cell_w", ctypes.c_void_p), ("w_cell", ctypes.c_float)]
 
 
 class AfAdamParams(ctypes.Structure):
@@ -67,6 +68,7 @@ SIGNATURES = {
     "af_phase_to_signal": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "af_spectral_variance": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "af_project": (ctypes.c_int, [_VP, _VP, _VP, _I32, _VP, _VP]),
+    "af_scenario_combine": (ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _VP]),
     "af_cross_workspace_size": (ctypes.c_int, [_VP, ctypes.POINTER(_SZ)]),
     "af_cross_forward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "af_cross_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),

@@ -159,33 +159,37 @@ class Plan:
 
     @staticmethod
     def loss_params(w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, psl_hard=False, w_spec=0.0, match=None,
-                    w_match=0.0, w_width=0.0, gamma=10.0, w_const=0.0, w_smooth=0.0):
+                    w_match=0.0, w_width=0.0, gamma=10.0, w_const=0.0, w_smooth=0.0, cell_w=None, w_cell=0.0):
         if band_w is not None:
             _need(band_w, torch.float32, "band_w")
         if match is not None:
             _need(match, torch.float32, "match")
+        if cell_w is not None:
+            _need(cell_w, torch.float32, "cell_w")
         p = L.AfLossParams(w_isl=float(w_isl), w_psl=float(w_psl), psl_temp=float(temp),
                            band_w=None if band_w is None else band_w.data_ptr(), psl_hard=1 if psl_hard else 0,
                            w_spec=float(w_spec), match_target=None if match is None else match.data_ptr(),
                            w_match=float(w_match), w_width=float(w_width), gamma=float(gamma),
-                           w_const=float(w_const), w_smooth=float(w_smooth))
-        p._keep = (band_w, match)  # keep the tensors alive while the struct is in use
+                           w_const=float(w_const), w_smooth=float(w_smooth),
+                           cell_w=None if cell_w is None else cell_w.data_ptr(), w_cell=float(w_cell))
+        p._keep = (band_w, match, cell_w)  # keep the tensors alive while the struct is in use
         return p
 
     def loss(self, s, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, grad=True, mag=False, ws=None,
              out_terms=None, out_grad=None, psl_hard=False, w_spec=0.0, match=None, w_match=0.0, w_width=0.0,
-             gamma=10.0, w_const=0.0, w_smooth=0.0):
+             gamma=10.0, w_const=0.0, w_smooth=0.0, cell_w=None, w_cell=0.0):
         """Built-in loss.  Returns (terms float32[B,4] = (L, ISL, PSL term, E),
         dL/d conj(s) or None, a grids or None).  psl_hard: the hard PSL
         (power ratio) instead of the soft one; w_spec: weight of the spectral
         variance (the experiment loss: w_psl=1, psl_hard=True,
         w_spec=lambda*alpha); match, w_match: L_match against a target power
         grid laid out like the a grid; w_width, gamma: the soft mainlobe
-        width; w_const: var(|s|); w_smooth: the phase-smoothness term."""
+        width; w_const: var(|s|); w_smooth: the phase-smoothness term;
+        cell_w, w_cell: a per-cell weight grid laid out like the a grid."""
         _need(s, torch.complex64, "s")
         ws = self.workspace if ws is None else ws
         lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match, w_width, gamma,
-                              w_const, w_smooth)
+                              w_const, w_smooth, cell_w, w_cell)
         t = out_terms if out_terms is not None else torch.empty(self.batch, 4, dtype=torch.float32, device=_DEV)
         g = None
         if grad:
@@ -198,22 +202,22 @@ class Plan:
 
     def loss_stage(self, stage, s, terms, grad, mag, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, ws=None,
                    psl_hard=False, w_spec=0.0, match=None, w_match=0.0, w_width=0.0, gamma=10.0, w_const=0.0,
-                   w_smooth=0.0):
+                   w_smooth=0.0, cell_w=None, w_cell=0.0):
         """Run one stage (0 forward, 1 backward and the per-waveform terms, 2
         reduce) of loss(); for timing."""
         ws = self.workspace if ws is None else ws
         lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match, w_width, gamma,
-                              w_const, w_smooth)
+                              w_const, w_smooth, cell_w, w_cell)
         L.check("af_loss_stage", L.lib().af_loss_stage(self._h, int(stage), _ptr(s), ctypes.byref(lp), _ptr(terms),
                                                        _ptr(mag), _ptr(grad), _ptr(ws), ws.numel(), _stream()))
 
     def optim_step(self, state, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, lr=0.01, betas=(0.9, 0.999),
                    eps=1e-8, ws=None, terms=None, psl_hard=False, w_spec=0.0, match=None, w_match=0.0,
-                   w_width=0.0, gamma=10.0, w_const=0.0, w_smooth=0.0):
+                   w_width=0.0, gamma=10.0, w_const=0.0, w_smooth=0.0, cell_w=None, w_cell=0.0):
         """One Adam step on the phases held in `state` (see PhaseState)."""
         ws = self.workspace if ws is None else ws
         lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match, w_width, gamma,
-                              w_const, w_smooth)
+                              w_const, w_smooth, cell_w, w_cell)
         ad = L.AfAdamParams(lr=float(lr), beta1=float(betas[0]), beta2=float(betas[1]), eps=float(eps))
         L.check("af_optim_step", L.lib().af_optim_step(
             self._h, _ptr(state.phi), _ptr(state.m), _ptr(state.v), _ptr(state.s), _ptr(state.step),
@@ -244,6 +248,19 @@ class Plan:
                                                  _stream()))
         return out
 
+
+    def scenario_combine(self, grids, lambdas):
+        """sum_s lambdas[s] grids[s] over the plan's cells (Eq. 24's linear
+        scenario terms as one weight grid): grids float32 [S, cells],
+        lambdas float32 [S] (device).  Returns float32 [cells]."""
+        _need(grids, torch.float32, "grids")
+        _need(lambdas, torch.float32, "lambdas")
+        if grids.dim() != 2 or grids.shape[1] != self.total_cells or lambdas.numel() != grids.shape[0]:
+            raise ValueError("grids must be [S, %d] with S lambdas" % self.total_cells)
+        out = torch.empty(self.total_cells, dtype=torch.float32, device=_DEV)
+        L.check("af_scenario_combine", L.lib().af_scenario_combine(self._h, grids.shape[0], _ptr(grids),
+                                                                   _ptr(lambdas), _ptr(out), _stream()))
+        return out
 
     def cross_workspace(self):
         """Device workspace for cross_backward (allocated once per plan)."""

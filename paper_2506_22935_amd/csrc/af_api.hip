@@ -458,9 +458,10 @@ af_status check_common(const af_plan* p, const void* s, void* ws, size_t ws_byte
 }
 
 // terms of the extended epilogue copy (split variants, forward and fused
-// ISL passes): the hard PSL, L_match, the soft mainlobe width
+// ISL passes): the hard PSL, L_match, the soft mainlobe width, cell weights
 bool extended_terms(const af_loss_params* lp) {
-    return (lp->psl_hard != 0 && lp->w_psl != 0.f) || lp->w_match != 0.f || lp->w_width != 0.f;
+    return (lp->psl_hard != 0 && lp->w_psl != 0.f) || lp->w_match != 0.f || lp->w_width != 0.f ||
+           lp->w_cell != 0.f;
 }
 
 af_status check_loss(const af_plan* p, const af_loss_params* lp) {
@@ -470,10 +471,13 @@ af_status check_loss(const af_plan* p, const af_loss_params* lp) {
     if (lp->psl_hard != 0 && lp->psl_hard != 1) return AF_ERR_INVALID_ARG;
     if (!std::isfinite(lp->w_match) || (lp->w_match != 0.f && !lp->match_target)) return AF_ERR_INVALID_ARG;
     if (!std::isfinite(lp->w_width) || !std::isfinite(lp->gamma) || !(lp->gamma >= 0.f) ||
-        !std::isfinite(lp->w_const) || !std::isfinite(lp->w_smooth))
+        !std::isfinite(lp->w_const) || !std::isfinite(lp->w_smooth) || !std::isfinite(lp->w_cell) ||
+        (lp->w_cell != 0.f && !lp->cell_w) || !aligned(lp->cell_w, 4) || !aligned(lp->match_target, 4))
         return AF_ERR_INVALID_ARG;
-    // L_match and the width run in the forward and fused ISL passes: not with the soft PSL
-    if ((lp->w_match != 0.f || lp->w_width != 0.f) && lp->w_psl != 0.f && !lp->psl_hard) return AF_ERR_UNSUPPORTED;
+    // L_match, the width and the cell weights run in the forward and fused
+    // ISL passes: not with the soft PSL
+    if ((lp->w_match != 0.f || lp->w_width != 0.f || lp->w_cell != 0.f) && lp->w_psl != 0.f && !lp->psl_hard)
+        return AF_ERR_UNSUPPORTED;
     // the hard PSL, L_match and the width run in the split variants (M <= 8192)
     if (extended_terms(lp))
         for (const af_plan::Class& k : p->classes)
@@ -497,7 +501,7 @@ bool needs_extra(const af_loss_params* lp) {
 // the mainlobe cells) and variants that split the two half transforms.
 bool fused_loss_ok(const af_plan* p, const af_loss_params* lp) {
     if (p->loss_passes_opt == 1 || lp->w_psl == 0.f || lp->psl_hard || lp->band_w != nullptr || lp->w_match != 0.f ||
-        lp->w_width != 0.f)
+        lp->w_width != 0.f || lp->w_cell != 0.f)
         return false;
     const float inv_t2 = 1.4426950408889634f / lp->psl_temp;
     if (!(std::sqrt(1.f + p->eps) * inv_t2 < 100.f)) return false;
@@ -525,6 +529,10 @@ AfArgs loss_args(const af_plan* p, const void* s, const af_loss_params* lp, floa
     }
     a.w_width = lp->w_width;
     a.gamma = lp->gamma;
+    if (lp->w_cell != 0.f) {
+        a.cell_w = lp->cell_w;
+        a.w_cell = lp->w_cell;
+    }
     return a;
 }
 
@@ -532,7 +540,8 @@ AfArgs loss_args(const af_plan* p, const void* s, const af_loss_params* lp, floa
 // pass alone serves: the hard PSL's gradient lives on one cell, and the
 // waveform-only terms take none through the AF.
 bool grid_gradient(const af_loss_params* lp) {
-    return lp->w_isl != 0.f || (lp->w_psl != 0.f && !lp->psl_hard) || lp->w_match != 0.f || lp->w_width != 0.f;
+    return lp->w_isl != 0.f || (lp->w_psl != 0.f && !lp->psl_hard) || lp->w_match != 0.f || lp->w_width != 0.f ||
+           lp->w_cell != 0.f;
 }
 // Do the passes of this loss leave gradient slabs (else the reduction reads none)?
 bool loss_writes_slabs(const af_loss_params* lp, bool want_grad) { return want_grad && grid_gradient(lp); }
@@ -600,7 +609,7 @@ ReduceArgs loss_reduce_args(const af_plan* p, const void* s, const af_loss_param
     r.w_spec = lp->w_spec;
     r.w_const = lp->w_const;
     r.w_smooth = lp->w_smooth;
-    r.ext_cells = ((lp->match_target && lp->w_match != 0.f) || lp->w_width != 0.f) ? 1 : 0;
+    r.ext_cells = ((lp->match_target && lp->w_match != 0.f) || lp->w_width != 0.f || lp->w_cell != 0.f) ? 1 : 0;
     r.vals = v.vals;
     r.g_extra = (want_grad && needs_extra(lp)) ? v.extra : nullptr;
     return r;
@@ -827,6 +836,16 @@ af_status af_project(const af_plan* p, const void* s, const float* mask, int32_t
     a.unit = unit;
     a.out = (float2*)out;
     return graf::launch_project(a, p->batch, p->max_n, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
+}
+
+af_status af_scenario_combine(const af_plan* p, int32_t n_scen, const float* grids, const float* lambdas, float* out,
+                              void* stream) {
+    if (!p || n_scen < 1 || !grids || !lambdas || !out || !aligned(grids, 4) || !aligned(lambdas, 4) ||
+        !aligned(out, 4))
+        return AF_ERR_INVALID_ARG;
+    return graf::launch_combine(grids, lambdas, n_scen, p->cells, out, (hipStream_t)stream) == hipSuccess
+               ? AF_OK
+               : AF_ERR_HIP;
 }
 
 // ------------------------------------------------------- cross-AF --

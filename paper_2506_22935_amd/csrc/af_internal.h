@@ -44,6 +44,7 @@ struct Part {
     double dle;
     double ext;    // weighted cell-wise extension terms over the segment's cells:
                    // w_match (p - p_target)^2 + w_width |tau| sigma(gamma (p(tau, 0) - 1/2))
+                   // + w_cell W_cell p
     float lse_m;
     float psl_p;
     int psl_i;
@@ -91,6 +92,8 @@ struct AfArgs {
     const float* match_t; // target power grid of L_match (MODE_FWD / MODE_FUSED_EXT), nullable
     float w_match;
     float w_width, gamma; // soft mainlobe width on the k = 0 column (MODE_FWD / MODE_FUSED_EXT)
+    const float* cell_w;  // per-cell weight grid (MODE_FWD / MODE_FUSED_EXT), nullable
+    float w_cell;
 };
 
 // The slab reduction runs 256-thread blocks over (256 >> sg_log) samples of
@@ -175,6 +178,9 @@ struct ProjectArgs {
     float2* out;
 };
 hipError_t launch_project(const ProjectArgs& a, int batch, int max_n, hipStream_t st);
+// out[i] = sum_s lambdas[s] grids[s * cells + i], in scenario order
+hipError_t launch_combine(const float* grids, const float* lambdas, int n_scen, int64_t cells, float* out,
+                          hipStream_t st);
 
 // Cross-ambiguity of s and u (af_cross.hip), over the plan's segments of one
 // size class; slabs and records are laid out like the auto-AF's

@@ -1,5 +1,7 @@
 // Gradient reduction, fused Adam on phases and small elementwise kernels,
 // plus the launch helpers for every kernel of the library.
+#include <algorithm>
+
 #include "af_reduce.h"
 
 namespace graf {
@@ -403,6 +405,24 @@ hipError_t launch_project(const ProjectArgs& a, int batch, int max_n, hipStream_
         attr = true;
     }
     hipLaunchKernelGGL(project_kernel, dim3(batch), dim3(256), (size_t)lds, st, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void combine_kernel(const float* __restrict__ grids,
+                                                     const float* __restrict__ lambdas, int n_scen, int64_t cells,
+                                                     float* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < cells; i += (int64_t)gridDim.x * 256) {
+        float acc = 0.f;
+        for (int s = 0; s < n_scen; ++s) acc = fmaf(lambdas[s], grids[(int64_t)s * cells + i], acc);
+        out[i] = acc;
+    }
+}
+
+hipError_t launch_combine(const float* grids, const float* lambdas, int n_scen, int64_t cells, float* out,
+                          hipStream_t st) {
+    if (cells <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((cells + 255) / 256, 8192);
+    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, st, grids, lambdas, n_scen, cells, out);
     return hipGetLastError();
 }
 

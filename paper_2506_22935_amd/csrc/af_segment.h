@@ -426,14 +426,16 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
     float2* const mlb = reinterpret_cast<float2*>(scratch);
     double isl = 0.0, ls = 0.0, dle = 0.0, mt = 0.0;
-    // L_match against a target power grid, the soft mainlobe width and the
-    // hard-PSL maximum (forward and fused ISL modes; the extended epilogue
-    // copy; split variants only: the halves-in-turn variant keeps its registers)
+    // L_match against a target power grid, the soft mainlobe width, a
+    // per-cell weight grid and the hard-PSL maximum (forward and fused ISL
+    // modes; the extended epilogue copy; split variants only: the
+    // halves-in-turn variant keeps its registers)
     constexpr bool EXT_OK = SPLIT && EXT_MODE<MODE, EXTK>();
     const bool match = EXT_OK && a.match_t != nullptr;
     const bool width = EXT_OK && a.w_width != 0.f;
+    const bool cellw = EXT_OK && a.cell_w != nullptr;
     const bool hard_rt = EXT_OK && a.psl_hard != 0;
-    const bool ext_rt = match || width || hard_rt;
+    const bool ext_rt = match || width || cellw || hard_rt;
     // hard PSL: this lane's largest sidelobe power and its cell (tau >= 0 row)
     float hp = -1.f;
     int hi = 0;
@@ -575,6 +577,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             float isl_f = 0.f, dle_f = 0.f, mloc = -INFINITY, sl_f = 0.f;
             float mt_f = 0.f, dlm_f = 0.f;  // L_match: both cells of the pair explicitly
             float wd_f = 0.f;               // soft mainlobe width
+            float cw_f = 0.f;               // per-cell weights: sum W p
             float avs[(MODE == MODE_FWD) ? P : 1];
             // One straight-line copy per loss configuration (shift rule,
             // banded weights, mainlobe complement, soft-PSL on/off): every
@@ -660,6 +663,16 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                             const float u = active ? mult * a.w_width * ld * a.gamma * sg * (1.f - sg) : 0.f;
                             cm += u * invE2;
                             dlm_f = fmaf(-2.f * u * pw, invE, dlm_f);
+                        }
+                    }
+                    if (EXT && cellw) {
+                        // W p on both cells of the pair, each with its own weight
+                        const float wp = active ? a.cell_w[row_p + k] : 0.f;
+                        const float wn = (active && two_rows) ? a.cell_w[row_n + kn] : 0.f;
+                        cw_f = fmaf(wp + wn, pw, cw_f);
+                        if constexpr (NEEDS_INV) {
+                            cm += a.w_cell * (wp + wn) * invE2;
+                            dlm_f = fmaf(-2.f * a.w_cell * (wp + wn) * pw, invE, dlm_f);
                         }
                     }
                     if (EXT && match) {
@@ -765,7 +778,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             }
             isl += (double)(mult * isl_f);
             dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f + dlm_f);
-            if (match || width) mt += (double)fmaf(a.w_match, mt_f, a.w_width * wd_f);
+            if (match || width || cellw)
+                mt += (double)fmaf(a.w_match, mt_f, fmaf(a.w_width, wd_f, a.w_cell * cw_f));
             if (FWD_SUMS && want_lse && (lse_fixed || MODE == MODE_LOSS)) {
                 ls += (double)(mult * sl_f);
             } else if (MODE == MODE_FWD && want_lse && mloc > -INFINITY) {
@@ -940,7 +954,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     }
     isl = (double)wave_sum((float)isl);
     if (MODE != MODE_FWD) dle = (double)wave_sum((float)dle);
-    if (match || width) mt = (double)wave_sum((float)mt);
+    if (match || width || cellw) mt = (double)wave_sum((float)mt);
     // hard PSL: the wavefront's largest power, then its smallest cell index
     const bool hard = hard_rt;
     if (hard) {

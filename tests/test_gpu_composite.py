@@ -249,3 +249,46 @@ def test_new_terms_rejections(af):
     with pytest.raises(_lib.AfError) as ei:
         big.project(to_dev(rand_c64(5000, 2)), torch.ones(5000, device="cuda"))  # mask beyond N = 4096
     assert ei.value.code == -2
+
+
+@pytest.mark.parametrize("n,m,periodic", [(100, 256, False), (128, 128, True), (1000, 2048, False)])
+def test_multi_scenario_weights(af, n, m, periodic):
+    # Eq. 24 over three target-profile scenarios: the GPU combines the grids
+    # once and runs one pass; the oracle sums the scenario losses one by one
+    say("multi-scenario", n, m, periodic)
+    s = rand_c64(n, 1700 + n)
+    T = n - 1
+    rows, cols = (n, n) if periodic else (2 * T + 1, m)
+    rng = np.random.default_rng(n)
+    grids = [(rng.uniform(0, 1, (rows, cols)) * (rng.uniform(0, 1, (rows, 1)) < 0.4)).astype(np.float32)
+             for _ in range(3)]
+    lams = np.array([0.5, 2.0, 1.25], dtype=np.float32)
+    plan = af.Plan([n], [m], eps=EPS, periodic=periodic)
+    comb = plan.scenario_combine(torch.from_numpy(np.stack([g.ravel() for g in grids])).cuda(),
+                                 torch.from_numpy(lams).cuda())
+    terms, g, _ = plan.loss(to_dev(s), w_isl=0.0, cell_w=comb, w_cell=1.0)
+    terms_h, g_h, _ = plan.loss(to_dev(s), w_isl=0.0, w_psl=1.0, psl_hard=True, cell_w=comb, w_cell=1.0)
+    torch.cuda.synchronize()
+    ref_comb = O.combine_scenario_weights([g_.astype(np.float64) for g_ in grids], lams.astype(np.float64))
+    assert np.max(np.abs(comb.cpu().numpy().reshape(rows, cols) - ref_comb)) <= 1e-6 * np.max(ref_comb)
+    scen = [O.LossParams(w_isl=0.0, eps=EPS, cell_w=g_.astype(np.float64), w_cell=1.0) for g_ in grids]
+    L, gref = O.multi_scenario_loss_and_grad(s, m, T, scen, lams.astype(np.float64), periodic=periodic)
+    assert abs(terms[0, 0].item() - L) <= 1e-4 * L, (terms[0, 0].item(), L)
+    check_grad(g.cpu().numpy().astype(np.complex128), gref, "multi-scenario")
+    # with the hard PSL of the experiment loss on top
+    ex = O.experiment_loss_and_grad(s, m, 0.0, h_tau=1, h_k=1, periodic=periodic, eps=EPS)
+    assert abs(terms_h[0, 0].item() - (L + ex["psl"])) <= 1e-4 * (L + ex["psl"])
+    check_grad(g_h.cpu().numpy().astype(np.complex128), gref + ex["g_psl"], "multi-scenario + hard PSL")
+
+
+def test_cell_weights_rejections(af):
+    from paper_2506_22935_amd import _lib
+    plan = af.Plan([128], [256], eps=EPS)
+    s = to_dev(rand_c64(128, 3))
+    w = torch.ones(255 * 256, dtype=torch.float32, device="cuda")
+    with pytest.raises(_lib.AfError) as ei:
+        plan.loss(s, w_isl=0.0, w_psl=1.0, cell_w=w, w_cell=1.0)  # with the soft PSL
+    assert ei.value.code == -2
+    with pytest.raises(_lib.AfError) as ei:
+        plan.loss(s, w_isl=0.0, w_cell=1.0)  # weight without a grid
+    assert ei.value.code == -1
