@@ -435,7 +435,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const bool width = EXT_OK && a.w_width != 0.f;
     const bool cellw = EXT_OK && a.cell_w != nullptr;
     const bool hard_rt = EXT_OK && a.psl_hard != 0;
-    const bool ext_rt = match || width || cellw || hard_rt;
+    const bool ext_full = match || width || cellw;  // beyond the hard-PSL maximum
+    const bool ext_rt = ext_full || hard_rt;
     // hard PSL: this lane's largest sidelobe power and its cell (tau >= 0 row)
     float hp = -1.f;
     int hi = 0;
@@ -584,15 +585,16 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // condition left inside is per lane and becomes a select.
             // MAIN: the lag may hold mainlobe cells (tau <= h_tau); without
             // them every mainlobe test is compiled out
-            // EXT: the rarely used extensions (hard-PSL maximum, L_match) in one
-            // copy, each behind a uniform runtime test
+            // EXT: the rarely used extensions, each behind a uniform runtime
+            // test: 1 the hard-PSL maximum alone, 2 also L_match, the mainlobe
+            // width and the cell weights
             auto epilogue = [&](auto fixed_c, auto banded_c, auto compl_c, auto psl_c, auto main_c, auto ext_c) {
                 constexpr bool FIXED = decltype(fixed_c)::value;
                 constexpr bool BANDED = decltype(banded_c)::value;
                 constexpr bool COMPL = decltype(compl_c)::value;
                 constexpr bool PSL = decltype(psl_c)::value;
                 constexpr bool MAIN = decltype(main_c)::value;
-                constexpr bool EXT = decltype(ext_c)::value;
+                constexpr int EXT = decltype(ext_c)::value;  // 0, 1: hard PSL only, 2: every extension
                 const float c_main = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
@@ -610,7 +612,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     const float av = NEED_IA ? xa * ia : __builtin_amdgcn_sqrtf(xa);
                     const bool main_cell = MAIN && active && main_tau && kc <= w.h_k;
                     const bool sd = active && !main_cell;
-                    if (EXT && hard_rt) {
+                    if (EXT >= 1 && hard_rt) {
                         // largest power, then the smallest cell index
                         const int ci = tau * RL + k;
                         const bool better = sd && (pw > hp || (pw == hp && ci < hi));
@@ -655,7 +657,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     // powers) weigh |tau| sigma(gamma (p - 1/2)), since
                     // p(0, 0) = 1 for every waveform; upstream
                     // |tau| gamma sigma' per cell, energy term -2 p / E
-                    if (EXT && width && k == 0) {
+                    if (EXT == 2 && width && k == 0) {
                         const float ld = (float)(CIRC ? min(tau, N - tau) : tau);
                         const float sg = 1.f / (1.f + fast_exp2(-kLog2e * a.gamma * (pw - 0.5f)));
                         wd_f += active ? mult * ld * sg : 0.f;
@@ -665,7 +667,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                             dlm_f = fmaf(-2.f * u * pw, invE, dlm_f);
                         }
                     }
-                    if (EXT && cellw) {
+                    if (EXT == 2 && cellw) {
                         // W p on both cells of the pair, each with its own weight
                         const float wp = active ? a.cell_w[row_p + k] : 0.f;
                         const float wn = (active && two_rows) ? a.cell_w[row_n + kn] : 0.f;
@@ -675,7 +677,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                             dlm_f = fmaf(-2.f * a.w_cell * (wp + wn) * pw, invE, dlm_f);
                         }
                     }
-                    if (EXT && match) {
+                    if (EXT == 2 && match) {
                         // target rows (the -tau row is read only with a distinct
                         // partner) through plain per-lane pointers: the lag, and
                         // so the row, differs between the lane groups of a wavefront
@@ -740,9 +742,16 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             };
             // the hot fused passes also get a copy without mainlobe logic for
             // the lags beyond the mainlobe (tau > h_tau: all but a few)
-            // the extended copy exists in split variants only
+            // the extended copies exist in split variants only: the hard-PSL
+            // maximum alone (the experiment loss's forward pass) keeps a copy
+            // without the other extensions' per-cell tests
             auto ext_copy = [&]() {
-                if constexpr (SPLIT) by_loss(T_{}, F_{}, T_{}, T_{});
+                if constexpr (SPLIT) {
+                    if (ext_full)
+                        by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 2>{});
+                    else
+                        by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 1>{});
+                }
             };
             if constexpr (MODE == MODE_FWD) {
                 if (!want_lse && ext_rt)
