@@ -49,6 +49,30 @@ class AFLoss(torch.autograd.Function):
         return 2.0 * ctx.g * grad_loss[ctx.owner], None, None, None, None, None
 
 
+class CrossAFMagnitude(torch.autograd.Function):
+    """(s, u) (packed complex64, the same lengths) -> a = sqrt(|chi_su|^2 /
+    (E_s E_u) + eps) grids of the cross-ambiguity (packed float32); the
+    gradient flows to both inputs.  The backward's workspace lives only for
+    the call, so the plan's own serves every call on a stream."""
+
+    @staticmethod
+    def forward(ctx, s, u, plan: Plan):
+        mag, _, _ = plan.cross_forward(s.detach(), u.detach(), mag=True)
+        ctx.plan = plan
+        ctx.save_for_backward(s, u)
+        return mag
+
+    @staticmethod
+    def backward(ctx, grad_mag):
+        s, u = ctx.saved_tensors
+        gs, gu = ctx.plan.cross_backward(s.detach(), u.detach(), grad_mag.contiguous().to(torch.float32))
+        return 2.0 * gs, 2.0 * gu, None
+
+
+def cross_af_magnitude(s, u, plan):
+    return CrossAFMagnitude.apply(s, u, plan)
+
+
 def af_magnitude(s, plan):
     return AFMagnitude.apply(s, plan)
 

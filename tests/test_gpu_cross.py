@@ -132,3 +132,23 @@ def test_cross_rejections(af):
     with pytest.raises(_lib.AfError) as ei:
         plan.cross_backward(s, s, g, ws=torch.empty(256, dtype=torch.uint8, device="cuda"))
     assert ei.value.code == -5
+
+
+def test_cross_autograd_user_loss(af):
+    # a user loss through torch autograd: L = sum w a on the cross-AF grid
+    say("cross autograd")
+    from paper_2506_22935_amd.autograd import cross_af_magnitude
+    n, m, T = 200, 512, 50
+    s0, u0 = rand_c64(n, 91), rand_c64(n, 92)
+    w = np.random.default_rng(93).standard_normal((2 * T + 1) * m).astype(np.float32)
+    plan = af.Plan([n], [m], [T], eps=EPS)
+    s = to_dev(s0).requires_grad_(True)
+    u = to_dev(u0).requires_grad_(True)
+    a = cross_af_magnitude(s, u, plan)
+    (a * torch.from_numpy(w).cuda()).sum().backward()
+    torch.cuda.synchronize()
+    rs, ru = O.cross_magnitude_backward(s0, u0, m, T, w.reshape(2 * T + 1, m).astype(np.float64), EPS)
+    # torch's gradient of a real loss at a complex leaf is 2 dL/d conj(.)
+    for g, r in ((s.grad, rs), (u.grad, ru)):
+        gg = g.cpu().numpy().astype(np.complex128) / 2
+        assert np.max(np.abs(gg - r)) <= 1e-4 * np.max(np.abs(r))
