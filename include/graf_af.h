@@ -248,7 +248,9 @@ af_status af_scenario_combine(const af_plan* plan, int32_t n_scen, const float* 
  * on the plan's grids ([2T+1][M], row tau + T), with a = sqrt(|chi_su|^2 /
  * (E_s E_u) + eps) (|chi_su|^2 <= E_s E_u; chi_su = chi when u = s).  Plans
  * whose classes are aperiodic with M <= 8192 (N <= 4096) only;
- * AF_ERR_UNSUPPORTED otherwise.
+ * AF_ERR_UNSUPPORTED otherwise.  Grid offsets must be even and mag 8-byte
+ * aligned (the forward writes the a grids as pairs of bins);
+ * AF_ERR_INVALID_ARG otherwise.
  * af_cross_forward: mag (a grids), chi (chi_su grids) and energy (device
  * float[batch][2] = E_s, E_u) are each nullable; no workspace.
  * af_cross_backward: grad_mag holds dL/da on the grids; grad_s and grad_u

@@ -854,6 +854,9 @@ af_status check_cross(const af_plan* p, const void* s, const void* u) {
     if (!p || !s || !u || !aligned(s, 8) || !aligned(u, 8)) return AF_ERR_INVALID_ARG;
     for (const af_plan::Class& k : p->classes)
         if (k.circ || !graf::cross_lg_supported(k.lg)) return AF_ERR_UNSUPPORTED;
+    // the kernels move the a and dL/da grids as 8-byte bin pairs
+    for (const af_wave& w : p->waves)
+        if (w.grid_off & 1) return AF_ERR_INVALID_ARG;
     return AF_OK;
 }
 size_t cross_slab_bytes(const af_plan* p) { return align256((size_t)p->slab_elems * sizeof(float2)); }
@@ -891,7 +894,7 @@ af_status af_cross_forward(const af_plan* p, const void* s, const void* u, float
                            void* stream) {
     af_status rc = check_cross(p, s, u);
     if (rc != AF_OK) return rc;
-    if (!aligned(mag, 4) || !aligned(chi, 8) || !aligned(energy, 4)) return AF_ERR_INVALID_ARG;
+    if (!aligned(mag, 8) || !aligned(chi, 8) || !aligned(energy, 4)) return AF_ERR_INVALID_ARG;
     graf::CrossArgs a = cross_args(p, s, u);
     a.mag = mag;
     a.chi = (float2*)chi;

@@ -106,6 +106,11 @@ __global__ __launch_bounds__(XWGS) void xaf_kernel(CrossArgs a) {
         const int tau = job_tau(j0 + grp, active);
         const int64_t row = w.grid_off + (int64_t)(T + tau) * M;
         float2 qa[XP];
+        // the forward writes bins 2(l + qL) and 2(l + qL) + 1 of the row (the
+        // two halves) as one 8-byte pair, holding the even half's magnitudes
+        // until the odd half's are known (the backward's upstream reads stay
+        // per bin: reading pairs and holding the odd half measured slower)
+        float hold[XP];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             float2 v[XP];
@@ -125,10 +130,12 @@ __global__ __launch_bounds__(XWGS) void xaf_kernel(CrossArgs a) {
                 const int k = 2 * (l + q * L) + h;
                 const float pw = cabs2(v[q]) * invEE;
                 if constexpr (MODE == 0) {
-                    if (active) {
-                        if (a.mag) a.mag[row + k] = __builtin_amdgcn_sqrtf(pw + a.eps);
-                        if (a.chi) a.chi[row + k] = v[q];
-                    }
+                    const float av = __builtin_amdgcn_sqrtf(pw + a.eps);
+                    if (h == 0)
+                        hold[q] = av;
+                    else if (active && a.mag)
+                        *reinterpret_cast<float2*>(a.mag + row + 2 * (l + q * L)) = make_float2(hold[q], av);
+                    if (active && a.chi) a.chi[row + k] = v[q];
                 } else {
                     const float g = active ? a.grad_mag[row + k] : 0.f;
                     const float ia = __builtin_amdgcn_rsqf(pw + a.eps);
