@@ -478,7 +478,8 @@ af_status check_loss(const af_plan* p, const af_loss_params* lp) {
     // ISL passes: not with the soft PSL
     if ((lp->w_match != 0.f || lp->w_width != 0.f || lp->w_cell != 0.f) && lp->w_psl != 0.f && !lp->psl_hard)
         return AF_ERR_UNSUPPORTED;
-    // the hard PSL, L_match and the width run in the split variants (M <= 8192)
+    // the hard PSL, L_match, the width and the cell weights run in the split
+    // variants (M <= 8192)
     if (extended_terms(lp))
         for (const af_plan::Class& k : p->classes)
             if (!graf::variant_info(k.variant, k.lg).split) return AF_ERR_UNSUPPORTED;
@@ -548,8 +549,8 @@ bool loss_writes_slabs(const af_loss_params* lp, bool want_grad) { return want_g
 // Is the forward pass alone enough for this loss?
 bool forward_only(const af_loss_params* lp, bool want_grad) { return !want_grad || !grid_gradient(lp); }
 
-// The experiment loss's per-waveform kernel (after the AF pass: it reads the
-// segment records and E)
+// The per-waveform kernel: the hard PSL, the spectral variance, var(|s|) and
+// the smoothness term (after the AF pass: it reads the segment records and E)
 af_status launch_extra(const af_plan* p, const void* s, const af_loss_params* lp, bool want_grad, const WsView& v,
                        hipStream_t st) {
     if (!needs_extra(lp)) return AF_OK;

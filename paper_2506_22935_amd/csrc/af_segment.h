@@ -1066,7 +1066,7 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     static_assert(!CIRC || (V::SPLIT && V::S_LDS), "periodic AF: split variants with samples in LDS");
     extern __shared__ float2 dyn[];
     // block reductions; [64, 96) holds the per-wave hard-PSL records,
-    // [96, 112) the per-wave L_match sums
+    // [96, 112) the per-wave sums of the cell-wise extension terms
     __shared__ double scratch[112];
     constexpr int MH = 1 << LG;
     float2* lds = dyn;

@@ -98,6 +98,14 @@ def test_null_arguments(lib):
     assert lib.af_phase_to_signal(None, None, 5, None) == -1
     sz = ctypes.c_size_t()
     assert lib.af_plan_workspace_size(None, ctypes.byref(sz)) == -1
+    # the composite-loss, projection, scenario and cross-AF entry points check
+    # their arguments on the host before any device work
+    assert lib.af_project(None, None, None, 0, None, None) == -1
+    assert lib.af_scenario_combine(None, 2, None, None, None, None) == -1
+    assert lib.af_cross_workspace_size(None, ctypes.byref(sz)) == -1
+    assert lib.af_cross_forward(None, None, None, None, None, None, None) == -1
+    assert lib.af_cross_backward(None, None, None, None, None, None, None, 0, None) == -1
+    assert lib.af_spectral_variance(None, None, None, None, None, 0, None) == -1
 
 
 def test_gemm_config_resolution(lib):

@@ -292,3 +292,42 @@ def test_cell_weights_rejections(af):
     with pytest.raises(_lib.AfError) as ei:
         plan.loss(s, w_isl=0.0, w_cell=1.0)  # weight without a grid
     assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("variant,n,m,T", [(0, 300, 1024, 40), (3, 300, 1024, 40), (4, 1500, 4096, 30),
+                                           (1, 3000, 8192, 20), (5, 3000, 8192, 20)])
+def test_extended_terms_every_split_variant(af, variant, n, m, T):
+    # every extended term at once (hard PSL, L_match, width, cell weights,
+    # var(|s|), smoothness, ISL) on each split variant's extended instances,
+    # with a lag window
+    say("extended terms variant", variant, n, m, T)
+    rows = 2 * T + 1
+    side = ~O.mainlobe_mask(m, T, 1, 1)
+    for seed in range(2100, 2140):
+        s = rand_c64(n, seed)
+        c = O.chi(s, m, T)
+        E = O.energy(s)
+        p = O.power(c, E)
+        top = np.sort(np.unique(np.round(p[side], 9)))
+        if top[-1] - top[-2] > 1e-4 * top[-1]:
+            break
+    rng = np.random.default_rng(variant)
+    target = rng.uniform(0, 2e-3, (rows, m)).astype(np.float32)
+    cellw = (rng.uniform(0, 1, (rows, m)) * (rng.uniform(0, 1, (rows, 1)) < 0.3)).astype(np.float32)
+    plan = af.Plan([n], [m], [T], eps=EPS, variant=variant)
+    assert plan.summary()["variant"] == variant
+    kw = dict(w_isl=0.3, w_psl=1.0, psl_hard=True, match=torch.from_numpy(target.ravel()).cuda(), w_match=5.0,
+              w_width=0.2, gamma=5.0, cell_w=torch.from_numpy(cellw.ravel()).cuda(), w_cell=0.5, w_const=1.0,
+              w_smooth=0.5)
+    terms, g, _ = plan.loss(to_dev(s), **kw)
+    torch.cuda.synchronize()
+    params = O.LossParams(w_isl=0.3, eps=EPS, match=target.astype(np.float64), w_match=5.0, w_width=0.2, gamma=5.0,
+                          cell_w=cellw.astype(np.float64), w_cell=0.5, w_const=1.0, w_smooth=0.5)
+    base = O.loss_grad_from_chi(s, m, T, c, params)
+    psl, cell = O.hard_psl(c, E, side)
+    G = np.zeros_like(c)
+    G[cell] = c[cell] / (E * E)
+    g_psl = O.grad_from_upstream(s, m, T, G, -2.0 * psl / E)
+    want = base["loss"] + psl
+    assert abs(terms[0, 0].item() - want) <= 1e-4 * want, (terms[0, 0].item(), want)
+    check_grad(g.cpu().numpy().astype(np.complex128), base["g"] + g_psl, "variant %d" % variant)
