@@ -602,8 +602,90 @@ def cpu_baseline_cross(n, m, seed, budget_s=10.0):
                 sample="cross-AF a grid + backward of one pair (N=%d, M=%d), %d repeats, %.1f s" % (n, m, done, t_all))
 
 
+def bench_composite(args, torch):
+    """The composite loss of Sec. 5.2 in a descent loop: 512 random-phase
+    codes, N = 256, M = 512, full window; L = ISL + hard PSL + L_match
+    against the thumbtack surface (power 1 at the origin cell, 0 elsewhere)
+    + 0.01 soft mainlobe width (gamma 10) + 0.01 phase smoothness; a step is
+    one Adam step on the phases of the batch (the extended fused pass, the
+    per-waveform kernel and the reduction with Adam), inputs in HBM."""
+    import numpy as np
+    from paper_2506_22935_amd import af, workloads as W
+    B, n, m = 512, 256, 512
+    T = n - 1
+    rows = 2 * T + 1
+    cells = B * rows * m
+    phases = W.random_phases(B * n, seed=args.seed + 31)
+    plan = af.Plan([n] * B, [m] * B, eps=1e-12)
+    target = torch.zeros(cells, dtype=torch.float32, device="cuda")
+    target.view(B, rows, m)[:, T, 0] = 1.0  # thumbtack: the origin cell of every grid
+    st = af.PhaseState(torch.from_numpy(phases.astype(np.float32)).cuda())
+    terms = torch.empty(B, 4, device="cuda")
+    ws = plan.workspace
+    lp = dict(w_isl=1.0, w_psl=1.0, psl_hard=True, match=target, w_match=1.0, w_width=0.01, gamma=10.0,
+              w_smooth=0.01)
+    log("composite: %d codes N=%d M=%d, %.3g cells, %d segments" % (B, n, m, cells, plan.summary()["segments"]))
+    start = None
+
+    def step():
+        plan.optim_step(st, lr=0.01, terms=terms, ws=ws, **lp)
+
+    for _ in range(args.warmup):
+        step()
+    start = float(terms[:, 0].mean())
+    ms = timed(step, args.steps, torch)
+    end = float(terms[:, 0].mean())
+    grad = torch.empty(B * n, dtype=torch.complex64, device="cuda")
+    fused_ms = timed(lambda: plan.loss_stage(0, st.s, terms, grad, None, ws=ws, **lp), 20, torch)
+    # per lag pair: one forward and one inverse M-point transform
+    flops = B * 2.0 * fft_flops(n, m)
+    ach = flops / (fused_ms * 1e-3) / 1e12
+    log("composite: %.4f ms/step, extended fused pass %.4f ms, mean loss %.4f -> %.4f over %d steps"
+        % (ms, fused_ms, start, end, args.steps))
+    out = dict(value=cells / (ms * 1e-3), ms_per_step=ms,
+                config=dict(workload="composite: 512 random-phase codes, N=256, M=512, full window, ISL + hard PSL + "
+                                     "L_match (thumbtack) + 0.01 width + 0.01 smoothness, Adam step on the phases",
+                            waveforms=B, n=n, m=m, cells=cells, stage_ms=dict(fused_pass=round(fused_ms, 5))),
+                roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                              frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
+                              kernel="extended fused ISL pass (hard-PSL records, L_match, width)",
+                              kernel_ms=round(fused_ms, 5), flops_per_launch=flops))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_composite(n, m, phases, budget_s=10.0)
+    return out
+
+
+def cpu_baseline_composite(n, m, phases, budget_s=10.0):
+    """The oracle's composite loss and gradient (the hard PSL's single-cell
+    part included) on consecutive waveforms of the batch until the budget is
+    spent."""
+    import numpy as np
+    import oracle as O
+    from oracle import _native
+    from paper_2506_22935_amd import workloads as W
+    T = n - 1
+    target = np.zeros((2 * T + 1, m))
+    target[T, 0] = 1.0
+    params = O.LossParams(w_isl=1.0, eps=1e-12, match=target, w_match=1.0, w_width=0.01, gamma=10.0, w_smooth=0.01)
+    done, t_all = 0, 0.0
+    while t_all < budget_s and (done + 1) * n <= len(phases):
+        s = O.to_c64_exact(W.unimodular(phases[done * n:(done + 1) * n]))
+        t0 = time.perf_counter()
+        t = O.loss_and_grad(s, m, T, params)
+        E = O.energy(s)
+        psl, cell = O.hard_psl(t["chi"], E, t["side"])
+        G = np.zeros_like(t["chi"])
+        G[cell] = t["chi"][cell] / (E * E)
+        O.grad_from_upstream(s, m, T, G, -2.0 * psl / E)
+        t_all += time.perf_counter() - t0
+        done += 1
+    return dict(value=done * (2 * T + 1) * m / t_all, unit="cells/s", cores=_native.threads(), kind="oracle",
+                sample="composite loss + gradient of the first %d waveforms (N=%d, M=%d), %.1f s" % (done, n, m, t_all))
+
+
 WORKLOADS = {"single": bench_single, "uneven": bench_uneven, "large": bench_large, "proposal": bench_proposal,
-             "periodic": bench_periodic, "experiment": bench_experiment, "copy": bench_copy, "cross": bench_cross}
+             "periodic": bench_periodic, "experiment": bench_experiment, "copy": bench_copy, "cross": bench_cross,
+             "composite": bench_composite}
 
 
 def main():

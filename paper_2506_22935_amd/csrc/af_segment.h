@@ -596,6 +596,30 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 constexpr bool MAIN = decltype(main_c)::value;
                 constexpr int EXT = decltype(ext_c)::value;  // 0, 1: hard PSL only, 2: every extension
                 const float c_main = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
+                // the per-cell reads of L_match and the cell weights (both cells
+                // of the pair; the -tau row only with a distinct partner) go
+                // out together before the cells' arithmetic, so one memory
+                // round trip serves the lane's P cells.  Plain per-lane
+                // pointers: the lag, and so the row, differs between the lane
+                // groups of a wavefront
+                constexpr int XR = EXT == 2 ? P : 1;
+                float tg_p[XR], tg_n[XR], cw_p[XR], cw_n[XR];
+                if constexpr (EXT == 2) {
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        const int k = CIRC ? l + q * L : 2 * (l + q * L) + h;
+                        const int kn = k ? RL - k : 0;
+                        tg_p[q] = tg_n[q] = cw_p[q] = cw_n[q] = 0.f;
+                        if (match) {
+                            tg_p[q] = active ? a.match_t[row_p + k] : 0.f;
+                            tg_n[q] = (active && two_rows) ? a.match_t[row_n + kn] : 0.f;
+                        }
+                        if (cellw) {
+                            cw_p[q] = active ? a.cell_w[row_p + k] : 0.f;
+                            cw_n[q] = (active && two_rows) ? a.cell_w[row_n + kn] : 0.f;
+                        }
+                    }
+                }
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     // bin of the grid row (periodic: v[q] is bin l + qL of N)
@@ -669,8 +693,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     }
                     if (EXT == 2 && cellw) {
                         // W p on both cells of the pair, each with its own weight
-                        const float wp = active ? a.cell_w[row_p + k] : 0.f;
-                        const float wn = (active && two_rows) ? a.cell_w[row_n + kn] : 0.f;
+                        const float wp = cw_p[EXT == 2 ? q : 0];
+                        const float wn = cw_n[EXT == 2 ? q : 0];
                         cw_f = fmaf(wp + wn, pw, cw_f);
                         if constexpr (NEEDS_INV) {
                             cm += a.w_cell * (wp + wn) * invE2;
@@ -678,11 +702,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         }
                     }
                     if (EXT == 2 && match) {
-                        // target rows (the -tau row is read only with a distinct
-                        // partner) through plain per-lane pointers: the lag, and
-                        // so the row, differs between the lane groups of a wavefront
-                        const float dp = active ? pw - a.match_t[row_p + k] : 0.f;
-                        const float dn = (active && two_rows) ? pw - a.match_t[row_n + kn] : 0.f;
+                        const float dp = active ? pw - tg_p[EXT == 2 ? q : 0] : 0.f;
+                        const float dn = (active && two_rows) ? pw - tg_n[EXT == 2 ? q : 0] : 0.f;
                         mt_f = fmaf(dp, dp, fmaf(dn, dn, mt_f));
                         if constexpr (NEEDS_INV) {
                             cm += 2.f * a.w_match * (dp + dn) * invE2;
