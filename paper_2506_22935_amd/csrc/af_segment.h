@@ -434,6 +434,13 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const bool match = EXT_OK && a.match_t != nullptr;
     const bool width = EXT_OK && a.w_width != 0.f;
     const bool cellw = EXT_OK && a.cell_w != nullptr;
+    // the extensions' arguments read once per segment into uniform locals:
+    // read through the argument struct inside the cell loops, they came from
+    // a stack copy of it, each read a memory round trip that also waited for
+    // the target reads in flight
+    const float* const x_match_t = a.match_t;
+    const float* const x_cell_w = a.cell_w;
+    const float x_w_match = a.w_match, x_w_width = a.w_width, x_gamma = a.gamma, x_w_cell = a.w_cell;
     const bool hard_rt = EXT_OK && a.psl_hard != 0;
     const bool ext_full = match || width || cellw;  // beyond the hard-PSL maximum
     const bool ext_rt = ext_full || hard_rt;
@@ -611,12 +618,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         const int kn = k ? RL - k : 0;
                         tg_p[q] = tg_n[q] = cw_p[q] = cw_n[q] = 0.f;
                         if (match) {
-                            tg_p[q] = active ? a.match_t[row_p + k] : 0.f;
-                            tg_n[q] = (active && two_rows) ? a.match_t[row_n + kn] : 0.f;
+                            tg_p[q] = active ? x_match_t[row_p + k] : 0.f;
+                            tg_n[q] = (active && two_rows) ? x_match_t[row_n + kn] : 0.f;
                         }
                         if (cellw) {
-                            cw_p[q] = active ? a.cell_w[row_p + k] : 0.f;
-                            cw_n[q] = (active && two_rows) ? a.cell_w[row_n + kn] : 0.f;
+                            cw_p[q] = active ? x_cell_w[row_p + k] : 0.f;
+                            cw_n[q] = (active && two_rows) ? x_cell_w[row_n + kn] : 0.f;
                         }
                     }
                 }
@@ -683,10 +690,10 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     // |tau| gamma sigma' per cell, energy term -2 p / E
                     if (EXT == 2 && width && k == 0) {
                         const float ld = (float)(CIRC ? min(tau, N - tau) : tau);
-                        const float sg = 1.f / (1.f + fast_exp2(-kLog2e * a.gamma * (pw - 0.5f)));
+                        const float sg = 1.f / (1.f + fast_exp2(-kLog2e * x_gamma * (pw - 0.5f)));
                         wd_f += active ? mult * ld * sg : 0.f;
                         if constexpr (NEEDS_INV) {
-                            const float u = active ? mult * a.w_width * ld * a.gamma * sg * (1.f - sg) : 0.f;
+                            const float u = active ? mult * x_w_width * ld * x_gamma * sg * (1.f - sg) : 0.f;
                             cm += u * invE2;
                             dlm_f = fmaf(-2.f * u * pw, invE, dlm_f);
                         }
@@ -697,8 +704,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         const float wn = cw_n[EXT == 2 ? q : 0];
                         cw_f = fmaf(wp + wn, pw, cw_f);
                         if constexpr (NEEDS_INV) {
-                            cm += a.w_cell * (wp + wn) * invE2;
-                            dlm_f = fmaf(-2.f * a.w_cell * (wp + wn) * pw, invE, dlm_f);
+                            cm += x_w_cell * (wp + wn) * invE2;
+                            dlm_f = fmaf(-2.f * x_w_cell * (wp + wn) * pw, invE, dlm_f);
                         }
                     }
                     if (EXT == 2 && match) {
@@ -706,8 +713,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         const float dn = (active && two_rows) ? pw - tg_n[EXT == 2 ? q : 0] : 0.f;
                         mt_f = fmaf(dp, dp, fmaf(dn, dn, mt_f));
                         if constexpr (NEEDS_INV) {
-                            cm += 2.f * a.w_match * (dp + dn) * invE2;
-                            dlm_f = fmaf(-4.f * a.w_match * pw * invE, dp + dn, dlm_f);
+                            cm += 2.f * x_w_match * (dp + dn) * invE2;
+                            dlm_f = fmaf(-4.f * x_w_match * pw * invE, dp + dn, dlm_f);
                         }
                     }
                     if constexpr (NEEDS_INV) {
@@ -809,7 +816,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             isl += (double)(mult * isl_f);
             dle += (double)((MODE == MODE_BWD_MAG ? 1.f : mult) * dle_f + dlm_f);
             if (match || width || cellw)
-                mt += (double)fmaf(a.w_match, mt_f, fmaf(a.w_width, wd_f, a.w_cell * cw_f));
+                mt += (double)fmaf(x_w_match, mt_f, fmaf(x_w_width, wd_f, x_w_cell * cw_f));
             if (FWD_SUMS && want_lse && (lse_fixed || MODE == MODE_LOSS)) {
                 ls += (double)(mult * sl_f);
             } else if (MODE == MODE_FWD && want_lse && mloc > -INFINITY) {
