@@ -441,13 +441,15 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const float* const x_match_t = a.match_t;
     const float* const x_cell_w = a.cell_w;
     const float x_w_match = a.w_match, x_w_width = a.w_width, x_gamma = a.gamma, x_w_cell = a.w_cell;
+    // likewise the loss weights and eps that the cell loops use
+    const float x_w_isl = a.w_isl, x_w_psl = a.w_psl, x_eps = a.eps;
     const bool hard_rt = EXT_OK && a.psl_hard != 0;
     const bool ext_full = match || width || cellw;  // beyond the hard-PSL maximum
     const bool ext_rt = ext_full || hard_rt;
     // hard PSL: this lane's largest sidelobe power and its cell (tau >= 0 row)
     float hp = -1.f;
     int hi = 0;
-    float lm = (want_lse && (lse_fixed || MODE == MODE_LOSS)) ? lse_ref(a.eps) : -INFINITY;
+    float lm = (want_lse && (lse_fixed || MODE == MODE_LOSS)) ? lse_ref(x_eps) : -INFINITY;
 
     // Y' of lag tau, half h, in the exit layout v[q] = Y'[2 (l + qL) + h]
     auto lag_spectrum = [&](float2* v, int h, int tau, bool active) {
@@ -602,7 +604,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 constexpr bool PSL = decltype(psl_c)::value;
                 constexpr bool MAIN = decltype(main_c)::value;
                 constexpr int EXT = decltype(ext_c)::value;  // 0, 1: hard PSL only, 2: every extension
-                const float c_main = -mult * a.w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
+                const float c_main = -mult * x_w_isl * invE2;  // d(M - mainlobe power)/d conj(chi)
                 // the per-cell reads of L_match and the cell weights (both cells
                 // of the pair; the -tau row only with a distinct partner) go
                 // out together before the cells' arithmetic, so one memory
@@ -638,7 +640,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     // one reciprocal square root and a multiply
                     constexpr bool NEED_IA = MODE == MODE_BWD_MAG || MODE == MODE_LOSS ||
                                              (MODE == MODE_BWD_LOSS && PSL);
-                    const float xa = pw + a.eps;
+                    const float xa = pw + x_eps;
                     const float ia = NEED_IA ? __builtin_amdgcn_rsqf(xa) : 0.f;
                     const float av = NEED_IA ? xa * ia : __builtin_amdgcn_sqrtf(xa);
                     const bool main_cell = MAIN && active && main_tau && kc <= w.h_k;
@@ -732,27 +734,27 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                             c = 0.5f * g * invE2 * ia;
                             dle_f = fmaf(-g * pw * invE, ia, dle_f);
                         } else if constexpr (MODE == MODE_BWD_LOSS) {
-                            float cs = COMPL ? 0.f : a.w_isl * wt * invE2;
+                            float cs = COMPL ? 0.f : x_w_isl * wt * invE2;
                             if constexpr (PSL) {
                                 const float qq = fast_exp2((av - glob_m) * inv_t2) * glob_inv_s;
-                                    cs = fmaf(a.w_psl * qq * 0.5f * invE2, ia, cs);
-                                dle_f = fmaf(sd ? -a.w_psl * qq * pw * invE : 0.f, ia, dle_f);
+                                    cs = fmaf(x_w_psl * qq * 0.5f * invE2, ia, cs);
+                                dle_f = fmaf(sd ? -x_w_psl * qq * pw * invE : 0.f, ia, dle_f);
                             }
                             c = sd ? mult * cs : ((COMPL && main_cell) ? c_main : 0.f);
                         } else if constexpr (MODE == MODE_LOSS) {
                             if (direct_isl && main_cell) {
                                 // H of the ISL part on this mainlobe bin
                                 const int ks = k < (RL >> 1) ? k : k - RL;
-                                mlb[lam * n_mb + ks + w.h_k] = cscale(v[q], -mult * a.w_isl * invE2);
+                                mlb[lam * n_mb + ks + w.h_k] = cscale(v[q], -mult * x_w_isl * invE2);
                             }
                             // soft-PSL part without the normaliser 1/S
-                            c = sd ? mult * a.w_psl * e * 0.5f * invE2 * ia : 0.f;
-                            dle_f = fmaf(sd ? -a.w_psl * e * pw * invE : 0.f, ia, dle_f);
+                            c = sd ? mult * x_w_psl * e * 0.5f * invE2 * ia : 0.f;
+                            dle_f = fmaf(sd ? -x_w_psl * e * pw * invE : 0.f, ia, dle_f);
                         } else {  // MODE_FUSED_ISL
                             if constexpr (COMPL)
                                 c = main_cell ? c_main : 0.f;
                             else
-                                c = sd ? mult * a.w_isl * wt * invE2 : 0.f;
+                                c = sd ? mult * x_w_isl * wt * invE2 : 0.f;
                         }
                         v[q] = cscale(v[q], c + cm);
                     }
@@ -791,7 +793,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 else
                     by_loss(F_{}, T_{}, T_{}, F_{});
             } else if constexpr (MODE == MODE_BWD_LOSS) {
-                if (a.w_psl != 0.f)
+                if (x_w_psl != 0.f)
                     by_loss(T_{}, T_{}, T_{}, F_{});
                 else
                     by_loss(T_{}, F_{}, T_{}, F_{});
@@ -956,7 +958,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 // cells (both signs of tau for tau > 0), into the second slab
                 float2 v[P];
                 lag_spectrum(v, hsel, tau, active);
-                const float c_main = -mult * a.w_isl * invE2;
+                const float c_main = -mult * x_w_isl * invE2;
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const int k = CIRC ? l + q * L : 2 * (l + q * L) + hsel;
