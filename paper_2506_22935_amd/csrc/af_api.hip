@@ -167,7 +167,7 @@ af_status build_schedule(af_plan* p) {
         k.dyn_lds = vi.fft_lds + (vi.s_lds ? 8 * (2 << k.lg) : 0);  // samples zero-padded to M
         for (int mode = 0; mode < graf::kNumModes; ++mode) {
             const int r = graf::variant_max_resident(mode, v, k.lg, k.circ, k.dyn_lds);
-            if (r <= 0 && mode == graf::MODE_FUSED_EXT && !vi.split) {
+            if (r <= 0 && graf::is_ext_mode(mode) && !vi.split) {
                 k.grid[mode] = 0;  // no extended instance: those terms are refused
                 continue;
             }
@@ -579,7 +579,7 @@ af_status loss_passes(const af_plan* p, const void* s, const af_loss_params* lp,
     AfArgs a = loss_args(p, s, lp, mag, v);
     af_status rc;
     if (forward_only(lp, want_grad)) {
-        rc = launch(p, graf::MODE_FWD, a, st, only_class);
+        rc = launch(p, extended_terms(lp) ? graf::MODE_FWD_EXT : graf::MODE_FWD, a, st, only_class);
     } else if (a.w_psl == 0.f) {
         rc = launch(p, extended_terms(lp) ? graf::MODE_FUSED_EXT : graf::MODE_FUSED_ISL, a, st, only_class);
     } else if (fused_loss_ok(p, lp)) {
@@ -784,7 +784,7 @@ af_status af_loss_stage(const af_plan* p, int32_t stage, const void* s, const af
             if (fused) return launch(p, extended_terms(lp) ? graf::MODE_FUSED_EXT : graf::MODE_FUSED_ISL, a, st);
             if (fused_loss) return launch(p, graf::MODE_LOSS, a, st);
             a.ystore = fwd_only ? nullptr : v.store;
-            return launch(p, graf::MODE_FWD, a, st);
+            return launch(p, (fwd_only && extended_terms(lp)) ? graf::MODE_FWD_EXT : graf::MODE_FWD, a, st);
         case 1:
             if (!(fwd_only || fused || fused_loss)) {
                 a.mag = nullptr;

@@ -59,12 +59,17 @@ enum Mode : int {
     MODE_LOSS = 4,      // ISL (mainlobe complement) + soft-PSL (fixed shift) loss,
                         // forward and backward in one pass; the soft-PSL
                         // gradient is left unnormalised for the reduction
-    MODE_FUSED_EXT = 5  // launch id only: the MODE_FUSED_ISL pass in its own
+    MODE_FUSED_EXT = 5, // launch id only: the MODE_FUSED_ISL pass in its own
                         // instance with the extended epilogue terms (hard-PSL
                         // maximum, L_match, mainlobe width; split variants), so
                         // that the plain fused pass keeps its registers
+    MODE_FWD_EXT = 6    // launch id only: the MODE_FWD pass with the extended
+                        // epilogue terms, likewise; the plain forward carries
+                        // none of their code and keeps every value in registers
 };
-constexpr int kNumModes = 6;
+constexpr int kNumModes = 7;
+// launch ids that run the extended epilogue (split variants only)
+constexpr bool is_ext_mode(int mode) { return mode == MODE_FUSED_EXT || mode == MODE_FWD_EXT; }
 
 struct AfArgs {
     WaveDesc w0;          // the waveform of a one-waveform class (single != 0)
@@ -88,11 +93,11 @@ struct AfArgs {
     float2* slabs;        // [sum segs*N]
     float2* slabs2;       // [sum isl_segs*N] ISL part of MODE_LOSS
     float* energy;        // [B], written by the segment holding lag 0
-    int psl_hard;         // MODE_FWD / MODE_FUSED_EXT: record the hard-PSL maximum
-    const float* match_t; // target power grid of L_match (MODE_FWD / MODE_FUSED_EXT), nullable
+    int psl_hard;         // MODE_FWD_EXT / MODE_FUSED_EXT: record the hard-PSL maximum
+    const float* match_t; // target power grid of L_match (MODE_FWD_EXT / MODE_FUSED_EXT), nullable
     float w_match;
-    float w_width, gamma; // soft mainlobe width on the k = 0 column (MODE_FWD / MODE_FUSED_EXT)
-    const float* cell_w;  // per-cell weight grid (MODE_FWD / MODE_FUSED_EXT), nullable
+    float w_width, gamma; // soft mainlobe width on the k = 0 column (MODE_FWD_EXT / MODE_FUSED_EXT)
+    const float* cell_w;  // per-cell weight grid (MODE_FWD_EXT / MODE_FUSED_EXT), nullable
     float w_cell;
 };
 

@@ -276,11 +276,12 @@ __device__ void stage_split_twiddles(const AfArgs& a, float2* hi, float2* lo, in
 // tau = N/2 give one row each), and the lag product and its adjoint index
 // samples modulo N.
 // instances that take the extended epilogue terms (hard-PSL maximum,
-// L_match, mainlobe width): the forward pass, and the fused ISL pass built
-// with EXTK (split variants)
+// L_match, mainlobe width, cell weights): the forward and the fused ISL
+// passes built with EXTK (split variants); the plain instances of both
+// carry none of that code
 template <int MODE, bool EXTK>
 constexpr bool EXT_MODE() {
-    return MODE == MODE_FWD || (MODE == MODE_FUSED_ISL && EXTK);
+    return (MODE == MODE_FWD || MODE == MODE_FUSED_ISL) && EXTK;
 }
 
 template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, bool CIRC, bool EXTK, typename Tw>

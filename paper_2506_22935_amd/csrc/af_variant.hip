@@ -37,6 +37,9 @@ static void* pick_mode(int mode, int lg) {
         case MODE_FUSED_EXT:
             if constexpr (VSel::SPLIT) return pick_lg<MODE_FUSED_ISL, 1, CIRC, true>(lg);
             return nullptr;
+        case MODE_FWD_EXT:
+            if constexpr (VSel::SPLIT) return pick_lg<MODE_FWD, 1, CIRC, true>(lg);
+            return nullptr;
     }
     return nullptr;
 }
