@@ -42,6 +42,14 @@ def random_code(n, seed):
     return unimodular(random_phases(n, seed))
 
 
+def complex_gaussian(n, seed):
+    """Circular complex Gaussian samples (unit variance), rounded to complex64:
+    a waveform whose modulus varies, so no AF cell vanishes exactly."""
+    rng = np.random.default_rng(seed)
+    z = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) / math.sqrt(2.0)
+    return z.astype(np.complex64)
+
+
 def lfm_noisy_phases(n=16384, time_bandwidth=1000.0, sigma=0.3, seed=0):
     """Quadratic LFM phase pi*BT*(n/N - 1/2)^2 plus Gaussian phase noise."""
     rng = np.random.default_rng(seed)

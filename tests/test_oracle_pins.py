@@ -132,6 +132,31 @@ def test_barker13_golden():
     assert abs(20 * math.log10(cut[side].max() / 13.0) - (-22.2788)) < 1e-3
 
 
+def test_psl_db_barker13():
+    # the oracle's PSL reporter (Eq. 18 in dB) on the Barker-13 zero-Doppler
+    # cut, from a power cut and from a magnitude cut, against the golden value
+    golden = code = None
+    with open(os.path.join(HERE, "golden", "barker13.txt")) as f:
+        for line in f:
+            if line.startswith("code:"):
+                code = np.array([float(x) for x in line.split()[1:]])
+            elif line.startswith("psl_db_zero_doppler:"):
+                golden = float(line.split()[1])
+    s = code.astype(np.complex128)
+    T = 12
+    c = O.chi(s, 32)[:, 0]
+    E = O.energy(s)
+    side = np.ones(2 * T + 1, dtype=bool)
+    side[T] = False
+    p = O.power(c, E)
+    assert abs(O.psl_db(p, side) - golden) < 1e-3
+    assert abs(O.psl_db(np.sqrt(p), side, is_power=False) - golden) < 1e-3
+    # the origin is excluded: with it the level would be 0 dB
+    assert abs(O.psl_db(p, np.ones_like(side))) < 1e-12
+    # no sidelobe energy: -inf
+    assert O.psl_db(np.where(side, 0.0, p), side) == -math.inf
+
+
 def test_invariances():
     n, m = 21, 64
     s = rand_complex(n, 6)
