@@ -207,6 +207,21 @@ af_status af_backward(const af_plan* plan, const void* s, const float* grad_mag,
 af_status af_loss(const af_plan* plan, const void* s, const af_loss_params* loss, float* terms, float* mag,
                   void* grad_s, void* ws, size_t ws_bytes, void* stream);
 
+/* af_loss for callers that cannot allocate device memory or take a
+ * workspace argument (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same passes and results as af_loss,
+ * with the workspace taken from a library-owned device array of 64 MiB per
+ * GPU (held by each device that loads the library until the process ends).
+ * Calls no hipMalloc or hipFree.  The plan must come from af_plan_create on
+ * the same device; plans whose af_plan_workspace_size exceeds 64 MiB get
+ * AF_ERR_WORKSPACE, and AF_ERR_HIP means the array could not be resolved on
+ * that device.  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind (no call needs it zeroed: each pass writes what it later
+ * reads), so calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialised by the caller. */
+af_status af_loss_no_alloc(const af_plan* plan, const void* s, const af_loss_params* loss, float* terms, float* mag,
+                           void* grad_s, void* stream);
+
 /* One stage of af_loss on its own, for timing and profiling.  stage 0: the
  * forward pass (a grids and loss partials; with grad_s set and a loss that
  * allows it, the single fused pass instead); stage 1: the backward pass (only

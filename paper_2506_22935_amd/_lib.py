@@ -63,6 +63,7 @@ SIGNATURES = {
     "af_forward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "af_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "af_loss": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(AfLossParams), _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "af_loss_no_alloc": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(AfLossParams), _VP, _VP, _VP, _VP]),
     "af_loss_stage": (ctypes.c_int, [_VP, _I32, _VP, ctypes.POINTER(AfLossParams), _VP, _VP, _VP, _VP, _SZ,
                                      _VP]),
     "af_phase_to_signal": (ctypes.c_int, [_VP, _VP, _I64, _VP]),

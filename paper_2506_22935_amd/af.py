@@ -200,6 +200,18 @@ class Plan:
                                            _ptr(ws), ws.numel(), _stream()))
         return t, g, m
 
+    def loss_no_alloc(self, s, terms, grad=None, mag=None, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None,
+                      psl_hard=False, w_spec=0.0, match=None, w_match=0.0, w_width=0.0, gamma=10.0, w_const=0.0,
+                      w_smooth=0.0, cell_w=None, w_cell=0.0):
+        """loss() through af_loss_no_alloc: the workspace is the library's own
+        device array (no workspace argument, nothing allocated by the call).
+        terms, grad (nullable) and mag (nullable) are caller-owned outputs."""
+        _need(s, torch.complex64, "s")
+        lp = self.loss_params(w_isl, w_psl, temp, band_w, psl_hard, w_spec, match, w_match, w_width, gamma,
+                              w_const, w_smooth, cell_w, w_cell)
+        L.check("af_loss_no_alloc", L.lib().af_loss_no_alloc(self._h, _ptr(s), ctypes.byref(lp), _ptr(terms),
+                                                             _ptr(mag), _ptr(grad), _stream()))
+
     def loss_stage(self, stage, s, terms, grad, mag, w_isl=1.0, w_psl=0.0, temp=0.05, band_w=None, ws=None,
                    psl_hard=False, w_spec=0.0, match=None, w_match=0.0, w_width=0.0, gamma=10.0, w_const=0.0,
                    w_smooth=0.0, cell_w=None, w_cell=0.0):

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -36,6 +37,46 @@ int ilog2(int64_t x) {
     return r;
 }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// Workspace of af_loss_no_alloc: a file-scope device array, one copy per GPU
+// (each device that loads the library holds it until the process ends).
+// Its name in host code is a stand-in, not a device address, so no host
+// code passes it to a kernel: af_plan_create resolves the array's address
+// on the plan's device once (hipGetSymbolAddress, with that device current)
+// and every later use goes through that pointer.
+constexpr size_t kNoAllocWsBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocWsBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+int g_scratch_state[kMaxDevices] = {};  // 0 not resolved yet, 1 resolved, -1 failed
+
+// Resolve device dev's copy of `scratch`; dev must be the current device.
+void resolve_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_state[dev] != 0) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && ptr != nullptr && ((uintptr_t)ptr & 255) == 0) {
+        g_scratch_ptr[dev] = ptr;
+        g_scratch_state[dev] = 1;
+    } else {
+        (void)hipGetLastError();  // leave no error behind for the next call
+        g_scratch_state[dev] = -1;
+    }
+}
+
+void* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_state[dev] == 1 ? g_scratch_ptr[dev] : nullptr;
+}
 
 }  // namespace
 
@@ -616,6 +657,24 @@ ReduceArgs loss_reduce_args(const af_plan* p, const void* s, const af_loss_param
     return r;
 }
 
+// af_loss on a given workspace (the caller's, or af_loss_no_alloc's array)
+af_status loss_call(const af_plan* p, const void* s, const af_loss_params* lp, float* terms, float* mag, void* grad_s,
+                    void* ws, size_t ws_bytes, hipStream_t st) {
+    af_status rc = check_common(p, s, ws, ws_bytes);
+    if (rc != AF_OK) return rc;
+    if ((rc = check_loss(p, lp)) != AF_OK) return rc;
+    if (!aligned(mag, 16) || !aligned(grad_s, 8) || !aligned(terms, 4) || !aligned(lp->band_w, 4))
+        return AF_ERR_INVALID_ARG;
+    const WsView v = ws_view(p, ws);
+    rc = loss_passes(p, s, lp, mag, grad_s != nullptr, v, st);
+    if (rc != AF_OK) return rc;
+    if (!terms && !grad_s) return AF_OK;
+    ReduceArgs r = loss_reduce_args(p, s, lp, grad_s != nullptr, v);
+    r.grad = (float2*)grad_s;
+    r.terms = terms;
+    return graf::launch_reduce(r, st) == hipSuccess ? AF_OK : AF_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -688,6 +747,9 @@ af_status af_plan_create(int32_t batch, const af_wave* waves, const af_plan_opts
         delete p;
         return rc;
     }
+    // this device's copy of af_loss_no_alloc's workspace, once per device; a
+    // failure only disables that entry point
+    resolve_scratch(dev);
     *out = p;
     return AF_OK;
 }
@@ -750,19 +812,16 @@ af_status af_backward(const af_plan* p, const void* s, const float* grad_mag, vo
 
 af_status af_loss(const af_plan* p, const void* s, const af_loss_params* lp, float* terms, float* mag, void* grad_s,
                   void* ws, size_t ws_bytes, void* stream) {
-    af_status rc = check_common(p, s, ws, ws_bytes);
-    if (rc != AF_OK) return rc;
-    if ((rc = check_loss(p, lp)) != AF_OK) return rc;
-    if (!aligned(mag, 16) || !aligned(grad_s, 8) || !aligned(terms, 4) || !aligned(lp->band_w, 4))
-        return AF_ERR_INVALID_ARG;
-    const WsView v = ws_view(p, ws);
-    rc = loss_passes(p, s, lp, mag, grad_s != nullptr, v, (hipStream_t)stream);
-    if (rc != AF_OK) return rc;
-    if (!terms && !grad_s) return AF_OK;
-    ReduceArgs r = loss_reduce_args(p, s, lp, grad_s != nullptr, v);
-    r.grad = (float2*)grad_s;
-    r.terms = terms;
-    return graf::launch_reduce(r, (hipStream_t)stream) == hipSuccess ? AF_OK : AF_ERR_HIP;
+    return loss_call(p, s, lp, terms, mag, grad_s, ws, ws_bytes, (hipStream_t)stream);
+}
+
+af_status af_loss_no_alloc(const af_plan* p, const void* s, const af_loss_params* lp, float* terms, float* mag,
+                           void* grad_s, void* stream) {
+    if (!p) return AF_ERR_INVALID_ARG;
+    if (p->ws_total > kNoAllocWsBytes) return AF_ERR_WORKSPACE;
+    void* ws = scratch_ptr(p->device);
+    if (!ws) return AF_ERR_HIP;
+    return loss_call(p, s, lp, terms, mag, grad_s, ws, kNoAllocWsBytes, (hipStream_t)stream);
 }
 
 af_status af_loss_stage(const af_plan* p, int32_t stage, const void* s, const af_loss_params* lp, float* terms,
