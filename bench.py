@@ -42,6 +42,38 @@ def timed(fn, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
+EAGER = False  # --eager: time launches from the host instead (for counter runs)
+
+
+def graph_ms(fn, k, torch, reps=5):
+    """Per-call ms of fn: k calls captured in one HIP graph, the graph replayed
+    reps times on the current stream between HIP events; the median replay
+    divided by k.  Launch overhead from the host is out of the timed region;
+    the gaps between the graph's kernels stay in.  With --eager: k calls
+    launched from the host between HIP events, no graph."""
+    if EAGER:
+        return timed(fn, k, torch), None
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(k):
+                fn()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    times = sorted(timed(g.replay, 1, torch) / k for _ in range(reps))
+    return times[len(times) // 2], g
+
+
+def alg_fft_flops(cells, m, transforms=2):
+    """Algorithmic transform flops of a pass over `cells` AF cells: `transforms`
+    M-point transforms per cell at 5 log2 M flops per point (the forward
+    spectrum and the adjoint's inverse: 2)."""
+    return transforms * 5.0 * math.log2(m) * cells
+
+
 def cpu_baseline_single(n, m, seed, budget_s=10.0):
     """The float64 oracle (direct sums, OpenMP) on the same single-waveform
     problem: loss + gradient repeated for about budget_s seconds, as cells
@@ -64,14 +96,15 @@ def cpu_baseline_single(n, m, seed, budget_s=10.0):
 
 
 def source_digest():
-    """SHA-256 over the kernel sources and the public header: a profile's
-    counter figures describe the kernels only while this is unchanged."""
+    """SHA-256 over the device-code sources (every csrc file but the host-only
+    af_api.hip): a profile's counter figures describe the kernels only while
+    this is unchanged."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2506_22935_amd", "csrc", "*.h")) +
-                   glob.glob(os.path.join(ROOT, "paper_2506_22935_amd", "csrc", "*.hip")) +
-                   glob.glob(os.path.join(ROOT, "include", "*.h")))
+    files = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_2506_22935_amd", "csrc", "*.h")) +
+                   glob.glob(os.path.join(ROOT, "paper_2506_22935_amd", "csrc", "*.hip"))
+                   if os.path.basename(f) != "af_api.hip")
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -133,24 +166,30 @@ def bench_single(args, torch):
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        ms = timed(step, args.steps, torch)
-        stage_ms = [timed(lambda st=st: plan.loss_stage(st, s, terms, grad, mag, ws=ws, **lp), args.steps, torch)
-                    for st in (0, 2)]
+        # the timed steps: --steps whole steps in one HIP graph, replayed
+        ms, _ = graph_ms(step, args.steps, torch)
+        # the stages alone, each as a graph of --steps launches
+        stage_ms = [graph_ms(lambda st=st: plan.loss_stage(st, s, terms, grad, mag, ws=ws, **lp), args.steps,
+                             torch)[0] for st in (0, 2)]
         log("variant=%d: %.4f ms/step, fused pass %.4f ms, reduce %.4f ms" % (variant, ms, stage_ms[0], stage_ms[1]))
         results[variant] = (ms, stage_ms, plan)
     variant = min(results, key=lambda k: results[k][0])
     ms, stage_ms, plan = results[variant]
 
-    # roofline of the dominant kernel, the fused loss pass: one forward and
-    # one inverse M-point transform per lag pair (T + 1 of them) over the
-    # kernel's average duration; bound by vector ALU issue
-    flops = 2.0 * fft_flops(T + 1, m)
+    # roofline of the dominant kernel, the fused loss pass, bound by vector
+    # ALU issue: the algorithmic count is two M-point transforms per cell
+    # (5 log2 M flops per point each) over the pass's average launch time;
+    # the transforms it executes (one forward and one inverse per lag pair,
+    # T + 1 pairs: the lag-pair symmetry halves the count) are reported beside
+    flops = alg_fft_flops(cells, m)
+    exec_flops = 2.0 * fft_flops(T + 1, m)
     ach = flops / (stage_ms[0] * 1e-3) / 1e12
     roof = dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                 frac=round(ach / FP32_PEAK_TFLOPS, 4),
                 traffic=profiled_traffic("af_loss_fused_n1024_m2048.md", plan.summary()["variant"]),
                 kernel="fused loss pass (forward + backward transforms, a grid, loss partials)",
-                kernel_ms=round(stage_ms[0], 5), flops_per_launch=flops)
+                kernel_ms=round(stage_ms[0], 5), flops_per_launch=flops, executed_transform_flops=exec_flops,
+                executed_tflops=round(exec_flops / (stage_ms[0] * 1e-3) / 1e12, 2))
 
     # the a grid the step writes, against HBM
     hbm_step = 4.0 * cells / (ms * 1e-3) / 1e9
@@ -164,23 +203,32 @@ def bench_single(args, torch):
         mag2 = torch.empty(cells, dtype=torch.float32, device="cuda")
         g2 = torch.empty(n, dtype=torch.complex64, device="cuda")
 
-        def mstep():
+        def fwd():
             mplan.forward(s, mag=True, ws=mws, out_mag=mag2)
+
+        def bwd():
             mplan.backward(s, ga, ws=mws, out=g2)
+
+        def mstep():
+            fwd()
+            bwd()
 
         for _ in range(args.warmup):
             mstep()
-        mms = timed(mstep, args.steps, torch)
+        mms, _ = graph_ms(mstep, args.steps, torch)
+        fms, _ = graph_ms(fwd, args.steps, torch)
         mat["store" if store == 1 else "recompute"] = dict(
-            ms_per_step=round(mms, 5), cells_per_s=cells / (mms * 1e-3),
+            ms_per_step=round(mms, 5), forward_ms=round(fms, 5), cells_per_s=cells / (mms * 1e-3),
             hbm_frac_8B_per_cell=round(8.0 * cells / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
-        log("materialised fwd+bwd (store=%d): %.4f ms" % (store, mms))
+        log("materialised fwd+bwd (store=%d): %.4f ms (forward %.4f ms)" % (store, mms, fms))
 
     out = dict(value=cells / (ms * 1e-3), ms_per_step=ms,
                config=dict(workload="single: N=1024 random-phase code, 2047 lags x M=2048, "
                                     "ISL(|tau|<=1,|k|<=1)+softPSL(T=0.05) fwd+bwd, a grid written",
                            n=n, m=m, lags=2 * n - 1, cells=cells, variant=plan.summary()["variant"],
                            path="fused loss pass + reduce",
+                           timing=("%d host-launched steps" % args.steps) if EAGER else
+                                  ("%d steps in one HIP graph, median of 5 replays" % args.steps),
                            stage_ms=dict(fused_pass=round(stage_ms[0], 5), reduce=round(stage_ms[1], 5)),
                            a_grid_hbm_gbs=round(hbm_step, 1), a_grid_hbm_frac=round(hbm_step / HBM_PEAK_GBS, 4),
                            materialised_fwd_bwd=mat),
@@ -227,8 +275,10 @@ def bench_uneven(args, torch):
     # the fused ISL pass alone (one persistent launch per size class)
     grad = torch.empty(plan.total_samples, dtype=torch.complex64, device="cuda")
     fused_ms = timed(lambda: plan.loss_stage(0, st.s, terms, grad, None, w_isl=1.0, ws=ws), 20, torch)
-    # one forward and one inverse M-point transform per lag pair (N of them)
-    flops = sum(2.0 * fft_flops(int(n), int(m)) for n, m in zip(ns, ms))
+    # algorithmic: two M-point transforms per cell; executed: one forward
+    # and one inverse per lag pair (N of them per waveform)
+    flops = sum(alg_fft_flops((2 * int(n) - 1) * int(m), int(m)) for n, m in zip(ns, ms))
+    exec_flops = sum(2.0 * fft_flops(int(n), int(m)) for n, m in zip(ns, ms))
     ach = flops / (fused_ms * 1e-3) / 1e12
     log("uneven: %.3f ms/step (graph), fused pass %.3f ms, sum ISL %.4g -> %.4g" % (ms_step, fused_ms, isl0, isl1))
     out = dict(value=cells / (ms_step * 1e-3), ms_per_step=ms_step,
@@ -238,7 +288,8 @@ def bench_uneven(args, torch):
                            isl_sum_before=isl0, isl_sum_after=isl1),
                roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                              frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
-                             kernel="fused ISL forward+backward (all size classes)", kernel_ms=round(fused_ms, 4)))
+                             kernel="fused ISL forward+backward (all size classes)", kernel_ms=round(fused_ms, 4),
+                             flops_per_launch=flops, executed_transform_flops=exec_flops))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_uneven(ns, ms, phases, args.seed)
     return out
@@ -329,8 +380,8 @@ def bench_proposal(args, torch):
     from paper_2506_22935_amd import proposal as P
     n, m, B = 256, 512, 4096
     pr = P.Proposer(n, m, seed=args.seed)
-    _, train_ms = P.timed_ms(lambda: P.train(pr, n, m, batch=512, steps=args.train_steps, seed=args.seed + 1,
-                                             log=log))
+    _, train_ms = P.timed_ms(lambda: P.train(pr, n, m, batch=B, steps=args.train_steps, seed=args.seed + 1,
+                                             pretrain_steps=args.pretrain_steps, log=log))
     te = P.DescriptorBatch(n, m, B, seed=args.seed + 2)
     res = P.evaluate(pr, te, plain_steps=2000, refine_steps=50, fallback_steps=2000, seed=args.seed + 3, log=log)
     # MLP kernels alone: one forward + backward at batch 4096 (MFMA roofline)
@@ -351,6 +402,8 @@ def bench_proposal(args, torch):
     gemm_flops = sum(2.0 * B * sizes[i] * sizes[i + 1] for i in range(len(sizes) - 1))
     mlp_flops = 3.0 * gemm_flops - 2.0 * B * sizes[0] * sizes[1]  # forward, dW, dX (no dX for the input)
     mlp_tf = mlp_flops / (mlp_ms * 1e-3) / 1e12
+    # medians over every descriptor (inf where the target is never reached):
+    # a learned median of inf gives a ratio of 0
     speedup = res["median_plain_ms"] / res["median_learned_ms"] if res["median_learned_ms"] > 0 else None
     keep = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items()
             if not isinstance(v, torch.Tensor)}
@@ -358,7 +411,8 @@ def bench_proposal(args, torch):
                metric="time-to-target weighted ISL, learned vs plain",
                config=dict(workload="proposal: 4096 descriptors, N=256, M=512, weighted ISL; plain Adam 2000 steps "
                                     "vs network + refinement",
-                           train_steps=args.train_steps, train_ms=round(train_ms, 1), optimiser_step_ms=res["step_ms"],
+                           train_steps=args.train_steps, train_batch=B, pretrain_steps=args.pretrain_steps,
+                           train_ms=round(train_ms, 1), optimiser_step_ms=res["step_ms"],
                            optimiser_cells_per_s=cells / (res["step_ms"] * 1e-3), evaluation=keep,
                            mlp_fwd_bwd_ms=round(mlp_ms, 4)),
                roofline=dict(bound="mfma", achieved=round(mlp_tf, 2), peak=2500.0, unit="TFLOP/s",
@@ -393,8 +447,10 @@ def bench_periodic(args, torch):
         step()
     ms = timed(step, args.steps, torch)
     fused_ms = timed(lambda: plan.loss_stage(0, s, terms, grad, None, ws=ws, **lp), 20, torch)
-    # one forward and one inverse N-point transform per lag tau in [0, N/2]
-    flops = B * 2.0 * fft_flops(n // 2 + 1, n)
+    # algorithmic: two N-point transforms per cell of the N x N grid;
+    # executed: one forward and one inverse per lag tau in [0, N/2]
+    flops = alg_fft_flops(cells, n)
+    exec_flops = B * 2.0 * fft_flops(n // 2 + 1, n)
     ach = flops / (fused_ms * 1e-3) / 1e12
     log("periodic: %.4f ms/step, fused pass %.4f ms, mean ISL %.3f, mean soft-PSL %.4f"
         % (ms, fused_ms, float(terms[:, 1].mean()), float(terms[:, 2].mean())))
@@ -406,7 +462,8 @@ def bench_periodic(args, torch):
                roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                              frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
                              kernel="fused periodic loss pass (forward + inverse N-point transforms)",
-                             kernel_ms=round(fused_ms, 5), flops_per_launch=flops))
+                             kernel_ms=round(fused_ms, 5), flops_per_launch=flops,
+                             executed_transform_flops=exec_flops))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_periodic(n, phases, budget_s=10.0)
     return out
@@ -481,7 +538,10 @@ def bench_experiment(args, torch):
     lpk = dict(w_isl=0.0, w_psl=1.0, psl_hard=True, w_spec=0.5 * alpha)
     fwd_ms = timed(lambda: plan.loss_stage(0, s, terms, grad, None, ws=ws, **lpk), 50, torch)
     extra_ms = timed(lambda: plan.loss_stage(1, s, terms, grad, None, ws=ws, **lpk), 50, torch)
-    flops = B * fft_flops(n // 2 + 1, n)
+    # algorithmic: one N-point transform per cell of the N x N grid (forward
+    # only); executed: one per lag tau in [0, N/2]
+    flops = alg_fft_flops(B * n * n, n, transforms=1)
+    exec_flops = B * fft_flops(n // 2 + 1, n)
     ach = flops / (fwd_ms * 1e-3) / 1e12
     steps_total = B * iters * len(lams)
     out = dict(metric="experiment-loss Adam iterations/s (waveform-iterations)", unit="waveform-iterations/s",
@@ -496,7 +556,8 @@ def bench_experiment(args, torch):
                roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                              frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
                              kernel="forward pass with the hard-PSL maximum (one N-point transform per lag)",
-                             kernel_ms=round(fwd_ms, 5), flops_per_launch=flops))
+                             kernel_ms=round(fwd_ms, 5), flops_per_launch=flops,
+                             executed_transform_flops=exec_flops))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_experiment(n, phases, budget_s=10.0)
     return out
@@ -559,9 +620,11 @@ def bench_cross(args, torch):
     ms = timed(step, args.steps, torch)
     fwd_ms = timed(lambda: plan.cross_forward(s, u, mag=True), 20, torch)
     bwd_ms = timed(lambda: plan.cross_backward(s, u, g_up, ws=ws), 20, torch)
-    # per row: two M/2-point transforms forward, and as many inverse in the backward
-    half = fft_flops(2 * rows * B, m // 2)
-    flops_bwd = 2.0 * half
+    # algorithmic: two M-point transforms per cell (the spectrum and the
+    # adjoint's inverse); executed: per row two M/2-point transforms forward
+    # and as many inverse
+    flops_bwd = alg_fft_flops(cells, m)
+    exec_flops = 2.0 * fft_flops(2 * rows * B, m // 2)
     ach = flops_bwd / (bwd_ms * 1e-3) / 1e12
     log("cross: %.4f ms/step (forward %.4f, backward %.4f)" % (ms, fwd_ms, bwd_ms))
     out = dict(value=cells / (ms * 1e-3), ms_per_step=ms,
@@ -572,7 +635,8 @@ def bench_cross(args, torch):
                roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                              frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
                              kernel="cross-AF backward (forward + inverse transforms, two-output gather)",
-                             kernel_ms=round(bwd_ms, 5), flops_per_launch=flops_bwd))
+                             kernel_ms=round(bwd_ms, 5), flops_per_launch=flops_bwd,
+                             executed_transform_flops=exec_flops))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_cross(n, m, args.seed, budget_s=10.0)
     return out
@@ -637,8 +701,10 @@ def bench_composite(args, torch):
     end = float(terms[:, 0].mean())
     grad = torch.empty(B * n, dtype=torch.complex64, device="cuda")
     fused_ms = timed(lambda: plan.loss_stage(0, st.s, terms, grad, None, ws=ws, **lp), 20, torch)
-    # per lag pair: one forward and one inverse M-point transform
-    flops = B * 2.0 * fft_flops(n, m)
+    # algorithmic: two M-point transforms per cell; executed: one forward
+    # and one inverse per lag pair
+    flops = alg_fft_flops(cells, m)
+    exec_flops = B * 2.0 * fft_flops(n, m)
     ach = flops / (fused_ms * 1e-3) / 1e12
     log("composite: %.4f ms/step, extended fused pass %.4f ms, mean loss %.4f -> %.4f over %d steps"
         % (ms, fused_ms, start, end, args.steps))
@@ -649,7 +715,8 @@ def bench_composite(args, torch):
                 roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                               frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
                               kernel="extended fused ISL pass (hard-PSL records, L_match, width)",
-                              kernel_ms=round(fused_ms, 5), flops_per_launch=flops))
+                              kernel_ms=round(fused_ms, 5), flops_per_launch=flops,
+                              executed_transform_flops=exec_flops))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_composite(n, m, phases, budget_s=10.0)
     return out
@@ -699,8 +766,14 @@ def main():
     ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: the library's default)")
     ap.add_argument("--sweep", action="store_true", help="single workload: time variants 0, 3, 4, report the best")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--train-steps", type=int, default=3000, help="proposal workload: network training steps")
+    ap.add_argument("--train-steps", type=int, default=10000, help="proposal workload: network training steps")
+    ap.add_argument("--pretrain-steps", type=int, default=0,
+                    help="proposal workload: supervised warm-start steps on plain-optimiser codes (0: none)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time host-launched calls instead of graph replays (for profiler counter runs)")
     args = ap.parse_args()
+    global EAGER
+    EAGER = args.eager
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path; "
               "run with --gpus 1", file=sys.stderr)

@@ -10,11 +10,16 @@ of the ambiguity function.
 Pipeline:
   1. plain optimiser (Adam on phases from random phases) on training
      descriptors -> target codes;
-  2. supervised pre-training on those codes (global-phase invariant loss);
+  2. supervised pre-training on those codes, with a loss invariant under the
+     symmetries that leave the weighted ISL unchanged: a global phase, a
+     linear phase ramp, time reversal and conjugation (|chi| is the same
+     under the first three and mirrored in k under the last, and W depends
+     on |k_c| only);
   3. fine-tuning through the differentiable AF loss: d -> net -> phi -> s ->
      weighted ISL -> dL/d conj(s) -> dL/dphi -> net backward -> Adam;
   4. use: net(d) then a few plain refinement steps.
 """
+import math
 import time
 
 import numpy as np
@@ -71,6 +76,45 @@ def weighted_isl(db, phi):
     return terms[:, 1]
 
 
+RAMP_OVERSAMPLE = 8  # linear-phase slopes searched on a grid of 2 pi / (8 N)
+
+
+def alignment_loss(phi, target_phi):
+    """Symmetry-invariant distance between phase codes [B, N] and its
+    gradient.  |chi|, and with it the weighted ISL (whose weights depend on
+    |tau| and |k_c| only), is unchanged by a global phase, a linear phase
+    ramp (a frequency offset multiplies each lag product by a constant),
+    time reversal and conjugation.  Per code the loss is
+    1 - max |mean_n e^{j(phi_n - phi'_n - a n)}| over the four images phi'
+    of the target (itself, reversed, conjugated, both) and the ramp slope a
+    (on a grid of RAMP_OVERSAMPLE N slopes, by an FFT); the global phase is
+    maximised in closed form by the modulus.  Averaged over the batch.
+    Returns (loss, dloss/dphi), the gradient taken at the best image and
+    slope."""
+    B, n = phi.shape
+    rev = torch.flip(target_phi, dims=[1])
+    images = torch.stack([target_phi, rev, -target_phi, -rev])  # [4, B, N]
+    e = torch.polar(torch.ones_like(images), phi.unsqueeze(0) - images)
+    K = RAMP_OVERSAMPLE * n
+    zs = torch.fft.fft(e, n=K, dim=2) / n  # z(a_j), a_j = 2 pi j / K
+    mag = zs.abs()
+    best_j = mag.argmax(dim=2)  # [4, B]
+    best_val = mag.gather(2, best_j.unsqueeze(2)).squeeze(2)  # [4, B]
+    best_i = best_val.argmax(dim=0)  # [B]: the image closest to the code
+    rows = torch.arange(B, device=phi.device)
+    jb = best_j[best_i, rows]  # [B]
+    a = (2.0 * math.pi / K) * jb.to(phi.dtype)
+    nn = torch.arange(n, device=phi.device, dtype=phi.dtype)
+    eb = e[best_i, rows] * torch.polar(torch.ones_like(phi), -a.unsqueeze(1) * nn.unsqueeze(0))
+    zb = eb.mean(dim=1, keepdim=True)
+    az = zb.abs().clamp_min(1e-12)
+    loss = float((1 - az).mean())
+    # with e_n = e^{j(phi_n - phi'_n - a n)}, dz/dphi_n = j e_n / N, so
+    # d(1 - |z|)/dphi_n = Im(conj(z) e_n) / (N |z|); averaged over the batch
+    dphi = (torch.conj(zb) * eb).imag / (az * n * B)
+    return loss, dphi.contiguous()
+
+
 class Proposer:
     """The network and its two training stages."""
 
@@ -83,16 +127,10 @@ class Proposer:
         return phi
 
     def pretrain_step(self, d, target_phi, lr=1e-3):
-        """Global-phase invariant alignment: L = mean_b (1 - |mean_n e^{j(phi - phi*)}|)."""
+        """Supervised step towards plain-optimiser codes with the
+        symmetry-invariant alignment loss."""
         phi, cache = self.net.forward(d)
-        delta = phi - target_phi
-        e = torch.polar(torch.ones_like(delta), delta)
-        z = e.mean(dim=1, keepdim=True)
-        az = z.abs().clamp_min(1e-12)
-        loss = float((1 - az).mean())
-        # d(1 - |z|)/d phi_n = Im(conj(z) e_n) / (N |z|), averaged over the batch
-        dphi = (torch.conj(z) * e).imag / (az * self.n * d.shape[0])
-        dphi = dphi.contiguous()
+        loss, dphi = alignment_loss(phi, target_phi)
         dW, db_ = self.net.backward(dphi, MLPm.to_bf16(dphi), cache)
         self.net.adam(dW, db_, lr=lr)
         return loss
@@ -125,6 +163,13 @@ def time_to_target(traj, target, step_ms, offset_ms=0.0):
     return ms
 
 
+def median_all(t):
+    """Median over every descriptor, those that never reach the target
+    counted as inf (the lower median of an even count)."""
+    v, _ = torch.sort(t.double())
+    return float(v[(v.numel() - 1) // 2])
+
+
 def timed_ms(fn):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -133,17 +178,28 @@ def timed_ms(fn):
     return out, (time.perf_counter() - t0) * 1e3
 
 
-def train(proposer, n, m, batch=512, steps=3000, lr=1e-3, lr_late=3e-4, seed=1, pretrain_steps=0,
-          pretrain_plain_steps=2000, log=None):
+def train(proposer, n, m, batch=4096, steps=3000, lr=1e-3, lr_late=3e-4, seed=1, pretrain_steps=0,
+          pretrain_draws=2, pretrain_plain_steps=2000, log=None):
     """Fine-tune through the AF loss on fresh descriptor draws (same mainlobes,
-    new shaping weights every step); optional supervised warm start on codes
-    the plain optimiser finds for the first draw."""
+    new shaping weights every step); with pretrain_steps > 0, first a
+    supervised warm start on the codes the plain optimiser finds for
+    pretrain_draws draws of the shaping weights (symmetry-invariant loss)."""
     tr = DescriptorBatch(n, m, batch, seed=seed)
     if pretrain_steps:
-        st, _ = plain_optimize(tr, pretrain_plain_steps, lr=0.01, seed=seed + 7)
-        tgt = st.phi.view(batch, n).clone()
-        for _ in range(pretrain_steps):
-            proposer.pretrain_step(tr.d, tgt, lr=lr)
+        sets = []
+        for k in range(pretrain_draws):
+            if k:
+                tr.resample_shaping(seed * 7919 + k)
+            st, traj = plain_optimize(tr, pretrain_plain_steps, lr=0.01, seed=seed + 7 + k)
+            sets.append((tr.d.clone(), st.phi.view(batch, n).clone()))
+            if log:
+                log("pretrain targets %d: plain-%d mean weighted ISL %.3f" % (k, pretrain_plain_steps,
+                                                                             float(traj[-1].mean())))
+        for it in range(pretrain_steps):
+            d, tgt = sets[it % len(sets)]
+            loss = proposer.pretrain_step(d, tgt, lr=lr)
+            if log and (it % 1000 == 0 or it == pretrain_steps - 1):
+                log("pretrain step %d: alignment loss %.4f" % (it, loss))
     isl = None
     for it in range(steps):
         tr.resample_shaping(seed * 1_000_003 + it)
@@ -170,20 +226,32 @@ def evaluate(proposer, db, plain_steps=2000, refine_steps=50, fallback_steps=200
     within = time_to_target(traj_l[:refine_steps + 1], target, step_ms_l, offset_ms=ms_net)
     fin_p = torch.isfinite(t_plain)
     fin_l = torch.isfinite(t_learned)
+    # ISL at equal wall time: plain after as many steps as the learned path's
+    # proposal + refine_steps take, and the learned path after plain's budget
+    eq_steps = min(plain_steps - 1, int(round((ms_net + refine_steps * step_ms_l) / step_ms)))
     res = dict(
         step_ms=step_ms, net_ms=ms_net, plain_steps=plain_steps, refine_steps=refine_steps,
         isl_random=float(traj_p[0].mean()), isl_plain_final=float(target.mean()),
         isl_proposal=float(traj_l[0].mean()), isl_after_refine=float(traj_l[min(refine_steps, traj_l.shape[0] - 1)].mean()),
         reach_within_refine=float(torch.isfinite(within).float().mean()),
         reach_with_fallback=float(fin_l.float().mean()),
-        median_plain_ms=float(t_plain[fin_p].median()) if bool(fin_p.any()) else float("inf"),
-        median_learned_ms=float(t_learned[fin_l].median()) if bool(fin_l.any()) else float("inf"),
+        reach_plain=float(fin_p.float().mean()),
+        # medians over every descriptor, inf where the target is never reached
+        median_plain_ms=median_all(t_plain),
+        median_learned_ms=median_all(t_learned),
+        # medians over the descriptors that reach it (reported, not compared)
+        median_plain_reached_ms=float(t_plain[fin_p].median()) if bool(fin_p.any()) else float("inf"),
+        median_learned_reached_ms=float(t_learned[fin_l].median()) if bool(fin_l.any()) else float("inf"),
         learned_faster_frac=float((t_learned < t_plain).float().mean()),
+        equal_time_steps=eq_steps,
+        isl_plain_at_equal_time=float(traj_p[eq_steps].mean()),
+        isl_learned_after_plain_budget=float(traj_l[min(plain_steps, traj_l.shape[0] - 1)].mean()),
         phi_plain=st_p.phi, phi_learned_refined=st_l.phi, traj_learned=traj_l, traj_plain=traj_p)
     if log:
         log("evaluate: plain %.3f ms/step; ISL random %.2f plain-%d %.2f proposal %.2f +%d refine %.2f; "
-            "reach within %d: %.3f, with fallback %.3f; median time plain %.1f ms learned %.1f ms"
+            "reach within %d: %.3f, with fallback %.3f; median time (all descriptors, inf if never) plain %.1f "
+            "ms learned %.1f ms; plain at equal time (%d steps) %.2f"
             % (step_ms, res["isl_random"], plain_steps, res["isl_plain_final"], res["isl_proposal"], refine_steps,
                res["isl_after_refine"], refine_steps, res["reach_within_refine"], res["reach_with_fallback"],
-               res["median_plain_ms"], res["median_learned_ms"]))
+               res["median_plain_ms"], res["median_learned_ms"], eq_steps, res["isl_plain_at_equal_time"]))
     return res
