@@ -247,15 +247,17 @@ def bench_uneven(args, torch):
     from paper_2506_22935_amd import af, workloads as W
     ns, ms, phases = W.uneven_batch(512, seed=args.seed)
     cells = int(sum((2 * n - 1) * m for n, m in zip(ns, ms)))
-    plan = af.Plan(ns.tolist(), ms.tolist(), eps=1e-12, variant=args.variant)
+    plan = af.Plan(ns.tolist(), ms.tolist(), eps=1e-12, variant=args.variant, one_launch=not args.per_class)
     log("uneven: %d waveforms, %.3g cells, %d segments" % (len(ns), cells, plan.summary()["segments"]))
     st = af.PhaseState(torch.from_numpy(np.concatenate(phases).astype(np.float32)).cuda())
     tuned = None
-    if args.variant < 0:
-        # the plan's autotuner times every variant that fits each size class
+    if args.variant < 0 and not args.per_class:
+        # the plan's autotuner times every variant that fits each size class,
+        # the tuned classes together, and one launch of all of them
         v, tms = plan.autotune(st.s)
-        tuned = dict(largest_class_variant=v, tuned_pass_ms=round(tms, 4))
-        log("autotuned: largest class -> variant %d, %.3f ms per fused pass" % (v, tms))
+        tuned = dict(variant=v, one_launch=bool(v == 6), tuned_pass_ms=round(tms, 4))
+        log("autotuned: variant %d (%s), %.3f ms per forward + fused pass"
+            % (v, "one launch" if v == 6 else "largest class", tms))
     terms = torch.empty(plan.batch, 4, device="cuda")
     ws = plan.workspace
     for _ in range(args.warmup):
@@ -285,6 +287,8 @@ def bench_uneven(args, torch):
                config=dict(workload="uneven: 512 random-phase codes, N log-uniform [64,4096], M=next pow2>=2N, "
                                     "full lag grid, ISL fwd+bwd + Adam step, %d steps in one HIP graph" % args.steps,
                            waveforms=len(ns), cells=cells, segments=plan.summary()["segments"], autotune=tuned,
+                           launches=("one persistent launch over one work queue" if plan.summary()["variant"] == 6
+                                     else "one persistent launch per size class, classes concurrent"),
                            isl_sum_before=isl0, isl_sum_after=isl1),
                roofline=dict(bound="alu", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                              frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None,
@@ -769,6 +773,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=10000, help="proposal workload: network training steps")
     ap.add_argument("--pretrain-steps", type=int, default=0,
                     help="proposal workload: supervised warm-start steps on plain-optimiser codes (0: none)")
+    ap.add_argument("--per-class", action="store_true",
+                    help="uneven workload: one launch per size class (default variants), not one launch for all")
     ap.add_argument("--eager", action="store_true",
                     help="time host-launched calls instead of graph replays (for profiler counter runs)")
     args = ap.parse_args()

@@ -90,10 +90,17 @@ typedef struct {
     float eps;                 /* eps in a = sqrt(p + eps); e.g. 1e-12 */
     int32_t store_mode;        /* 0: decide by budget, 1: store spectra, 2: recompute */
     int64_t budget_bytes;      /* workspace budget; <= 0 means unlimited */
-    int32_t variant;           /* -1: library default; >= 0 forces a kernel variant */
+    int32_t variant;           /* -1: library default; >= 0 forces a kernel variant (6:
+                                  the one-launch kernel, for every size class) */
     int32_t segment_iters;     /* lag iterations per work item; 0: planner's choice */
     int32_t loss_passes;       /* 0: af_loss / af_optim_step use one fused pass where the
                                   loss allows it; 1: always a forward then a backward pass */
+    int32_t launch_mode;       /* 0: waveforms of several sizes (Doppler size classes,
+                                  M <= 8192, one lag kind) run in one persistent launch
+                                  over one longest-first work queue (variant 6); 1: one
+                                  persistent launch per size class, the classes
+                                  concurrent on library-owned streams (Sec. 4.3, batch
+                                  processing) */
 } af_plan_opts;
 
 typedef struct af_plan af_plan;

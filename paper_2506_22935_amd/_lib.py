@@ -28,7 +28,8 @@ class AfWave(ctypes.Structure):
 class AfPlanOpts(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_float), ("store_mode", ctypes.c_int32),
                 ("budget_bytes", ctypes.c_int64), ("variant", ctypes.c_int32),
-                ("segment_iters", ctypes.c_int32), ("loss_passes", ctypes.c_int32)]
+                ("segment_iters", ctypes.c_int32), ("loss_passes", ctypes.c_int32),
+                ("launch_mode", ctypes.c_int32)]
 
 
 class AfLossParams(ctypes.Structure):

@@ -39,7 +39,7 @@ class Plan:
     """
 
     def __init__(self, lengths, ms, max_lags=None, h_tau=1, h_k=1, eps=1e-12, store_mode=0,
-                 budget_bytes=0, variant=-1, segment_iters=0, loss_passes=0, periodic=False):
+                 budget_bytes=0, variant=-1, segment_iters=0, loss_passes=0, periodic=False, one_launch=True):
         lengths = [int(n) for n in lengths]
         ms = [int(m) for m in ms]
         B = len(lengths)
@@ -70,7 +70,7 @@ class Plan:
         self.total_samples, self.total_cells = s_off, g_off
         opts = L.AfPlanOpts(eps=float(eps), store_mode=int(store_mode), budget_bytes=int(budget_bytes),
                             variant=int(variant), segment_iters=int(segment_iters),
-                            loss_passes=int(loss_passes))
+                            loss_passes=int(loss_passes), launch_mode=0 if one_launch else 1)
         h = ctypes.c_void_p()
         L.check("af_plan_create", L.lib().af_plan_create(B, waves, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h

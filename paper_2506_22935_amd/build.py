@@ -28,7 +28,8 @@ def _units():
     units = [("af_api.hip", [], "af_api.o"),
              ("af_reduce.hip", [], "af_reduce.o"),
              ("mlp_kernels.hip", [], "mlp_kernels.o"),
-             ("af_cross.hip", [], "af_cross.o")]
+             ("af_cross.hip", [], "af_cross.o"),
+             ("af_union.hip", [], "af_union.o")]
     for v in range(N_VARIANTS):
         units.append(("af_variant.hip", ["-DGRAF_VARIANT=%d" % v], "af_variant%d.o" % v))
     return [u for u in units if os.path.exists(os.path.join(CSRC, u[0]))]

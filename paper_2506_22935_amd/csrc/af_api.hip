@@ -29,6 +29,7 @@ constexpr int kMaxM = 32768;
 constexpr int kMinCircN = 64;   // periodic AF: N = M, the split variants' sizes
 constexpr int kMaxCircN = 4096;
 constexpr int kMaxSpecN = 4096;  // spectral variance: three N-vectors in LDS
+constexpr int kMaxQueues = 64;   // ticket counters: at most one per class (2 kinds x 9 sizes)
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 int ilog2(int64_t x) {
@@ -105,7 +106,15 @@ struct af_plan {
         double cost = 0.0;
     };
     std::vector<Class> classes;
-    std::vector<int> forced;  // per class: variant forced by the autotuner (-1: default)
+    std::vector<int> forced;  // per natural class: variant forced by the autotuner (-1: default)
+    int natural_classes = 0;  // distinct (transform size, lag kind) pairs
+    bool one_launch = true;   // run several classes as one launch of the one-launch kernel when they fit it
+    bool one_active = false;  // the current schedule is that one launch
+    // cross-AF launches: one per natural class over its slice of d_segs_x
+    struct XClass {
+        int lg = 0, circ = 0, begin = 0, count = 0;
+    };
+    std::vector<XClass> xclasses;
     std::vector<WaveDesc> wave_desc;  // host copy of the device descriptors
     int opt_variant = -1;
     bool stores = false;
@@ -120,22 +129,62 @@ struct af_plan {
     // plan-owned device tables
     WaveDesc* d_waves = nullptr;
     SegDesc* d_segs = nullptr;
+    SegDesc* d_segs_x = nullptr;       // the segments in natural-class order (one-launch plans)
     graf::RBlock* d_chunks = nullptr;  // reduce blocks
     float2* d_tw = nullptr;
-    size_t cap_segs = 0, cap_chunks = 0;
+    int* d_queue = nullptr;            // ticket counters of the one-launch kernel, one per class
+    size_t cap_segs = 0, cap_chunks = 0, cap_segs_x = 0;
+
+    // Plans with several size classes run them concurrently: class 0 (the
+    // largest) on the caller's stream, class c > 0 on side[c - 1], forked
+    // from and joined back into the caller's stream with events, so that a
+    // class's tail overlaps the next classes' work instead of draining the
+    // GPU between launches.  Default-priority streams; capturable.
+    std::vector<hipStream_t> side;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
 };
 
 namespace {
 
+void free_streams(af_plan* p) {
+    for (hipStream_t s : p->side) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : p->join) (void)hipEventDestroy(e);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    p->side.clear();
+    p->join.clear();
+    p->fork = nullptr;
+}
+
+// side streams and events for C concurrent classes
+af_status make_streams(af_plan* p, int C) {
+    if (C <= 1) return AF_OK;
+    if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess) return AF_ERR_HIP;
+    for (int c = 1; c < C; ++c) {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return AF_ERR_HIP;
+        p->side.push_back(s);
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return AF_ERR_HIP;
+        p->join.push_back(e);
+    }
+    return AF_OK;
+}
+
 void free_tables(af_plan* p) {
+    free_streams(p);
     if (p->d_waves) (void)hipFree(p->d_waves);
     if (p->d_segs) (void)hipFree(p->d_segs);
+    if (p->d_segs_x) (void)hipFree(p->d_segs_x);
     if (p->d_chunks) (void)hipFree(p->d_chunks);
     if (p->d_tw) (void)hipFree(p->d_tw);
+    if (p->d_queue) (void)hipFree(p->d_queue);
     p->d_waves = nullptr;
     p->d_segs = nullptr;
+    p->d_segs_x = nullptr;
     p->d_chunks = nullptr;
     p->d_tw = nullptr;
+    p->d_queue = nullptr;
 }
 
 // Periodic (circular) waveforms: N = M bins, run as the even half of the
@@ -184,23 +233,40 @@ af_status build_schedule(af_plan* p) {
     std::sort(keys.begin(), keys.end());
     keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
     std::reverse(keys.begin(), keys.end());
-    const int C = (int)keys.size();
-    if ((int)p->forced.size() != C) p->forced.assign(C, -1);
+    const int NC = (int)keys.size();
+    p->natural_classes = NC;
+    if ((int)p->forced.size() != NC) p->forced.assign(NC, -1);
+    // one launch for every class: the classes share a lag kind and each fits
+    // the one-launch kernel; by default for plans with several classes,
+    // always when that variant is asked for, never once the autotuner has
+    // forced variants per class
+    bool union_ok = true, forced_any = false;
+    for (int key : keys)
+        if ((key & 1) != (keys[0] & 1) || !graf::variant_info(graf::kUnionVariant, key >> 1).fits) union_ok = false;
+    for (int f : p->forced) forced_any = forced_any || f >= 0;
+    if (p->opt_variant == graf::kUnionVariant && !union_ok) return AF_ERR_UNSUPPORTED;
+    const bool one = union_ok && !forced_any &&
+                     (p->opt_variant == graf::kUnionVariant || (p->opt_variant < 0 && p->one_launch && NC > 1));
+    const int C = one ? 1 : NC;
     std::vector<af_plan::Class> cls(C);
-    std::vector<int> cls_of_wave(B);
+    std::vector<int> cls_of_wave(B), nat_of_wave(B);
     for (int b = 0; b < B; ++b) {
         const int key = 2 * (ilog2(kernel_m(p->waves[b])) - 1) + (is_circ(p->waves[b]) ? 1 : 0);
-        const int c = (int)(std::find(keys.begin(), keys.end(), key) - keys.begin());
+        const int nat = (int)(std::find(keys.begin(), keys.end(), key) - keys.begin());
+        const int c = one ? 0 : nat;
+        nat_of_wave[b] = nat;
         cls_of_wave[b] = c;
-        cls[c].lg = key >> 1;
+        cls[c].lg = std::max(cls[c].lg, key >> 1);
         cls[c].circ = key & 1;
         cls[c].max_n = std::max(cls[c].max_n, p->waves[b].n);
     }
     int total_slots = 0;
     for (int c = 0; c < C; ++c) {
         af_plan::Class& k = cls[c];
-        int v = p->forced[c];
-        if (v < 0 && p->opt_variant >= 0 && variant_fits(p->opt_variant, k.lg, k.max_n, k.circ)) v = p->opt_variant;
+        int v = one ? graf::kUnionVariant : p->forced[c];
+        if (v < 0 && p->opt_variant >= 0 && p->opt_variant != graf::kUnionVariant &&
+            variant_fits(p->opt_variant, k.lg, k.max_n, k.circ))
+            v = p->opt_variant;
         if (v < 0) v = default_variant(k.lg, k.max_n, k.circ);
         if (v < 0 || !variant_fits(v, k.lg, k.max_n, k.circ)) return AF_ERR_UNSUPPORTED;
         k.variant = v;
@@ -233,7 +299,10 @@ af_status build_schedule(af_plan* p) {
         cost_iter[b] = (double)lpi[b] * (k.circ ? mk / 2 : mk) * ilog2(mk);
         total += iters[b] * cost_iter[b];
     }
-    const double target = total / (2.0 * std::max(1, total_slots));
+    // about two items per resident work group; six for the one-launch
+    // kernel, whose work groups take items from one queue by ticket, so that
+    // the queue's last items are short
+    const double target = total / ((one ? 6.0 : 2.0) * std::max(1, total_slots));
 
     std::vector<WaveDesc> wd(B);
     std::vector<SegDesc> segs;
@@ -310,6 +379,24 @@ af_status build_schedule(af_plan* p) {
     std::vector<SegDesc> exec(order.size());
     for (size_t i = 0; i < order.size(); ++i) exec[i] = segs[order[i]];
 
+    // cross-AF launches: one per natural class; with one launch they run
+    // over a second copy of the segments in natural-class order
+    std::vector<af_plan::XClass> xcls(NC);
+    std::vector<SegDesc> exec_x;
+    for (int c = 0; c < NC; ++c) {
+        xcls[c].lg = keys[c] >> 1;
+        xcls[c].circ = keys[c] & 1;
+        if (one) {
+            xcls[c].begin = (int)exec_x.size();
+            for (const SegDesc& sd : segs)
+                if (nat_of_wave[sd.wave] == c) exec_x.push_back(sd);
+            xcls[c].count = (int)exec_x.size() - xcls[c].begin;
+        } else {
+            xcls[c].begin = cls[c].begin;
+            xcls[c].count = cls[c].count;
+        }
+    }
+
     // workspace layout and the store decision
     const size_t parts_b = align256(segs.size() * sizeof(graf::Part));
     const size_t energy_b = align256((size_t)B * sizeof(float));
@@ -352,6 +439,15 @@ af_status build_schedule(af_plan* p) {
         if (hipMalloc(&p->d_chunks, rblocks.size() * sizeof(graf::RBlock)) != hipSuccess) return hip_fail();
         p->cap_chunks = rblocks.size();
     }
+    if (one && exec_x.size() > p->cap_segs_x) {
+        if (p->d_segs_x) (void)hipFree(p->d_segs_x);
+        p->d_segs_x = nullptr;
+        if (hipMalloc(&p->d_segs_x, exec_x.size() * sizeof(SegDesc)) != hipSuccess) return hip_fail();
+        p->cap_segs_x = exec_x.size();
+    }
+    if (one && hipMemcpy(p->d_segs_x, exec_x.data(), exec_x.size() * sizeof(SegDesc), hipMemcpyHostToDevice) !=
+                   hipSuccess)
+        return hip_fail();
     if (!p->d_waves && hipMalloc(&p->d_waves, (size_t)B * sizeof(WaveDesc)) != hipSuccess) return hip_fail();
     if (hipMemcpy(p->d_waves, wd.data(), (size_t)B * sizeof(WaveDesc), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_segs, exec.data(), exec.size() * sizeof(SegDesc), hipMemcpyHostToDevice) != hipSuccess ||
@@ -370,6 +466,8 @@ af_status build_schedule(af_plan* p) {
     }
     p->wave_desc = wd;
     p->classes = cls;
+    p->xclasses = xcls;
+    p->one_active = one;
     p->stores = stores;
     p->n_segs = (int)segs.size();
     p->n_chunks = (int)rblocks.size();
@@ -390,6 +488,7 @@ af_status validate_plan_inputs(int32_t batch, const af_wave* waves, const af_pla
     if (batch <= 0 || !waves || !opts) return AF_ERR_INVALID_ARG;
     if (!(opts->eps >= 0.f) || opts->store_mode < 0 || opts->store_mode > 2) return AF_ERR_INVALID_ARG;
     if (opts->loss_passes < 0 || opts->loss_passes > 1) return AF_ERR_INVALID_ARG;
+    if (opts->launch_mode < 0 || opts->launch_mode > 1) return AF_ERR_INVALID_ARG;
     for (int b = 0; b < batch; ++b) {
         const af_wave& w = waves[b];
         if (w.n < 1 || w.s_off < 0 || w.grid_off < 0 || w.h_tau < 0 || w.h_k < 0 || (w.flags & ~AF_WAVE_PERIODIC))
@@ -470,11 +569,21 @@ ReduceArgs reduce_args(const af_plan* p, const void* s, const WsView& v) {
     return r;
 }
 
-// one persistent launch per size class, each on its own slice of the order
+// one persistent launch per size class, each on its own slice of the order;
+// with several classes, class c > 0 runs on its side stream between a fork
+// from and a join into st
 af_status launch(const af_plan* p, int mode, const AfArgs& a0, hipStream_t st, int only_class = -1) {
-    for (int c = 0; c < (int)p->classes.size(); ++c) {
+    const int C = (int)p->classes.size();
+    const bool concurrent = only_class < 0 && C > 1 && (int)p->side.size() >= C - 1;
+    if (concurrent) {
+        if (hipEventRecord(p->fork, st) != hipSuccess) return AF_ERR_HIP;
+        for (int c = 1; c < C; ++c)
+            if (hipStreamWaitEvent(p->side[c - 1], p->fork, 0) != hipSuccess) return AF_ERR_HIP;
+    }
+    for (int c = 0; c < C; ++c) {
         if (only_class >= 0 && c != only_class) continue;
         const af_plan::Class& k = p->classes[c];
+        hipStream_t cs = (concurrent && c > 0) ? p->side[c - 1] : st;
         AfArgs a = a0;
         a.segs = p->d_segs + k.begin;
         a.n_segs = k.count;
@@ -483,8 +592,19 @@ af_status launch(const af_plan* p, int mode, const AfArgs& a0, hipStream_t st, i
             a.w0 = p->wave_desc[k.single_wave];
             a.w0_index = k.single_wave;
         }
-        hipError_t e = graf::launch_af(mode, k.variant, k.lg, k.circ, a, k.grid[mode], k.dyn_lds, st);
+        if (k.variant == graf::kUnionVariant) {
+            // the one-launch kernel takes items by ticket from a zeroed counter
+            a.queue = p->d_queue + c;
+            if (graf::launch_queue_reset(a.queue, cs) != hipSuccess) return AF_ERR_HIP;
+        }
+        hipError_t e = graf::launch_af(mode, k.variant, k.lg, k.circ, a, k.grid[mode], k.dyn_lds, cs);
         if (e != hipSuccess) return AF_ERR_HIP;
+    }
+    if (concurrent) {
+        for (int c = 1; c < C; ++c) {
+            if (hipEventRecord(p->join[c - 1], p->side[c - 1]) != hipSuccess) return AF_ERR_HIP;
+            if (hipStreamWaitEvent(st, p->join[c - 1], 0) != hipSuccess) return AF_ERR_HIP;
+        }
     }
     return AF_OK;
 }
@@ -724,6 +844,7 @@ af_status af_plan_create(int32_t batch, const af_wave* waves, const af_plan_opts
     p->budget = opts->budget_bytes;
     p->seg_iters_opt = opts->segment_iters;
     p->loss_passes_opt = opts->loss_passes;
+    p->one_launch = opts->launch_mode == 0;
     p->log2_mmax = ilog2(mmax);
 
     // twiddles exp(-j 2 pi i / MMAX), computed in double, rounded once
@@ -746,6 +867,12 @@ af_status af_plan_create(int32_t batch, const af_wave* waves, const af_plan_opts
         free_tables(p);
         delete p;
         return rc;
+    }
+    if (hipMalloc(&p->d_queue, kMaxQueues * sizeof(int)) != hipSuccess ||
+        make_streams(p, p->natural_classes) != AF_OK) {
+        free_tables(p);
+        delete p;
+        return AF_ERR_HIP;
     }
     // this device's copy of af_loss_no_alloc's workspace, once per device; a
     // failure only disables that entry point
@@ -912,7 +1039,7 @@ af_status af_scenario_combine(const af_plan* p, int32_t n_scen, const float* gri
 namespace {
 af_status check_cross(const af_plan* p, const void* s, const void* u) {
     if (!p || !s || !u || !aligned(s, 8) || !aligned(u, 8)) return AF_ERR_INVALID_ARG;
-    for (const af_plan::Class& k : p->classes)
+    for (const af_plan::XClass& k : p->xclasses)
         if (k.circ || !graf::cross_lg_supported(k.lg)) return AF_ERR_UNSUPPORTED;
     // the kernels move the a and dL/da grids as 8-byte bin pairs
     for (const af_wave& w : p->waves)
@@ -936,8 +1063,9 @@ graf::CrossArgs cross_args(const af_plan* p, const void* s, const void* u) {
     return a;
 }
 af_status launch_cross_classes(const af_plan* p, int mode, graf::CrossArgs a, hipStream_t st) {
-    for (const af_plan::Class& k : p->classes) {
-        a.segs = p->d_segs + k.begin;
+    const SegDesc* segs = p->one_active ? p->d_segs_x : p->d_segs;
+    for (const af_plan::XClass& k : p->xclasses) {
+        a.segs = segs + k.begin;
         if (graf::launch_cross(mode, k.lg, a, k.count, st) != hipSuccess) return AF_ERR_HIP;
     }
     return AF_OK;
@@ -1033,53 +1161,78 @@ af_status af_plan_autotune(af_plan* p, const void* s, void* ws, size_t ws_bytes,
     std::memset(&lp, 0, sizeof(lp));
     lp.w_isl = 1.f;
     lp.psl_temp = 0.05f;
-    const int C = (int)p->classes.size();
-    std::vector<int> best(C, -1);
-    float total_best = 0.f;
+    // ms per forward + fused loss pass of one class (c >= 0) or of the whole
+    // plan (c < 0, classes concurrent), or < 0 when the schedule does not run
+    auto time_schedule = [&](int c) -> float {
+        if (build_schedule(p) != AF_OK || p->ws_total > ws_bytes) return -1.f;
+        const WsView view = ws_view(p, ws);
+        bool ok = true;
+        for (int it = 0; it < 2 && ok; ++it) ok = loss_passes(p, s, &lp, nullptr, true, view, st, c) == AF_OK;
+        if (!ok || hipStreamSynchronize(st) != hipSuccess) return -1.f;
+        const int reps = 5;
+        (void)hipEventRecord(e0, st);
+        for (int it = 0; it < reps && ok; ++it) {
+            AfArgs a = base_args(p, s, view);
+            ok = launch(p, graf::MODE_FWD, a, st, c) == AF_OK && loss_passes(p, s, &lp, nullptr, true, view, st, c) == AF_OK;
+        }
+        (void)hipEventRecord(e1, st);
+        if (!ok || hipEventSynchronize(e1) != hipSuccess) return -1.f;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms / reps;
+    };
+    const bool one_before = p->one_launch;
+    const std::vector<int> forced_before = p->forced;
     af_status rc = AF_OK;
-    // time each class with every variant that fits it, forward + fused loss
-    for (int c = 0; c < C && rc == AF_OK; ++c) {
+    // 1. per class: every variant that fits the class, the class timed alone
+    p->one_launch = false;
+    p->forced.assign(p->natural_classes, -1);
+    if (build_schedule(p) != AF_OK) rc = AF_ERR_UNSUPPORTED;
+    const int NC = p->natural_classes;
+    std::vector<af_plan::Class> nat = p->classes;
+    std::vector<int> best(NC, -1);
+    for (int c = 0; c < NC && rc == AF_OK; ++c) {
         float best_t = 0.f;
         for (int v = 0; v < graf::kNumVariants; ++v) {
-            if (!variant_fits(v, p->classes[c].lg, p->classes[c].max_n, p->classes[c].circ)) continue;
+            if (v == graf::kUnionVariant || !variant_fits(v, nat[c].lg, nat[c].max_n, nat[c].circ)) continue;
             p->forced[c] = v;
-            if (build_schedule(p) != AF_OK || p->ws_total > ws_bytes) continue;
-            const WsView view = ws_view(p, ws);
-            bool ok = true;
-            for (int it = 0; it < 2 && ok; ++it) ok = loss_passes(p, s, &lp, nullptr, true, view, st, c) == AF_OK;
-            if (!ok || hipStreamSynchronize(st) != hipSuccess) continue;
-            const int reps = 5;
-            (void)hipEventRecord(e0, st);
-            for (int it = 0; it < reps && ok; ++it) {
-                AfArgs a = base_args(p, s, view);
-                ok = launch(p, graf::MODE_FWD, a, st, c) == AF_OK &&
-                     loss_passes(p, s, &lp, nullptr, true, view, st, c) == AF_OK;
-            }
-            (void)hipEventRecord(e1, st);
-            if (!ok || hipEventSynchronize(e1) != hipSuccess) continue;
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            ms /= reps;
-            if (best[c] < 0 || ms < best_t) {
+            const float ms = time_schedule(c);
+            if (ms >= 0.f && (best[c] < 0 || ms < best_t)) {
                 best[c] = v;
                 best_t = ms;
             }
         }
         if (best[c] < 0) rc = AF_ERR_UNSUPPORTED;
         p->forced[c] = best[c];
-        total_best += best_t;
+    }
+    // 2. the tuned classes together, against one launch of all of them
+    float t_per = -1.f, t_one = -1.f;
+    if (rc == AF_OK) t_per = time_schedule(-1);
+    if (rc == AF_OK && NC > 1) {
+        const std::vector<int> tuned = p->forced;
+        p->forced.assign(NC, -1);
+        p->one_launch = true;
+        if (build_schedule(p) == AF_OK && p->classes.size() == 1 && p->classes[0].variant == graf::kUnionVariant)
+            t_one = time_schedule(-1);
+        if (!(t_one >= 0.f && (t_per < 0.f || t_one < t_per))) {
+            p->one_launch = false;
+            p->forced = tuned;
+            t_one = -1.f;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (rc == AF_OK && t_per < 0.f && t_one < 0.f) rc = AF_ERR_UNSUPPORTED;
     if (rc != AF_OK) {
-        p->forced.assign(C, -1);
+        p->one_launch = one_before;
+        p->forced = forced_before;
         (void)build_schedule(p);
         return rc;
     }
     rc = build_schedule(p);
     if (rc != AF_OK) return rc;
-    if (chosen) *chosen = C ? best[0] : -1;
-    if (best_ms) *best_ms = total_best;
+    if (chosen) *chosen = p->classes.empty() ? -1 : p->classes[0].variant;
+    if (best_ms) *best_ms = t_one >= 0.f ? t_one : t_per;
     return AF_OK;
 }
 

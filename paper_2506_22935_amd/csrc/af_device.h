@@ -286,6 +286,19 @@ struct TwSplit {
     __device__ __forceinline__ float2 operator()(int i) const { return cmul(hi[i >> b], lo[i & ((1 << b) - 1)]); }
 };
 
+// The short tables of the largest transform in a launch serving a smaller
+// one: w_M^i = w_MMAX^(i << sh) with sh = log2(MMAX / M).
+struct TwSplitSh {
+    const float2* hi;
+    const float2* lo;
+    int b;
+    int sh;
+    __device__ __forceinline__ float2 operator()(int i) const {
+        const int j = i << sh;
+        return cmul(hi[j >> b], lo[j & ((1 << b) - 1)]);
+    }
+};
+
 // Pass number PASS (0-based) with stride NS = P^PASS and radix R.
 // in: v laid out as slots [b*R + r] = x[j + r*MH/R], j = l + L*b
 // out: written to LDS y[(j/NS)*NS*R + j%NS + r*NS] unless LAST, in which

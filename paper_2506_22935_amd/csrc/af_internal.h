@@ -99,6 +99,7 @@ struct AfArgs {
     float w_width, gamma; // soft mainlobe width on the k = 0 column (MODE_FWD_EXT / MODE_FUSED_EXT)
     const float* cell_w;  // per-cell weight grid (MODE_FWD_EXT / MODE_FUSED_EXT), nullable
     float w_cell;
+    int* queue;           // one-launch plans: the work-queue ticket counter (zero at launch)
 };
 
 // The slab reduction runs 256-thread blocks over (256 >> sg_log) samples of
@@ -223,10 +224,17 @@ struct VariantInfo {
     int lo, hi, p, split, wgs, s_lds, fits, fft_lds, nacc;
     int circ;  // has periodic-AF instances
 };
-constexpr int kNumVariants = 6;
+constexpr int kNumVariants = 7;
+// Variant 6 is the one-launch kernel: every size class of a plan (M = 128 to
+// 8192, one lag kind) in one persistent launch over a single longest-first
+// work queue, each work group taking the next item with an atomic ticket.
+constexpr int kUnionVariant = 6;
 VariantInfo variant_info(int v, int lg);
 int variant_max_resident(int mode, int variant, int lg, int circ, int dyn_lds_bytes);
 hipError_t launch_af(int mode, int variant, int lg, int circ, const AfArgs& a, int grid, int dyn_lds_bytes,
                      hipStream_t st);
+// zero the one-launch kernel's ticket counter (a kernel, so that graph
+// capture records no memset node)
+hipError_t launch_queue_reset(int* queue, hipStream_t st);
 
 }  // namespace graf

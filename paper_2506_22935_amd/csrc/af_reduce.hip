@@ -315,12 +315,14 @@ void* variant_kernel_2(int mode, int lg, int circ);
 void* variant_kernel_3(int mode, int lg, int circ);
 void* variant_kernel_4(int mode, int lg, int circ);
 void* variant_kernel_5(int mode, int lg, int circ);
+void* variant_kernel_6(int mode, int lg, int circ);
 VariantInfo variant_info_0(int lg);
 VariantInfo variant_info_1(int lg);
 VariantInfo variant_info_2(int lg);
 VariantInfo variant_info_3(int lg);
 VariantInfo variant_info_4(int lg);
 VariantInfo variant_info_5(int lg);
+VariantInfo variant_info_6(int lg);
 
 VariantInfo variant_info(int v, int lg) {
     switch (v) {
@@ -330,6 +332,7 @@ VariantInfo variant_info(int v, int lg) {
         case 3: return variant_info_3(lg);
         case 4: return variant_info_4(lg);
         case 5: return variant_info_5(lg);
+        case 6: return variant_info_6(lg);
     }
     return VariantInfo{};
 }
@@ -342,6 +345,7 @@ static void* kernel_for(int mode, int variant, int lg, int circ) {
         case 3: return variant_kernel_3(mode, lg, circ);
         case 4: return variant_kernel_4(mode, lg, circ);
         case 5: return variant_kernel_5(mode, lg, circ);
+        case 6: return variant_kernel_6(mode, lg, circ);
     }
     return nullptr;
 }

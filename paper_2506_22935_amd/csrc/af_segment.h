@@ -303,6 +303,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     static_assert(!SPLIT || (2 * BUF * 2 >= 2 * M_), "row staging does not fit");
 
     int tid = threadIdx.x;
+    // an opaque lane index per item: the lane-dependent expressions below
+    // are not hoisted out of a persistent kernel's item loop, where one
+    // kernel serving several transform sizes would keep every size's copies
+    // live across its items
+    asm volatile("" : "+v"(tid));
     const int grp = tid / L;
     int l = tid - grp * L;
     const int lam = (SPLIT && !CIRC) ? (grp >> 1) : grp;
@@ -1141,6 +1146,77 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
         }
         process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG), CIRC, EXTK>(a, sg, lds, twl, s_lds,
                                                                                   V::S_LDS != 0, scratch, st);
+    }
+}
+
+// ------------------------------------------------- one-launch kernel -----
+// Every size class of a plan in one persistent launch: 512-thread work
+// groups, 16 points per lane, split halves, samples in LDS, the twiddles of
+// each class read from the two short tables of the plan's largest transform.
+// The LDS of the transform buffers is the same for every size (WGS P (1 +
+// 1/32) complex values), so one allocation serves all classes; items come
+// from one work queue sorted longest first, taken with an atomic ticket.
+using VU = Variant<16, 1, 512, 2, 6, 12, 1, 0>;
+
+template <int MODE, int LG, bool CIRC, bool EXTK>
+__device__ __forceinline__ void union_item(const AfArgs& a, const SegDesc& sg, WaveState& st, float2* lds,
+                                           float2* s_lds, double* scratch, const TwSplitSh& twl) {
+    if constexpr (VU::fits(LG)) {
+        constexpr int MH = 1 << LG;
+        if (sg.wave != st.wave) {
+            const WaveDesc w = a.waves[sg.wave];
+            stage_wave<MODE, VU::WGS, MH, CIRC>(a, w, sg.wave, s_lds, true, scratch, st, nullptr, 0);
+        }
+        process_segment<MODE, MH, VU::P, VU::SPLIT, VU::WGS, VU::nacc(LG), CIRC, EXTK>(a, sg, lds, twl, s_lds, true,
+                                                                                      scratch, st);
+    }
+}
+
+template <int MODE, bool CIRC = false, bool EXTK = false>
+__global__ __launch_bounds__(VU::WGS, VU::WAVES) void af_union_kernel(AfArgs a) {
+    extern __shared__ float2 dyn[];
+    __shared__ double scratch[112];
+    __shared__ int ticket;
+    constexpr int LGMAX = VU::HI;
+    float2* lds = dyn;
+    // short tables sized for the largest transform the kernel takes; the
+    // plan's largest M = 2^log2_mmax sets the split actually used
+    float2* tw_lo = dyn + VU::buf_lds_bytes(LGMAX) / 8;
+    float2* tw_hi = tw_lo + (1 << VU::split_bits(LGMAX));
+    float2* s_lds = dyn + VU::fft_lds_bytes(LGMAX) / 8;
+    const int b = (a.log2_mmax + 1) / 2;  // split bits of the plan's largest M
+    const int nlo = 1 << b, nhi = (1 << a.log2_mmax) >> b;
+    if (threadIdx.x == 0) ticket = atomicAdd(a.queue, 1);
+    for (int j = threadIdx.x; j < nlo + nhi; j += VU::WGS) {
+        if (j < nlo)
+            tw_lo[j] = a.tw[j];
+        else
+            tw_hi[j - nlo] = a.tw[(j - nlo) << b];
+    }
+    __syncthreads();
+    WaveState st;
+    st.wave = -1;
+    for (;;) {
+        const int item = ticket;  // the same for every thread of the group
+        if (item >= a.n_segs) break;
+        const SegDesc sg = a.segs[item];
+        const int log2m = a.waves[sg.wave].log2m;
+        const TwSplitSh twl{tw_hi, tw_lo, b, a.log2_mmax - log2m};
+        switch (log2m - 1) {
+            case 6: union_item<MODE, 6, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
+            case 7: union_item<MODE, 7, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
+            case 8: union_item<MODE, 8, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
+            case 9: union_item<MODE, 9, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
+            case 10: union_item<MODE, 10, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
+            case 11: union_item<MODE, 11, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
+            case 12: union_item<MODE, 12, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
+            default: break;
+        }
+        // every thread has read this item's ticket (process_segment ends
+        // with a barrier); take the next
+        __syncthreads();
+        if (threadIdx.x == 0) ticket = atomicAdd(a.queue, 1);
+        __syncthreads();
     }
 }
 

@@ -53,7 +53,7 @@ def _create(lib, waves, **opt):
     for k, v in opt.get("fields", {}).items():
         setattr(arr[0], k, v)
     opts = L.AfPlanOpts(eps=1e-12, store_mode=opt.get("store_mode", 0), budget_bytes=0, variant=-1,
-                        segment_iters=0)
+                        segment_iters=0, launch_mode=opt.get("launch_mode", 0))
     h = ctypes.c_void_p()
     rc = lib.af_plan_create(len(waves), arr, ctypes.byref(opts), ctypes.byref(h))
     if rc == 0:
@@ -89,6 +89,8 @@ def test_plan_validation_fields(lib):
     assert _create(lib, [(64, 128, -1)], fields={"grid_off": 2}) == -1
     assert _create(lib, [(64, 128, -1)], fields={"h_tau": -1}) == -1
     assert _create(lib, [(64, 128, -1)], store_mode=3) == -1
+    assert _create(lib, [(64, 128, -1)], launch_mode=2) == -1
+    assert _create(lib, [(64, 128, -1)], launch_mode=-1) == -1
 
 
 def test_null_arguments(lib):

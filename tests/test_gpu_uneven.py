@@ -1,5 +1,6 @@
-"""Uneven batches in one plan (one persistent launch per Doppler size class),
-the optimiser step and its HIP-graph capture (GPU only).
+"""Uneven batches in one plan: every Doppler size class in one persistent
+launch over one work queue (the default), or one launch per class with the
+classes concurrent; the optimiser step and its HIP-graph capture (GPU only).
 
 The batch is the uneven workload: 512 random-phase codes, N log-uniform in
 [64, 4096] (seed 0), M = next power of two >= 2N, full lag grid each, ISL.
@@ -140,3 +141,85 @@ def test_adam_steps_decrease_isl(af):
     torch.cuda.synchronize()
     ref = O.loss_and_grad(sr, m, n - 1, O.LossParams(eps=EPS))
     assert abs(terms[b, 1].item() - ref["isl"]) <= 1e-4 * ref["isl"]
+
+
+def small_uneven(af, count, seed, **kw):
+    ns, ms, phases = W.uneven_batch(count, seed=seed)
+    codes = [W.unimodular(p) for p in phases]
+    plan = af.Plan(ns.tolist(), ms.tolist(), eps=EPS, **kw)
+    return ns, ms, codes, plan, torch.from_numpy(np.concatenate(codes)).cuda()
+
+
+def test_one_launch_matches_per_class_and_oracle(af):
+    # the default plan of an uneven batch is one launch of the one-launch
+    # kernel (variant 6); per-class launches give the same loss and gradient
+    # up to float32 summation order, and both match the oracle
+    say("one launch vs per class")
+    ns, ms, codes, one, s = small_uneven(af, 40, 7)
+    assert len(set(ms.tolist())) > 2
+    assert one.summary()["variant"] == 6
+    per = af.Plan(ns.tolist(), ms.tolist(), eps=EPS, one_launch=False)
+    assert per.summary()["variant"] != 6
+    lp = dict(w_isl=1.0, w_psl=1.0, temp=0.05)
+    t1, g1, a1 = one.loss(s, grad=True, mag=True, **lp)
+    t2, g2, a2 = per.loss(s, grad=True, mag=True, **lp)
+    torch.cuda.synchronize()
+    t1, t2 = t1.cpu().numpy(), t2.cpu().numpy()
+    g1 = g1.cpu().numpy().astype(np.complex128)
+    g2 = g2.cpu().numpy().astype(np.complex128)
+    assert np.allclose(t1, t2, rtol=1e-5, atol=1e-6)
+    assert float((a1 - a2).abs().max()) <= 1e-6
+    for b in range(len(ns)):
+        o, n = one.s_offsets[b], int(ns[b])
+        gb1, gb2 = g1[o:o + n], g2[o:o + n]
+        assert np.max(np.abs(gb1 - gb2)) <= 1e-5 * np.max(np.abs(gb2)), b
+    order = np.argsort(ns)
+    for b in list(order[:3]) + [order[-1]]:
+        n, m = int(ns[b]), int(ms[b])
+        if n > 700:
+            continue
+        ref = O.loss_and_grad(O.to_c64_exact(codes[b]), m, n - 1,
+                              O.LossParams(eps=EPS, h_tau=1, h_k=1, w_isl=1.0, w_psl=1.0, temp=0.05))
+        assert abs(t1[b, 0] - ref["loss"]) <= 1e-4 * abs(ref["loss"])
+        o = one.s_offsets[b]
+        assert np.max(np.abs(g1[o:o + n] - ref["g"])) <= 1e-4 * np.max(np.abs(ref["g"])), b
+
+
+def test_one_launch_is_deterministic(af):
+    # work groups take items by atomic ticket, so the assignment changes from
+    # run to run; every item writes its own slab and record, so the results
+    # may not
+    say("one launch deterministic")
+    ns, ms, codes, plan, s = small_uneven(af, 64, 9)
+    assert plan.summary()["variant"] == 6
+    outs = []
+    for _ in range(3):
+        t, g, _ = plan.loss(s, w_isl=1.0, grad=True)
+        outs.append((t.cpu(), g.cpu()))
+    torch.cuda.synchronize()
+    for t, g in outs[1:]:
+        assert torch.equal(t, outs[0][0]) and torch.equal(g, outs[0][1])
+
+
+def test_one_launch_periodic_sizes(af):
+    # periodic waveforms of five sizes (N = M = 64 ... 4096) in one launch,
+    # ISL + soft-PSL against the oracle's periodic loss
+    say("one launch periodic")
+    ns = [64, 4096, 128, 256, 1024, 64, 512]
+    codes = [W.complex_gaussian(n, seed=900 + i) for i, n in enumerate(ns)]
+    plan = af.Plan(ns, ns, eps=EPS, periodic=True)
+    assert plan.summary()["variant"] == 6
+    s = torch.from_numpy(np.concatenate(codes)).cuda()
+    lp = dict(w_isl=1.0, w_psl=1.0, temp=0.05)
+    t, g, _ = plan.loss(s, grad=True, **lp)
+    torch.cuda.synchronize()
+    t = t.cpu().numpy()
+    g = g.cpu().numpy().astype(np.complex128)
+    for b, n in enumerate(ns):
+        if n > 1024:
+            continue
+        ref = O.loss_and_grad_circular(O.to_c64_exact(codes[b]),
+                                       O.LossParams(eps=EPS, h_tau=1, h_k=1, w_isl=1.0, w_psl=1.0, temp=0.05))
+        assert abs(t[b, 0] - ref["loss"]) <= 1e-4 * abs(ref["loss"]), b
+        o = plan.s_offsets[b]
+        assert np.max(np.abs(g[o:o + n] - ref["g"])) <= 1e-4 * np.max(np.abs(ref["g"])), b
