@@ -181,10 +181,17 @@ void af_plan_destroy(af_plan* plan);
 af_status af_plan_workspace_size(const af_plan* plan, size_t* bytes);
 af_status af_plan_get_summary(const af_plan* plan, af_plan_summary* out);
 
-/* Re-pick the kernel variant by timing every candidate on this plan's shapes
- * (forward + fused loss) with the given device inputs; synchronises `stream`.
- * ws must hold af_plan_workspace_size bytes for every candidate, which the
- * function checks.  Not capturable. */
+/* Re-pick the schedule by timing candidates on this plan's shapes (forward +
+ * fused ISL loss) with the given device inputs: every kernel variant that fits
+ * each size class, the tuned classes together at one, two or four work items
+ * per resident work group, and (several classes) one launch of all of them at
+ * three, six or twelve items per group; the fastest is kept.  Synchronises
+ * `stream`.  ws must hold af_plan_workspace_size bytes for a candidate to be
+ * timed (larger ones are skipped).  Results are cached per device
+ * architecture and plan shapes for the process, and, when the environment
+ * variable GRAF_AF_TUNE_CACHE names a file, read from and appended to it; a
+ * cached schedule is applied without timing (chosen_variant and best_ms then
+ * report the cached choice).  Not capturable. */
 af_status af_plan_autotune(af_plan* plan, const void* s, void* ws, size_t ws_bytes, void* stream,
                            int32_t* chosen_variant, float* best_ms);
 

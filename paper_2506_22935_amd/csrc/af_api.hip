@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -90,6 +92,7 @@ struct af_plan {
     int store_mode = 0;
     int64_t budget = 0;
     int seg_iters_opt = 0;
+    double items_per_slot = 0.0;  // work items per resident work group (0: the planner's default)
     int loss_passes_opt = 0;
 
     // schedule: one class per distinct M, each with its own kernel variant,
@@ -302,7 +305,8 @@ af_status build_schedule(af_plan* p) {
     // about two items per resident work group; six for the one-launch
     // kernel, whose work groups take items from one queue by ticket, so that
     // the queue's last items are short
-    const double target = total / ((one ? 6.0 : 2.0) * std::max(1, total_slots));
+    const double ips = p->items_per_slot > 0.0 ? p->items_per_slot : (one ? 6.0 : 2.0);
+    const double target = total / (ips * std::max(1, total_slots));
 
     std::vector<WaveDesc> wd(B);
     std::vector<SegDesc> segs;
@@ -777,6 +781,101 @@ ReduceArgs loss_reduce_args(const af_plan* p, const void* s, const af_loss_param
     return r;
 }
 
+// ---------------------------------------------------------- tuning cache --
+// Autotuned schedules keyed by the device architecture and the plan's shapes
+// (every waveform's N, M, lag window, kind, and the plan options that change
+// the schedule).  Held in memory for the process; with the environment
+// variable GRAF_AF_TUNE_CACHE naming a file, entries are also read from and
+// appended to it, one line per entry:
+//   <key> <one_launch> <items_per_slot> <ms> <classes> <variant per class...>
+struct TuneEntry {
+    bool one_launch = true;
+    std::vector<int> forced;
+    double items_per_slot = 0.0;
+    float ms = 0.f;
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, TuneEntry>> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const af_plan* p) {
+    hipDeviceProp_t prop;
+    std::string arch = hipGetDeviceProperties(&prop, p->device) == hipSuccess ? prop.gcnArchName : "unknown";
+    for (char& c : arch)
+        if (c == ' ' || c == ':') c = '_';
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the shapes
+    auto mix = [&](int64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    mix(p->batch);
+    for (const af_wave& w : p->waves) {
+        mix(w.n);
+        mix(w.m);
+        mix(w.max_lag);
+        mix(w.flags);
+    }
+    mix(p->store_mode);
+    mix(p->seg_iters_opt);
+    mix(p->loss_passes_opt);
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+    return arch + "/" + buf;
+}
+
+void tune_load_file() {
+    g_tune_loaded = true;
+    const char* path = std::getenv("GRAF_AF_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int one = 0, nc = 0;
+    double ips = 0.0;
+    float ms = 0.f;
+    while (std::fscanf(f, "%255s %d %lf %f %d", key, &one, &ips, &ms, &nc) == 5) {
+        if (nc < 0 || nc > 64) break;
+        TuneEntry e;
+        e.one_launch = one != 0;
+        e.items_per_slot = ips;
+        e.ms = ms;
+        e.forced.resize(nc);
+        bool ok = true;
+        for (int i = 0; i < nc && ok; ++i) ok = std::fscanf(f, "%d", &e.forced[i]) == 1;
+        if (!ok) break;
+        g_tune.emplace_back(key, e);
+    }
+    std::fclose(f);
+}
+
+bool tune_lookup(const std::string& key, TuneEntry* out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) tune_load_file();
+    for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+        if (it->first == key) {
+            *out = it->second;
+            return true;
+        }
+    return false;
+}
+
+void tune_store(const std::string& key, const TuneEntry& e) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) tune_load_file();
+    g_tune.emplace_back(key, e);
+    const char* path = std::getenv("GRAF_AF_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %.3f %.5f %d", key.c_str(), e.one_launch ? 1 : 0, e.items_per_slot, e.ms,
+                 (int)e.forced.size());
+    for (int v : e.forced) std::fprintf(f, " %d", v);
+    std::fprintf(f, "\n");
+    std::fclose(f);
+}
+
 // af_loss on a given workspace (the caller's, or af_loss_no_alloc's array)
 af_status loss_call(const af_plan* p, const void* s, const af_loss_params* lp, float* terms, float* mag, void* grad_s,
                     void* ws, size_t ws_bytes, hipStream_t st) {
@@ -916,7 +1015,7 @@ af_status af_forward(const af_plan* p, const void* s, float* mag, void* chi, flo
     a.chi = (float2*)chi;
     a.ystore = v.store;
     if (energy) a.energy = energy;
-    return launch(p, graf::MODE_FWD, a, (hipStream_t)stream);
+    return launch(p, chi ? graf::MODE_FWD : graf::MODE_FWD_MAG, a, (hipStream_t)stream);
 }
 
 af_status af_backward(const af_plan* p, const void* s, const float* grad_mag, void* grad_s, void* ws,
@@ -1150,6 +1249,21 @@ af_status af_optim_step(const af_plan* p, float* phi, float* adam_m, float* adam
 af_status af_plan_autotune(af_plan* p, const void* s, void* ws, size_t ws_bytes, void* stream, int32_t* chosen,
                            float* best_ms) {
     if (!p || !s || !ws) return AF_ERR_INVALID_ARG;
+    // a schedule tuned before for the same device architecture and plan
+    // shapes (in this process, or in the file GRAF_AF_TUNE_CACHE names)
+    const std::string key = tune_key(p);
+    TuneEntry hit;
+    if (tune_lookup(key, &hit) && (int)hit.forced.size() == p->natural_classes) {
+        p->one_launch = hit.one_launch;
+        p->forced = hit.forced;
+        p->items_per_slot = hit.items_per_slot;
+        af_status rc = build_schedule(p);
+        if (rc == AF_OK && p->ws_total <= ws_bytes) {
+            if (chosen) *chosen = p->classes.empty() ? -1 : p->classes[0].variant;
+            if (best_ms) *best_ms = hit.ms;
+            return AF_OK;
+        }
+    }
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return AF_ERR_HIP;
@@ -1183,6 +1297,8 @@ af_status af_plan_autotune(af_plan* p, const void* s, void* ws, size_t ws_bytes,
     };
     const bool one_before = p->one_launch;
     const std::vector<int> forced_before = p->forced;
+    const double ips_before = p->items_per_slot;
+    p->items_per_slot = 0.0;
     af_status rc = AF_OK;
     // 1. per class: every variant that fits the class, the class timed alone
     p->one_launch = false;
@@ -1205,34 +1321,58 @@ af_status af_plan_autotune(af_plan* p, const void* s, void* ws, size_t ws_bytes,
         if (best[c] < 0) rc = AF_ERR_UNSUPPORTED;
         p->forced[c] = best[c];
     }
-    // 2. the tuned classes together, against one launch of all of them
+    // 2. the tuned classes together, with one, two or four work items per
+    // resident work group; then one launch of all of them, with three, six
+    // or twelve items per group (shorter last items against more staging)
     float t_per = -1.f, t_one = -1.f;
-    if (rc == AF_OK) t_per = time_schedule(-1);
+    double ips_per = 0.0, ips_one = 0.0;
+    if (rc == AF_OK) {
+        for (double ips : {1.0, 2.0, 4.0}) {
+            p->items_per_slot = ips;
+            const float t = time_schedule(-1);
+            if (t >= 0.f && (t_per < 0.f || t < t_per)) {
+                t_per = t;
+                ips_per = ips;
+            }
+        }
+    }
     if (rc == AF_OK && NC > 1) {
         const std::vector<int> tuned = p->forced;
         p->forced.assign(NC, -1);
         p->one_launch = true;
-        if (build_schedule(p) == AF_OK && p->classes.size() == 1 && p->classes[0].variant == graf::kUnionVariant)
-            t_one = time_schedule(-1);
+        for (double ips : {3.0, 6.0, 12.0}) {
+            p->items_per_slot = ips;
+            if (build_schedule(p) != AF_OK || p->classes.size() != 1 || p->classes[0].variant != graf::kUnionVariant)
+                break;
+            const float t = time_schedule(-1);
+            if (t >= 0.f && (t_one < 0.f || t < t_one)) {
+                t_one = t;
+                ips_one = ips;
+            }
+        }
         if (!(t_one >= 0.f && (t_per < 0.f || t_one < t_per))) {
             p->one_launch = false;
             p->forced = tuned;
             t_one = -1.f;
         }
     }
+    p->items_per_slot = t_one >= 0.f ? ips_one : ips_per;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc == AF_OK && t_per < 0.f && t_one < 0.f) rc = AF_ERR_UNSUPPORTED;
     if (rc != AF_OK) {
         p->one_launch = one_before;
         p->forced = forced_before;
+        p->items_per_slot = ips_before;
         (void)build_schedule(p);
         return rc;
     }
     rc = build_schedule(p);
     if (rc != AF_OK) return rc;
+    const float t_best = t_one >= 0.f ? t_one : t_per;
+    tune_store(key, TuneEntry{p->one_launch, p->forced, p->items_per_slot, t_best});
     if (chosen) *chosen = p->classes.empty() ? -1 : p->classes[0].variant;
-    if (best_ms) *best_ms = t_one >= 0.f ? t_one : t_per;
+    if (best_ms) *best_ms = t_best;
     return AF_OK;
 }
 

@@ -275,20 +275,71 @@ struct Plan {
 // transform); TwSplit multiplies two short tables, hi[i >> b] * lo[i mod 2^b],
 // which fit in LDS beside the transform buffers of large sizes.
 struct TwTable {
+    static constexpr bool kPassTables = false;
     const float2* t;
     int sh;
     __device__ __forceinline__ float2 operator()(int i) const { return t[i << sh]; }
+    // w_M^i for i < M/2
+    __device__ __forceinline__ float2 low(int i) const { return t[i << sh]; }
 };
 struct TwSplit {
+    static constexpr bool kPassTables = false;
     const float2* hi;
     const float2* lo;
     int b;
     __device__ __forceinline__ float2 operator()(int i) const { return cmul(hi[i >> b], lo[i & ((1 << b) - 1)]); }
+    __device__ __forceinline__ float2 low(int i) const { return (*this)(i); }
 };
 
+// Per-pass twiddle tables of one transform size (MH points, P per lane).
+// Pass p >= 1 of the Stockham transform (stride NS = P^p, radix R) needs
+// w_M^(r k M / (NS R)) for r in [1, R) and k in [0, NS); its table holds them
+// as [r - 1][k].  The lanes of a wavefront have consecutive (or repeating) k,
+// so they read consecutive entries: no LDS bank conflicts, where reading one
+// shared table at index r k M / (NS R) put up to 16 lanes on one bank.
+template <int MH, int P>
+struct PassTables {
+    static constexpr int radix(int ns) { return ns * P >= MH ? MH / ns : P; }
+    // first entry of the table of the pass with stride ns (ns = P, P^2, ...)
+    static constexpr int offset(int ns) {
+        int o = 0;
+        for (int q = P; q < ns; q *= P) o += (radix(q) - 1) * q;
+        return o;
+    }
+    static constexpr int total() { return offset(MH); }
+};
+// Index into the w_M table (M = 2 MH) of entry e of the pass tables.
+template <int MH, int P, int NS = P>
+__device__ __forceinline__ int pass_table_source(int e) {
+    if constexpr (NS >= MH) {
+        return 0;
+    } else {
+        constexpr int R = PassTables<MH, P>::radix(NS);
+        constexpr int SZ = (R - 1) * NS;
+        if (e < SZ) {
+            const int r = e / NS + 1, k = e % NS;
+            return (r * k * (2 * MH / (NS * R))) & (2 * MH - 1);
+        }
+        return pass_table_source<MH, P, NS * P>(e - SZ);
+    }
+}
+// Half table w_M^i (i < M/2) followed by the pass tables; w_M^i for
+// i in [M/2, M) is -w_M^(i - M/2).
+struct TwPass {
+    static constexpr bool kPassTables = true;
+    const float2* half;
+    const float2* pass;
+    int mh;
+    __device__ __forceinline__ float2 operator()(int i) const {
+        const float2 w = half[i & (mh - 1)];
+        return i < mh ? w : make_float2(-w.x, -w.y);
+    }
+    __device__ __forceinline__ float2 low(int i) const { return half[i]; }
+};
 // The short tables of the largest transform in a launch serving a smaller
 // one: w_M^i = w_MMAX^(i << sh) with sh = log2(MMAX / M).
 struct TwSplitSh {
+    static constexpr bool kPassTables = false;
     const float2* hi;
     const float2* lo;
     int b;
@@ -297,6 +348,7 @@ struct TwSplitSh {
         const int j = i << sh;
         return cmul(hi[j >> b], lo[j & ((1 << b) - 1)]);
     }
+    __device__ __forceinline__ float2 low(int i) const { return (*this)(i); }
 };
 
 // Pass number PASS (0-based) with stride NS = P^PASS and radix R.
@@ -316,7 +368,11 @@ __device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, con
             // exp(SIGN j 2pi r k / (NS R)) = w_M^(r k M/(NS R))
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw((r * k) << tw_shift);
+                float2 w;
+                if constexpr (Tw::kPassTables)
+                    w = tw.pass[PassTables<MH, P>::offset(NS) + (r - 1) * NS + k];
+                else
+                    w = tw((r * k) << tw_shift);
                 if (SIGN > 0) w.y = -w.y;
                 u[r] = cmul(u[r], w);
                 // register-lean instances: a few twiddles in flight at a time

@@ -63,11 +63,15 @@ enum Mode : int {
                         // instance with the extended epilogue terms (hard-PSL
                         // maximum, L_match, mainlobe width; split variants), so
                         // that the plain fused pass keeps its registers
-    MODE_FWD_EXT = 6    // launch id only: the MODE_FWD pass with the extended
+    MODE_FWD_EXT = 6,   // launch id only: the MODE_FWD pass with the extended
                         // epilogue terms, likewise; the plain forward carries
                         // none of their code and keeps every value in registers
+    MODE_FWD_MAG = 7    // launch id only: af_forward without chi rows: a grid and
+                        // spectra only (its own instance in the halves-in-turn
+                        // variant, whose full forward does not fit 128 registers;
+                        // MODE_FWD elsewhere)
 };
-constexpr int kNumModes = 7;
+constexpr int kNumModes = 8;
 // launch ids that run the extended epilogue (split variants only)
 constexpr bool is_ext_mode(int mode) { return mode == MODE_FUSED_EXT || mode == MODE_FWD_EXT; }
 

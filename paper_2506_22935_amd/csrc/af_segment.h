@@ -116,20 +116,25 @@ struct WaveState {
 // barrier, so one memory round trip covers all of them.  CIRC (periodic AF,
 // N = MH): the samples are staged twice, s_lds[p] = s[p mod N] for p < 2 N,
 // so that the lag product reads s[(m + tau) mod N] as s_lds[m + tau].
-template <int MODE, int WGS, int MH, bool CIRC = false>
+template <int MODE, int WGS, int MH, bool CIRC = false, int P = 16>
 __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2* s_lds, bool s_in_lds,
                            double* scratch, WaveState& st, float2* twl, int twsh) {
     constexpr int NPT = (MH + WGS - 1) / WGS;
-    constexpr int TPT = (2 * MH + WGS - 1) / WGS;
+    constexpr int NTW = MH + PassTables<MH, P>::total();  // half table and pass tables
+    constexpr int TPT = (NTW + WGS - 1) / WGS;
     constexpr int PPT = 4;  // records per thread merged from registers
     constexpr bool MERGE = MODE == MODE_BWD_LOSS;
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    // opaque, as in process_segment: the sample indices below are not
+    // hoisted out of the persistent item loop
+    asm volatile("" : "+v"(tid));
     float2 tx[TPT];
     if (twl) {
 #pragma unroll
         for (int i = 0; i < TPT; ++i) {
             const int j = tid + i * WGS;
-            tx[i] = j < 2 * MH ? a.tw[j << twsh] : make_float2(0.f, 0.f);
+            const int src = j < MH ? j : pass_table_source<MH, P>(j - MH);
+            tx[i] = j < NTW ? a.tw[src << twsh] : make_float2(0.f, 0.f);
         }
     }
     const float2* __restrict__ sg_s = a.s + w.s_off;
@@ -180,7 +185,7 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
 #pragma unroll
         for (int i = 0; i < TPT; ++i) {
             const int j = tid + i * WGS;
-            if (j < 2 * MH) twl[j] = tx[i];
+            if (j < NTW) twl[j] = tx[i];
         }
     }
     st.wave = wave;
@@ -235,21 +240,24 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
     __syncthreads();
 }
 
-// Copy this size's twiddles w_M^i (i < 2 MH) from the global table to LDS
-// (classes with several waveforms, before their first item).
-template <int WGS, int MH>
+// Copy this size's twiddles from the global table to LDS as the half table
+// w_M^i (i < MH) and the transform's pass tables (classes with several
+// waveforms, before their first item).
+template <int WGS, int MH, int P>
 __device__ void stage_twiddles(const AfArgs& a, float2* twl, int twsh) {
-    constexpr int TPT = (2 * MH + WGS - 1) / WGS;
+    constexpr int NTW = MH + PassTables<MH, P>::total();
+    constexpr int TPT = (NTW + WGS - 1) / WGS;
     float2 tx[TPT];
 #pragma unroll
     for (int i = 0; i < TPT; ++i) {
         const int j = threadIdx.x + i * WGS;
-        tx[i] = j < 2 * MH ? a.tw[j << twsh] : make_float2(0.f, 0.f);
+        const int src = j < MH ? j : pass_table_source<MH, P>(j - MH);
+        tx[i] = j < NTW ? a.tw[src << twsh] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int i = 0; i < TPT; ++i) {
         const int j = threadIdx.x + i * WGS;
-        if (j < 2 * MH) twl[j] = tx[i];
+        if (j < NTW) twl[j] = tx[i];
     }
     __syncthreads();
 }
@@ -284,7 +292,11 @@ constexpr bool EXT_MODE() {
     return (MODE == MODE_FWD || MODE == MODE_FUSED_ISL) && EXTK;
 }
 
-template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, bool CIRC, bool EXTK, typename Tw>
+// MAGONLY (forward): a and spectra only, no loss sums and no chi rows, so the
+// instance carries a single family of epilogue copies (the halves-in-turn
+// variant then keeps every value in its 128 registers)
+template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, bool CIRC, bool EXTK, bool MAGONLY = false,
+          typename Tw>
 __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, const Tw& twl,
                                                 const float2* s_lds, bool s_in_lds, double* scratch,
                                                 const WaveState& ws) {
@@ -340,7 +352,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const float invE2 = invE * invE;
     const float2* __restrict__ sv = s_in_lds ? s_lds : sg_s;
     const float inv_t2 = kLog2e / a.temp;
-    const bool want_lse = FWD_SUMS && a.w_psl != 0.f;
+    const bool want_lse = !MAGONLY && FWD_SUMS && a.w_psl != 0.f;
     const bool lse_fixed = lse_fixed_shift(a.eps, inv_t2);
     const float aref_t2 = lse_ref(a.eps) * inv_t2;
     const float glob_m = ws.glob_m, glob_inv_s = ws.glob_inv_s;
@@ -348,7 +360,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const float* bu = banded ? a.band_w + w.band_off : nullptr;
     const float* bv = banded ? a.band_w + w.band_off + 31 : nullptr;
     const bool mag_out = HAS_MAG_OUT && a.mag != nullptr;
-    const bool chi_out = MODE == MODE_FWD && a.chi != nullptr;
+    const bool chi_out = !MAGONLY && MODE == MODE_FWD && a.chi != nullptr;
 
     // gradient accumulators: registers, or (halves in turn, long waveforms)
     // the segment's own slab in global memory, which only this group touches
@@ -478,7 +490,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             for (int r = 0; r < P; ++r) {
                 const int m = l + r * L;
                 float2 x = cmulc(sv[m + tz], sv[m]);
-                if (h) x = cmul(x, twl(m));
+                if (h) x = cmul(x, twl.low(m));
                 v[r] = x;
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
@@ -491,7 +503,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             for (int r = 0; r < P; ++r) {
                 const int m = l + r * L;
                 float2 x = cmulc(buf_load2(s_rs, (m + tz) * 8), buf_load2(s_rs, m * 8));
-                if (h) x = cmul(x, twl(m));
+                if (h) x = cmul(x, twl.low(m));
                 v[r] = x;
                 // bound how many loads the scheduler keeps in flight
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
@@ -505,7 +517,7 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         fft_group<MH, P, +1, (WGS >= 1024)>(v, buf, l, twl, sync);
         if (h) {
 #pragma unroll
-            for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl(l + q * L));
+            for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], twl.low(l + q * L));
         }
         if constexpr (L % 32 == 0) {
             const int bi = lds_index(l);
@@ -789,7 +801,9 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 1>{});
                 }
             };
-            if constexpr (MODE == MODE_FWD) {
+            if constexpr (MODE == MODE_FWD && MAGONLY) {
+                by_loss(T_{}, F_{}, T_{}, F_{});
+            } else if constexpr (MODE == MODE_FWD) {
                 if (!want_lse && ext_rt)
                     ext_copy();
                 else if (!want_lse)
@@ -1097,9 +1111,11 @@ using V5 = Variant<32, 1, 256, 1, 12, 12, 1, 0>; // M 8192: 32 points per lane, 
 // Persistent kernel over one size class: work group g runs items g, g + grid,
 // g + 2 grid, ... of the class's list, which the planner sorted longest first
 // (a static, deterministic assignment).
-template <int MODE, typename V, int LG, bool CIRC = false, bool EXTK = false>
+template <int MODE, typename V, int LG, bool CIRC = false, bool EXTK = false, bool MAGONLY = false>
 __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     static_assert(!CIRC || (V::SPLIT && V::S_LDS), "periodic AF: split variants with samples in LDS");
+    static_assert(!V::TW_LDS || (1 << LG) + PassTables<(1 << LG), V::P>::total() <= (2 << LG),
+                  "half table and pass tables exceed the twiddle area");
     extern __shared__ float2 dyn[];
     // block reductions; [64, 96) holds the per-wave hard-PSL records,
     // [96, 112) the per-wave sums of the cell-wise extension terms
@@ -1112,10 +1128,10 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     constexpr int TB = V::split_bits(LG);
     float2* tw_lo = dyn + V::buf_lds_bytes(LG) / 8;
     float2* tw_hi = tw_lo + (1 << TB);
-    using Tw = std::conditional_t<V::TW_LDS != 0, TwTable, TwSplit>;
+    using Tw = std::conditional_t<V::TW_LDS != 0, TwPass, TwSplit>;
     Tw twl;
     if constexpr (V::TW_LDS) {
-        twl = TwTable{tw_lds, 0};
+        twl = TwPass{tw_lds, tw_lds + MH, MH};
     } else {
         twl = TwSplit{tw_hi, tw_lo, TB};
         if (blockIdx.x < a.n_segs) stage_split_twiddles<V::WGS, MH, TB>(a, tw_hi, tw_lo, twsh_global);
@@ -1130,10 +1146,10 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
         if (a.single) {
             // one waveform: its samples, the twiddles and the first item's
             // descriptor travel in the same memory round trip
-            stage_wave<MODE, V::WGS, MH, CIRC>(a, a.w0, a.w0_index, s_lds, V::S_LDS != 0, scratch, st, tw_lds,
-                                         twsh_global);
+            stage_wave<MODE, V::WGS, MH, CIRC, V::P>(a, a.w0, a.w0_index, s_lds, V::S_LDS != 0, scratch, st,
+                                                     tw_lds, twsh_global);
         } else if (tw_lds) {
-            stage_twiddles<V::WGS, MH>(a, tw_lds, twsh_global);
+            stage_twiddles<V::WGS, MH, V::P>(a, tw_lds, twsh_global);
         }
     }
     for (int item = blockIdx.x; item < a.n_segs; item += gridDim.x) {
@@ -1142,9 +1158,9 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
         if (sg.wave != st.wave) {
             // a class with one waveform carries its descriptor in the arguments
             const WaveDesc w = a.single ? a.w0 : a.waves[sg.wave];
-            stage_wave<MODE, V::WGS, MH, CIRC>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st, nullptr, 0);
+            stage_wave<MODE, V::WGS, MH, CIRC, V::P>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st, nullptr, 0);
         }
-        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG), CIRC, EXTK>(a, sg, lds, twl, s_lds,
+        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG), CIRC, EXTK, MAGONLY>(a, sg, lds, twl, s_lds,
                                                                                   V::S_LDS != 0, scratch, st);
     }
 }

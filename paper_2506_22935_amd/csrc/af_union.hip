@@ -13,6 +13,7 @@ static void* union_mode(int mode) {
         case MODE_LOSS: return (void*)af_union_kernel<MODE_LOSS, CIRC>;
         case MODE_FUSED_EXT: return (void*)af_union_kernel<MODE_FUSED_ISL, CIRC, true>;
         case MODE_FWD_EXT: return (void*)af_union_kernel<MODE_FWD, CIRC, true>;
+        case MODE_FWD_MAG: return (void*)af_union_kernel<MODE_FWD, CIRC>;
     }
     return nullptr;
 }

@@ -12,17 +12,17 @@ namespace graf {
 #define GRAF_CAT(a, b) GRAF_CAT2(a, b)
 using VSel = GRAF_CAT(V, GRAF_VARIANT);
 
-template <int MODE, int LG, bool CIRC, bool EXTK = false>
+template <int MODE, int LG, bool CIRC, bool EXTK = false, bool MAGONLY = false>
 static void* pick_lg(int lg) {
     if constexpr (LG > 15) {
         return nullptr;
     } else {
         if (lg == LG) {
             if constexpr (VSel::fits(LG) && (!CIRC || (VSel::SPLIT && VSel::S_LDS)))
-                return (void*)af_kernel<MODE, VSel, LG, CIRC, EXTK>;
+                return (void*)af_kernel<MODE, VSel, LG, CIRC, EXTK, MAGONLY>;
             return nullptr;
         }
-        return pick_lg<MODE, LG + 1, CIRC, EXTK>(lg);
+        return pick_lg<MODE, LG + 1, CIRC, EXTK, MAGONLY>(lg);
     }
 }
 
@@ -40,6 +40,9 @@ static void* pick_mode(int mode, int lg) {
         case MODE_FWD_EXT:
             if constexpr (VSel::SPLIT) return pick_lg<MODE_FWD, 1, CIRC, true>(lg);
             return nullptr;
+        case MODE_FWD_MAG:
+            if constexpr (VSel::SPLIT) return pick_lg<MODE_FWD, 1, CIRC>(lg);
+            return pick_lg<MODE_FWD, 1, CIRC, false, true>(lg);
     }
     return nullptr;
 }

@@ -331,18 +331,28 @@ def test_small_temperature_uses_running_maximum(af):
     loss_vs_oracle(af, plan, codes, [m], [n - 1], dict(w_isl=1.0, w_psl=1.0, temp=0.01), "small T")
 
 
-def test_autotune_picks_a_fitting_variant(af):
+def test_autotune_picks_a_fitting_variant(af, tmp_path, monkeypatch):
     # two size classes; the tuner times every variant that fits each class
     # and the plan keeps computing the same loss and gradient afterwards
     say("autotune")
     ns, ms = [256, 256, 700], [512, 512, 2048]
     codes = [W.random_code(n, seed=600 + i) for i, n in enumerate(ns)]
     plan = af.Plan(ns, ms, eps=EPS)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("GRAF_AF_TUNE_CACHE", str(cache))
     v, best = plan.autotune(packed(codes))
     # per class: M = 2048 fits variants 0, 3 and 4; or one launch of both (6)
     assert v in (0, 3, 4, 6) and best > 0.0
     assert plan.summary()["variant"] == v
     loss_vs_oracle(af, plan, codes, ms, [n - 1 for n in ns], dict(w_isl=1.0, w_psl=0.0, temp=0.05), "autotuned")
+    # the choice is cached for these shapes: a second plan takes it without
+    # timing, and the cache file holds one line for it
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[0].startswith("gfx950")
+    again = af.Plan(ns, ms, eps=EPS)
+    v2, best2 = again.autotune(packed(codes))
+    assert (v2, best2) == (v, best) and again.summary() == plan.summary()
+    assert len(cache.read_text().splitlines()) == 1
 
 
 def test_fused_loss_graph_replay_matches_eager(af):
