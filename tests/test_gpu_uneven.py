@@ -223,3 +223,73 @@ def test_one_launch_periodic_sizes(af):
         assert abs(t[b, 0] - ref["loss"]) <= 1e-4 * abs(ref["loss"]), b
         o = plan.s_offsets[b]
         assert np.max(np.abs(g[o:o + n] - ref["g"])) <= 1e-4 * np.max(np.abs(ref["g"])), b
+
+
+def test_one_launch_every_mode_matches_per_class(af):
+    # every pass of the one-launch kernel against per-class launches (each of
+    # which the other tests hold to the oracle): forward with a and chi
+    # grids, the magnitude backward (stored and recomputed spectra), the
+    # two-pass soft-PSL loss (running maxima), and the extended epilogue
+    # terms (hard PSL, L_match, mainlobe width, cell weights)
+    say("one launch, every mode")
+    ns = [64, 100, 200, 300, 500, 90]
+    ms = [128, 256, 512, 1024, 1024, 512]
+    codes = [W.random_code(n, seed=950 + i) for i, n in enumerate(ns)]
+    s = torch.from_numpy(np.concatenate(codes)).cuda()
+    plans = {}
+    for one in (True, False):
+        for store in (1, 2):
+            plans[(one, store)] = af.Plan(ns, ms, eps=EPS, one_launch=one, store_mode=store)
+    assert plans[(True, 1)].summary()["variant"] == 6 and plans[(False, 1)].summary()["variant"] != 6
+    E = np.array([float(np.sum(np.abs(c.astype(np.complex128)) ** 2)) for c in codes])
+
+    def close(x, y, tol, what):
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert np.max(np.abs(x - y)) <= tol, (what, float(np.max(np.abs(x - y))), tol)
+
+    # forward: a and chi
+    out = {}
+    for one in (True, False):
+        p = plans[(one, 1)]
+        mag, chi, e = p.forward(s, mag=True, chi=True, ws=p.new_workspace())
+        out[one] = (mag, chi, e)
+    torch.cuda.synchronize()
+    close(out[True][0], out[False][0], 2e-6, "a")
+    close(torch.view_as_real(out[True][1]), torch.view_as_real(out[False][1]), 2e-6 * E.max(), "chi")
+    close(out[True][2], out[False][2], 1e-6 * E.max(), "E")
+    # magnitude backward, both store modes
+    cells = plans[(True, 1)].total_cells
+    ga = torch.from_numpy(W.upstream_grid(1, cells, seed=77).ravel()).cuda() * out[False][0]
+    grads = {}
+    for key, p in plans.items():
+        ws = p.new_workspace()
+        p.forward(s, mag=False, ws=ws)
+        grads[key] = p.backward(s, ga, ws=ws)
+    torch.cuda.synchronize()
+    ref = grads[(False, 2)]
+    scale = float(ref.abs().max())
+    for key, g in grads.items():
+        close(torch.view_as_real(g), torch.view_as_real(ref), 1e-5 * scale, "backward %s" % (key,))
+    # two-pass soft PSL (T = 0.01: running maxima, forward then backward)
+    lp = dict(w_isl=1.0, w_psl=1.0, temp=0.01)
+    res = {one: plans[(one, 2)].loss(s, **lp) for one in (True, False)}
+    torch.cuda.synchronize()
+    close(res[True][0], res[False][0], 1e-5 * float(res[False][0].abs().max()), "two-pass terms")
+    close(torch.view_as_real(res[True][1]), torch.view_as_real(res[False][1]),
+          1e-5 * float(res[False][1].abs().max()), "two-pass grad")
+    # extended terms
+    target = torch.rand(cells, device="cuda") * 0.01
+    cw = torch.rand(cells, device="cuda")
+    lp = dict(w_isl=1.0, match=target, w_match=0.5, w_width=0.01, gamma=10.0, cell_w=cw, w_cell=0.1)
+    res = {one: plans[(one, 2)].loss(s, **lp) for one in (True, False)}
+    torch.cuda.synchronize()
+    close(res[True][0], res[False][0], 1e-5 * float(res[False][0].abs().max()), "ext terms")
+    close(torch.view_as_real(res[True][1]), torch.view_as_real(res[False][1]),
+          1e-5 * float(res[False][1].abs().max()), "ext grad")
+    # the hard PSL (the forward pass with the extended epilogue): its value
+    # (a maximum, robust to rounding; its cell and gradient could move between
+    # near-equal sidelobes, so only the value is compared)
+    lp = dict(w_isl=0.0, w_psl=1.0, psl_hard=True, match=target, w_match=0.5)
+    fwd_only = {one: plans[(one, 2)].loss(s, grad=False, **lp) for one in (True, False)}
+    torch.cuda.synchronize()
+    close(fwd_only[True][0], fwd_only[False][0], 1e-5 * float(fwd_only[False][0].abs().max()), "ext forward")
