@@ -109,6 +109,18 @@ struct WaveState {
     float glob_m, glob_inv_s;
 };
 
+// Fill the pass tables that follow the half table w_M^i (i < MH, already in
+// LDS and visible to every thread) from it: w_M^i = -w_M^(i - MH) for i >= MH.
+template <int WGS, int MH, int P>
+__device__ __forceinline__ void build_pass_tables(float2* twl, int tid) {
+    constexpr int NP = PassTables<MH, P>::total();
+    for (int e = tid; e < NP; e += WGS) {
+        const int src = pass_table_source<MH, P>(e);
+        const float2 w = twl[src & (MH - 1)];
+        twl[MH + e] = src < MH ? w : make_float2(-w.x, -w.y);
+    }
+}
+
 // Stage waveform `wave` (N <= MH samples) into LDS and compute its energy;
 // with twl != nullptr also copy this size's twiddles w_M^i (i < 2 MH) from the
 // global table; for the loss backward also merge the forward pass records
@@ -120,8 +132,7 @@ template <int MODE, int WGS, int MH, bool CIRC = false, int P = 16>
 __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2* s_lds, bool s_in_lds,
                            double* scratch, WaveState& st, float2* twl, int twsh) {
     constexpr int NPT = (MH + WGS - 1) / WGS;
-    constexpr int NTW = MH + PassTables<MH, P>::total();  // half table and pass tables
-    constexpr int TPT = (NTW + WGS - 1) / WGS;
+    constexpr int TPT = (MH + WGS - 1) / WGS;  // the half table w_M^i, i < MH
     constexpr int PPT = 4;  // records per thread merged from registers
     constexpr bool MERGE = MODE == MODE_BWD_LOSS;
     int tid = threadIdx.x;
@@ -133,8 +144,7 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
 #pragma unroll
         for (int i = 0; i < TPT; ++i) {
             const int j = tid + i * WGS;
-            const int src = j < MH ? j : pass_table_source<MH, P>(j - MH);
-            tx[i] = j < NTW ? a.tw[src << twsh] : make_float2(0.f, 0.f);
+            tx[i] = j < MH ? a.tw[j << twsh] : make_float2(0.f, 0.f);
         }
     }
     const float2* __restrict__ sg_s = a.s + w.s_off;
@@ -185,7 +195,7 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
 #pragma unroll
         for (int i = 0; i < TPT; ++i) {
             const int j = tid + i * WGS;
-            if (j < NTW) twl[j] = tx[i];
+            if (j < MH) twl[j] = tx[i];
         }
     }
     st.wave = wave;
@@ -237,6 +247,8 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
         st.glob_m = m;
         st.glob_inv_s = (float)(1.0 / s);
     }
+    // the block sums above passed barriers after the half table's stores
+    if (twl) build_pass_tables<WGS, MH, P>(twl, tid);
     __syncthreads();
 }
 
@@ -245,20 +257,20 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
 // waveforms, before their first item).
 template <int WGS, int MH, int P>
 __device__ void stage_twiddles(const AfArgs& a, float2* twl, int twsh) {
-    constexpr int NTW = MH + PassTables<MH, P>::total();
-    constexpr int TPT = (NTW + WGS - 1) / WGS;
+    constexpr int TPT = (MH + WGS - 1) / WGS;
     float2 tx[TPT];
 #pragma unroll
     for (int i = 0; i < TPT; ++i) {
         const int j = threadIdx.x + i * WGS;
-        const int src = j < MH ? j : pass_table_source<MH, P>(j - MH);
-        tx[i] = j < NTW ? a.tw[src << twsh] : make_float2(0.f, 0.f);
+        tx[i] = j < MH ? a.tw[j << twsh] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int i = 0; i < TPT; ++i) {
         const int j = threadIdx.x + i * WGS;
-        if (j < NTW) twl[j] = tx[i];
+        if (j < MH) twl[j] = tx[i];
     }
+    __syncthreads();
+    build_pass_tables<WGS, MH, P>(twl, threadIdx.x);
     __syncthreads();
 }
 
