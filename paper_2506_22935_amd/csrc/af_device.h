@@ -274,8 +274,14 @@ struct Plan {
 // TwTable reads one table (index scaled by sh when the table serves a larger
 // transform); TwSplit multiplies two short tables, hi[i >> b] * lo[i mod 2^b],
 // which fit in LDS beside the transform buffers of large sizes.
+// Twiddle accessors.  kPassTables: per-pass tables (TwPass); kPass1: a
+// table of the first twiddled pass of 16-point passes, w_256^(r k) for r in
+// [1, 16), k in [0, 16) laid out [r - 1][k] (the first twiddled pass of any
+// transform of 256 points or more with P = 16 needs exactly these).
+constexpr int kPass1Entries = 15 * 16;
 struct TwTable {
     static constexpr bool kPassTables = false;
+    static constexpr bool kPass1 = false;
     const float2* t;
     int sh;
     __device__ __forceinline__ float2 operator()(int i) const { return t[i << sh]; }
@@ -284,9 +290,11 @@ struct TwTable {
 };
 struct TwSplit {
     static constexpr bool kPassTables = false;
+    static constexpr bool kPass1 = true;
     const float2* hi;
     const float2* lo;
     int b;
+    const float2* p1;
     __device__ __forceinline__ float2 operator()(int i) const { return cmul(hi[i >> b], lo[i & ((1 << b) - 1)]); }
     __device__ __forceinline__ float2 low(int i) const { return (*this)(i); }
 };
@@ -327,6 +335,7 @@ __device__ __forceinline__ int pass_table_source(int e) {
 // i in [M/2, M) is -w_M^(i - M/2).
 struct TwPass {
     static constexpr bool kPassTables = true;
+    static constexpr bool kPass1 = false;
     const float2* half;
     const float2* pass;
     int mh;
@@ -340,10 +349,12 @@ struct TwPass {
 // one: w_M^i = w_MMAX^(i << sh) with sh = log2(MMAX / M).
 struct TwSplitSh {
     static constexpr bool kPassTables = false;
+    static constexpr bool kPass1 = true;
     const float2* hi;
     const float2* lo;
     int b;
     int sh;
+    const float2* p1;
     __device__ __forceinline__ float2 operator()(int i) const {
         const int j = i << sh;
         return cmul(hi[j >> b], lo[j & ((1 << b) - 1)]);
@@ -371,6 +382,8 @@ __device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, con
                 float2 w;
                 if constexpr (Tw::kPassTables)
                     w = tw.pass[PassTables<MH, P>::offset(NS) + (r - 1) * NS + k];
+                else if constexpr (Tw::kPass1 && P == 16 && NS == 16 && R == 16)
+                    w = tw.p1[(r - 1) * 16 + k];  // w_M^(r k M / 256) = w_256^(r k)
                 else
                     w = tw((r * k) << tw_shift);
                 if (SIGN > 0) w.y = -w.y;

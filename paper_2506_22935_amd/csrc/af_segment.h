@@ -275,16 +275,23 @@ __device__ void stage_twiddles(const AfArgs& a, float2* twl, int twsh) {
 }
 
 // Copy the two short twiddle tables of TwSplit (lo: w_M^j, j < 2^b; hi:
-// w_M^(h 2^b), h < M / 2^b) from the global table, then synchronise.
+// w_M^(h 2^b), h < M / 2^b) and, with p1 (non-null only for M >= 256), the
+// first-pass table w_256^(r k) from the global table w_M^(i << twsh), then
+// synchronise.
 template <int WGS, int MH, int B>
-__device__ void stage_split_twiddles(const AfArgs& a, float2* hi, float2* lo, int twsh) {
+__device__ void stage_split_twiddles(const AfArgs& a, float2* hi, float2* lo, float2* p1, int twsh) {
     constexpr int M = 2 * MH;
     constexpr int NLO = 1 << B, NHI = M >> B;
-    for (int j = threadIdx.x; j < NLO + NHI; j += WGS) {
-        if (j < NLO)
+    const int np1 = (p1 && M >= 256) ? kPass1Entries : 0;
+    for (int j = threadIdx.x; j < NLO + NHI + np1; j += WGS) {
+        if (j < NLO) {
             lo[j] = a.tw[j << twsh];
-        else
+        } else if (j < NLO + NHI) {
             hi[j - NLO] = a.tw[((j - NLO) << B) << twsh];
+        } else {
+            const int e = j - NLO - NHI, r = e / 16 + 1, k = e % 16;
+            p1[e] = a.tw[((r * k * (M / 256)) & (M - 1)) << twsh];
+        }
     }
     __syncthreads();
 }
@@ -1107,8 +1114,10 @@ struct Variant {
     static constexpr int split_bits(int lg) { return (lg + 2) / 2; }
     static constexpr int split_lds_bytes(int lg) { return (((2 << lg) >> split_bits(lg)) + (1 << split_bits(lg))) * 8; }
     static constexpr int buf_lds_bytes(int lg) { return (WGS / ((1 << lg) / P)) * ((1 << lg) + ((1 << lg) >> 5)) * 8; }
+    // two-factor variants with 16-point passes also keep the first-pass table
+    static constexpr int p1_lds_bytes() { return (!TW_LDS && P == 16) ? kPass1Entries * 8 : 0; }
     static constexpr int fft_lds_bytes(int lg) {
-        return buf_lds_bytes(lg) + (TW_LDS ? (2 << lg) * 8 : split_lds_bytes(lg));
+        return buf_lds_bytes(lg) + (TW_LDS ? (2 << lg) * 8 : split_lds_bytes(lg) + p1_lds_bytes());
     }
 };
 
@@ -1145,8 +1154,9 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     if constexpr (V::TW_LDS) {
         twl = TwPass{tw_lds, tw_lds + MH, MH};
     } else {
-        twl = TwSplit{tw_hi, tw_lo, TB};
-        if (blockIdx.x < a.n_segs) stage_split_twiddles<V::WGS, MH, TB>(a, tw_hi, tw_lo, twsh_global);
+        float2* tw_p1 = (V::p1_lds_bytes() > 0 && MH >= 128) ? tw_hi + ((2 << LG) >> TB) : nullptr;
+        twl = TwSplit{tw_hi, tw_lo, TB, tw_p1};
+        if (blockIdx.x < a.n_segs) stage_split_twiddles<V::WGS, MH, TB>(a, tw_hi, tw_lo, tw_p1, twsh_global);
     }
     WaveState st;
     st.wave = -1;
@@ -1211,15 +1221,22 @@ __global__ __launch_bounds__(VU::WGS, VU::WAVES) void af_union_kernel(AfArgs a) 
     // plan's largest M = 2^log2_mmax sets the split actually used
     float2* tw_lo = dyn + VU::buf_lds_bytes(LGMAX) / 8;
     float2* tw_hi = tw_lo + (1 << VU::split_bits(LGMAX));
+    float2* tw_p1 = tw_hi + ((2 << LGMAX) >> VU::split_bits(LGMAX));
     float2* s_lds = dyn + VU::fft_lds_bytes(LGMAX) / 8;
     const int b = (a.log2_mmax + 1) / 2;  // split bits of the plan's largest M
-    const int nlo = 1 << b, nhi = (1 << a.log2_mmax) >> b;
+    const int mmax = 1 << a.log2_mmax;
+    const int nlo = 1 << b, nhi = mmax >> b;
+    const int np1 = mmax >= 256 ? kPass1Entries : 0;  // first-pass table (classes with M >= 256)
     if (threadIdx.x == 0) ticket = atomicAdd(a.queue, 1);
-    for (int j = threadIdx.x; j < nlo + nhi; j += VU::WGS) {
-        if (j < nlo)
+    for (int j = threadIdx.x; j < nlo + nhi + np1; j += VU::WGS) {
+        if (j < nlo) {
             tw_lo[j] = a.tw[j];
-        else
+        } else if (j < nlo + nhi) {
             tw_hi[j - nlo] = a.tw[(j - nlo) << b];
+        } else {
+            const int e = j - nlo - nhi, r = e / 16 + 1, k = e % 16;
+            tw_p1[e] = a.tw[(r * k * (mmax / 256)) & (mmax - 1)];
+        }
     }
     __syncthreads();
     WaveState st;
@@ -1229,7 +1246,7 @@ __global__ __launch_bounds__(VU::WGS, VU::WAVES) void af_union_kernel(AfArgs a) 
         if (item >= a.n_segs) break;
         const SegDesc sg = a.segs[item];
         const int log2m = a.waves[sg.wave].log2m;
-        const TwSplitSh twl{tw_hi, tw_lo, b, a.log2_mmax - log2m};
+        const TwSplitSh twl{tw_hi, tw_lo, b, a.log2_mmax - log2m, tw_p1};
         switch (log2m - 1) {
             case 6: union_item<MODE, 6, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
             case 7: union_item<MODE, 7, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
