@@ -204,7 +204,7 @@ int64_t grid_cells(const af_wave& w) {
 bool variant_fits(int v, int lg, int max_n, int circ) {
     const VariantInfo vi = graf::variant_info(v, lg);
     if (!vi.fits || (circ && !vi.circ)) return false;
-    const int lds = vi.fft_lds + (vi.s_lds ? 8 * (2 << lg) : 0);  // samples zero-padded to M
+    const int lds = vi.fft_lds + vi.s_bytes;
     return lds <= kMaxLds;
 }
 
@@ -274,7 +274,7 @@ af_status build_schedule(af_plan* p) {
         if (v < 0 || !variant_fits(v, k.lg, k.max_n, k.circ)) return AF_ERR_UNSUPPORTED;
         k.variant = v;
         const VariantInfo vi = graf::variant_info(v, k.lg);
-        k.dyn_lds = vi.fft_lds + (vi.s_lds ? 8 * (2 << k.lg) : 0);  // samples zero-padded to M
+        k.dyn_lds = vi.fft_lds + vi.s_bytes;
         for (int mode = 0; mode < graf::kNumModes; ++mode) {
             const int r = graf::variant_max_resident(mode, v, k.lg, k.circ, k.dyn_lds);
             if (r <= 0 && graf::is_ext_mode(mode) && !vi.split) {

@@ -277,11 +277,16 @@ struct Plan {
 // Twiddle accessors.  kPassTables: per-pass tables (TwPass); kPass1: a
 // table of the first twiddled pass of 16-point passes, w_256^(r k) for r in
 // [1, 16), k in [0, 16) laid out [r - 1][k] (the first twiddled pass of any
-// transform of 256 points or more with P = 16 needs exactly these).
+// transform of 256 points or more with P = 16 needs exactly these); kPass2:
+// likewise w_4096^(r k), k < 256, for the pass of stride 256, which serves
+// every transform size of that pass (radix R: w_{256 R}^(r k) =
+// w_4096^((16 / R) r k)).
 constexpr int kPass1Entries = 15 * 16;
+constexpr int kPass2Entries = 15 * 256;
 struct TwTable {
     static constexpr bool kPassTables = false;
     static constexpr bool kPass1 = false;
+    static constexpr bool kPass2 = false;
     const float2* t;
     int sh;
     __device__ __forceinline__ float2 operator()(int i) const { return t[i << sh]; }
@@ -291,6 +296,7 @@ struct TwTable {
 struct TwSplit {
     static constexpr bool kPassTables = false;
     static constexpr bool kPass1 = true;
+    static constexpr bool kPass2 = false;
     const float2* hi;
     const float2* lo;
     int b;
@@ -336,6 +342,7 @@ __device__ __forceinline__ int pass_table_source(int e) {
 struct TwPass {
     static constexpr bool kPassTables = true;
     static constexpr bool kPass1 = false;
+    static constexpr bool kPass2 = false;
     const float2* half;
     const float2* pass;
     int mh;
@@ -347,14 +354,17 @@ struct TwPass {
 };
 // The short tables of the largest transform in a launch serving a smaller
 // one: w_M^i = w_MMAX^(i << sh) with sh = log2(MMAX / M).
+template <bool P2>
 struct TwSplitSh {
     static constexpr bool kPassTables = false;
     static constexpr bool kPass1 = true;
+    static constexpr bool kPass2 = P2;
     const float2* hi;
     const float2* lo;
     int b;
     int sh;
     const float2* p1;
+    const float2* p2;  // staged whenever some transform has a pass of stride 256
     __device__ __forceinline__ float2 operator()(int i) const {
         const int j = i << sh;
         return cmul(hi[j >> b], lo[j & ((1 << b) - 1)]);
@@ -384,6 +394,8 @@ __device__ __forceinline__ void stockham_pass(float2* v, float2* lds, int l, con
                     w = tw.pass[PassTables<MH, P>::offset(NS) + (r - 1) * NS + k];
                 else if constexpr (Tw::kPass1 && P == 16 && NS == 16 && R == 16)
                     w = tw.p1[(r - 1) * 16 + k];  // w_M^(r k M / 256) = w_256^(r k)
+                else if constexpr (Tw::kPass2 && P == 16 && NS == 256)
+                    w = tw.p2[(r * (16 / R) - 1) * 256 + k];
                 else
                     w = tw((r * k) << tw_shift);
                 if (SIGN > 0) w.y = -w.y;

@@ -223,9 +223,9 @@ hipError_t launch_phase_to_signal(const float* phi, float2* s, int64_t count, hi
 
 // Kernel variants.  Variant v at transform size MH = 2^lg (M = 2 MH): fits
 // tells whether an instance exists; its dynamic LDS is fft_lds bytes plus,
-// when s_lds, 8 bytes per sample of the longest waveform it runs.
+// when s_lds, s_bytes for the samples (and whatever shares their region).
 struct VariantInfo {
-    int lo, hi, p, split, wgs, s_lds, fits, fft_lds, nacc;
+    int lo, hi, p, split, wgs, s_lds, fits, fft_lds, nacc, s_bytes;
     int circ;  // has periodic-AF instances
 };
 constexpr int kNumVariants = 7;

@@ -128,7 +128,9 @@ __device__ __forceinline__ void build_pass_tables(float2* twl, int tid) {
 // barrier, so one memory round trip covers all of them.  CIRC (periodic AF,
 // N = MH): the samples are staged twice, s_lds[p] = s[p mod N] for p < 2 N,
 // so that the lag product reads s[(m + tau) mod N] as s_lds[m + tau].
-template <int MODE, int WGS, int MH, bool CIRC = false, int P = 16>
+// UNPAD (aperiodic): MH + 1 entries, zero from N on, and the lag product
+// clamps its shifted index to MH instead of reading a zero-padded copy.
+template <int MODE, int WGS, int MH, bool CIRC = false, int P = 16, bool UNPAD = false>
 __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2* s_lds, bool s_in_lds,
                            double* scratch, WaveState& st, float2* twl, int twsh) {
     constexpr int NPT = (MH + WGS - 1) / WGS;
@@ -182,6 +184,13 @@ __device__ void stage_wave(const AfArgs& a, const WaveDesc& w, int wave, float2*
                 s_lds[p + MH] = sx[i];
             }
         }
+    } else if (UNPAD && s_in_lds) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int p = tid + i * WGS;
+            if (p < MH) s_lds[p] = sx[i];  // zero from N on
+        }
+        if (tid == 0) s_lds[MH] = make_float2(0.f, 0.f);
     } else if (s_in_lds) {
         // 2 MH entries, zero from N on: every lag product index m + tau
         // (m < MH, tau <= N) reads a sample or a zero
@@ -315,7 +324,7 @@ constexpr bool EXT_MODE() {
 // instance carries a single family of epilogue copies (the halves-in-turn
 // variant then keeps every value in its 128 registers)
 template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, bool CIRC, bool EXTK, bool MAGONLY = false,
-          typename Tw>
+          bool UNPAD = false, typename Tw>
 __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, const Tw& twl,
                                                 const float2* s_lds, bool s_in_lds, double* scratch,
                                                 const WaveState& ws) {
@@ -508,7 +517,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 #pragma unroll
             for (int r = 0; r < P; ++r) {
                 const int m = l + r * L;
-                float2 x = cmulc(sv[m + tz], sv[m]);
+                // UNPAD: entry MH is zero, as is every entry from N on
+                float2 x = cmulc(sv[UNPAD ? min(m + tz, MH) : m + tz], sv[m]);
                 if (h) x = cmul(x, twl.low(m));
                 v[r] = x;
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
@@ -1190,23 +1200,38 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
 // ------------------------------------------------- one-launch kernel -----
 // Every size class of a plan in one persistent launch: 512-thread work
 // groups, 16 points per lane, split halves, samples in LDS, the twiddles of
-// each class read from the two short tables of the plan's largest transform.
+// each class read from the two short tables of the plan's largest transform
+// and, for the passes of stride 16 and 256, from the tables of those passes.
 // The LDS of the transform buffers is the same for every size (WGS P (1 +
 // 1/32) complex values), so one allocation serves all classes; items come
 // from one work queue sorted longest first, taken with an atomic ticket.
+//
+// LDS: transform buffers, short tables, first-pass table, then one region
+// that holds (aperiodic) the stride-256 pass table and the samples, or
+// (periodic) the samples staged twice.  The aperiodic samples of the largest
+// size do not fit beside that table zero-padded to M, so that size stages
+// MH + 1 entries and clamps the lag product's index (UNPAD).
 using VU = Variant<16, 1, 512, 2, 6, 12, 1, 0>;
+constexpr int kUnionP2Bytes = kPass2Entries * 8;
+__host__ __device__ constexpr bool union_unpad(int lg) { return lg == VU::HI; }
+__host__ __device__ constexpr int union_region_bytes(int lg) {
+    const int circ = 8 * (2 << lg);
+    const int aper = kUnionP2Bytes + 8 * (union_unpad(lg) ? (1 << lg) + 2 : (2 << lg));
+    return circ > aper ? circ : aper;
+}
 
-template <int MODE, int LG, bool CIRC, bool EXTK>
+template <int MODE, int LG, bool CIRC, bool EXTK, typename Tw>
 __device__ __forceinline__ void union_item(const AfArgs& a, const SegDesc& sg, WaveState& st, float2* lds,
-                                           float2* s_lds, double* scratch, const TwSplitSh& twl) {
+                                           float2* s_lds, double* scratch, const Tw& twl) {
     if constexpr (VU::fits(LG)) {
         constexpr int MH = 1 << LG;
+        constexpr bool UNPAD = !CIRC && union_unpad(LG);
         if (sg.wave != st.wave) {
             const WaveDesc w = a.waves[sg.wave];
-            stage_wave<MODE, VU::WGS, MH, CIRC>(a, w, sg.wave, s_lds, true, scratch, st, nullptr, 0);
+            stage_wave<MODE, VU::WGS, MH, CIRC, VU::P, UNPAD>(a, w, sg.wave, s_lds, true, scratch, st, nullptr, 0);
         }
-        process_segment<MODE, MH, VU::P, VU::SPLIT, VU::WGS, VU::nacc(LG), CIRC, EXTK>(a, sg, lds, twl, s_lds, true,
-                                                                                      scratch, st);
+        process_segment<MODE, MH, VU::P, VU::SPLIT, VU::WGS, VU::nacc(LG), CIRC, EXTK, false, UNPAD>(
+            a, sg, lds, twl, s_lds, true, scratch, st);
     }
 }
 
@@ -1222,31 +1247,42 @@ __global__ __launch_bounds__(VU::WGS, VU::WAVES) void af_union_kernel(AfArgs a) 
     float2* tw_lo = dyn + VU::buf_lds_bytes(LGMAX) / 8;
     float2* tw_hi = tw_lo + (1 << VU::split_bits(LGMAX));
     float2* tw_p1 = tw_hi + ((2 << LGMAX) >> VU::split_bits(LGMAX));
-    float2* s_lds = dyn + VU::fft_lds_bytes(LGMAX) / 8;
+    float2* region = dyn + VU::fft_lds_bytes(LGMAX) / 8;
+    float2* tw_p2 = CIRC ? nullptr : region;
+    float2* s_lds = CIRC ? region : region + kPass2Entries;
     const int b = (a.log2_mmax + 1) / 2;  // split bits of the plan's largest M
     const int mmax = 1 << a.log2_mmax;
     const int nlo = 1 << b, nhi = mmax >> b;
     const int np1 = mmax >= 256 ? kPass1Entries : 0;  // first-pass table (classes with M >= 256)
+    // stride-256 pass table (classes with M >= 1024): w_4096^(r k) where
+    // r k M_max / 4096 is a whole index of the plan's table; the entries a
+    // transform of M <= M_max reads are all of that kind
+    const int np2 = (!CIRC && mmax >= 1024) ? kPass2Entries : 0;
     if (threadIdx.x == 0) ticket = atomicAdd(a.queue, 1);
-    for (int j = threadIdx.x; j < nlo + nhi + np1; j += VU::WGS) {
+    for (int j = threadIdx.x; j < nlo + nhi + np1 + np2; j += VU::WGS) {
         if (j < nlo) {
             tw_lo[j] = a.tw[j];
         } else if (j < nlo + nhi) {
             tw_hi[j - nlo] = a.tw[(j - nlo) << b];
-        } else {
+        } else if (j < nlo + nhi + np1) {
             const int e = j - nlo - nhi, r = e / 16 + 1, k = e % 16;
             tw_p1[e] = a.tw[(r * k * (mmax / 256)) & (mmax - 1)];
+        } else {
+            const int e = j - nlo - nhi - np1, r = e / 256 + 1, k = e % 256;
+            const int t = r * k * mmax;
+            tw_p2[e] = (t & 4095) == 0 ? a.tw[(t >> 12) & (mmax - 1)] : make_float2(0.f, 0.f);
         }
     }
     __syncthreads();
     WaveState st;
     st.wave = -1;
+    using Tw = TwSplitSh<!CIRC>;
     for (;;) {
         const int item = ticket;  // the same for every thread of the group
         if (item >= a.n_segs) break;
         const SegDesc sg = a.segs[item];
         const int log2m = a.waves[sg.wave].log2m;
-        const TwSplitSh twl{tw_hi, tw_lo, b, a.log2_mmax - log2m, tw_p1};
+        const Tw twl{tw_hi, tw_lo, b, a.log2_mmax - log2m, tw_p1, tw_p2};
         switch (log2m - 1) {
             case 6: union_item<MODE, 6, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;
             case 7: union_item<MODE, 7, CIRC, EXTK>(a, sg, st, lds, s_lds, scratch, twl); break;

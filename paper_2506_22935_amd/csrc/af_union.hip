@@ -23,8 +23,9 @@ void* variant_kernel_6(int mode, int lg, int circ) {
     return circ ? union_mode<true>(mode) : union_mode<false>(mode);
 }
 
-// Sizes as the planner sees them: the LDS of the largest class (transform
-// buffers, short twiddle tables, samples padded to M = 8192) whatever lg.
+// Sizes as the planner sees them: the transform buffers and short tables of
+// the largest class whatever lg, then the region of the pass-2 table and the
+// samples (or the periodic samples staged twice) for the plan's largest lg.
 VariantInfo variant_info_6(int lg) {
     VariantInfo vi{};
     vi.lo = VU::LO;
@@ -39,6 +40,7 @@ VariantInfo variant_info_6(int lg) {
         vi.fits = 1;
         vi.fft_lds = VU::fft_lds_bytes(VU::HI);
         vi.nacc = VU::nacc(lg);
+        vi.s_bytes = union_region_bytes(lg);
     }
     return vi;
 }

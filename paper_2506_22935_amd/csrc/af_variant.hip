@@ -63,10 +63,12 @@ VariantInfo GRAF_CAT(variant_info_, GRAF_VARIANT)(int lg) {
     vi.fits = 0;
     vi.fft_lds = 0;
     vi.nacc = 0;
+    vi.s_bytes = 0;
     if (lg >= 1 && lg <= 15 && VSel::fits(lg)) {
         vi.fits = 1;
         vi.fft_lds = VSel::fft_lds_bytes(lg);
         vi.nacc = VSel::nacc(lg);
+        vi.s_bytes = VSel::S_LDS ? 8 * (2 << lg) : 0;  // samples zero-padded to M
     }
     return vi;
 }

@@ -185,6 +185,41 @@ def test_one_launch_matches_per_class_and_oracle(af):
         assert np.max(np.abs(g1[o:o + n] - ref["g"])) <= 1e-4 * np.max(np.abs(ref["g"])), b
 
 
+def test_one_launch_largest_size_edges(af):
+    # the largest transform (M = 8192) stages its samples unpadded and clamps
+    # the lag product's index: N = M/2 (every shifted index past the samples
+    # is clamped), the smallest N of that size, and N between, beside sizes
+    # whose stride-256 pass reads the pass table at a stride (M = 1024, 2048)
+    say("one launch, M = 8192 edges")
+    ns = [4096, 2049, 3001, 500, 1000, 64]
+    ms = [8192, 8192, 8192, 1024, 2048, 128]
+    codes = [W.random_code(n, seed=970 + i) for i, n in enumerate(ns)]
+    s = torch.from_numpy(np.concatenate(codes)).cuda()
+    one = af.Plan(ns, ms, eps=EPS)
+    per = af.Plan(ns, ms, eps=EPS, one_launch=False)
+    assert one.summary()["variant"] == 6 and per.summary()["variant"] != 6
+    lp = dict(w_isl=1.0, w_psl=1.0, temp=0.05)
+    t1, g1, a1 = one.loss(s, grad=True, mag=True, **lp)
+    t2, g2, a2 = per.loss(s, grad=True, mag=True, **lp)
+    torch.cuda.synchronize()
+    assert np.allclose(t1.cpu().numpy(), t2.cpu().numpy(), rtol=1e-5, atol=1e-6)
+    assert float((a1 - a2).abs().max()) <= 1e-6
+    g1 = g1.cpu().numpy().astype(np.complex128)
+    g2 = g2.cpu().numpy().astype(np.complex128)
+    for b, n in enumerate(ns):
+        o = one.s_offsets[b]
+        assert np.max(np.abs(g1[o:o + n] - g2[o:o + n])) <= 1e-5 * np.max(np.abs(g2[o:o + n])), b
+    # the sizes the oracle runs in seconds, against the oracle
+    t1 = t1.cpu().numpy()
+    for b in (3, 5):
+        n, m = ns[b], ms[b]
+        ref = O.loss_and_grad(O.to_c64_exact(codes[b]), m, n - 1,
+                              O.LossParams(eps=EPS, h_tau=1, h_k=1, w_isl=1.0, w_psl=1.0, temp=0.05))
+        assert abs(t1[b, 0] - ref["loss"]) <= 1e-4 * abs(ref["loss"])
+        o = one.s_offsets[b]
+        assert np.max(np.abs(g1[o:o + n] - ref["g"])) <= 1e-4 * np.max(np.abs(ref["g"])), b
+
+
 def test_one_launch_is_deterministic(af):
     # work groups take items by atomic ticket, so the assignment changes from
     # run to run; every item writes its own slab and record, so the results
