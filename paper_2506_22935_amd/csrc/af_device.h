@@ -189,6 +189,15 @@ __device__ __forceinline__ float2 twiddle_const(float2 v) {
     }
 }
 
+// v[K] *= exp(SIGN j 2 pi K / R) for every slot K < P (compile-time constants)
+template <int R, int SIGN, int P, int K = 0>
+__device__ __forceinline__ void twist_const(float2* v) {
+    if constexpr (K < P) {
+        v[K] = twiddle_const<K, R, SIGN>(v[K]);
+        twist_const<R, SIGN, P, K + 1>(v);
+    }
+}
+
 // -------------------------------------------------------- register DFTs --
 // In-place DFT of R values held in registers, natural order in and out.
 template <int R, int SIGN>
