@@ -497,13 +497,10 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     int hi = 0;
     float lm = (want_lse && (lse_fixed || MODE == MODE_LOSS)) ? lse_ref(x_eps) : -INFINITY;
 
-    // the odd half's factor w_M^m at the lane's points m = l + r L: with
-    // per-pass tables one half-table read per point; with two-factor tables
-    // w_M^l read once per lane (returned here) times the constant
+    // the odd half's factor w_M^m at the lane's points m = l + r L: w_M^l,
+    // read once per lane (returned here), times the constant
     // w_M^(r L) = exp(-j 2 pi r / 2P)
-    auto odd_base = [&](int h) {
-        return (!Tw::kPassTables && h) ? twl.low(l) : make_float2(1.f, 0.f);
-    };
+    auto odd_base = [&](int h) { return h ? twl.low(l) : make_float2(1.f, 0.f); };
     // Y' of lag tau, half h, in the exit layout v[q] = Y'[2 (l + qL) + h]
     auto lag_spectrum = [&](float2* v, int h, int tau, bool active) {
         if (CIRC) {
@@ -527,11 +524,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 const int m = l + r * L;
                 // UNPAD: entry MH is zero, as is every entry from N on
                 float2 x = cmulc(sv[UNPAD ? min(m + tz, MH) : m + tz], sv[m]);
-                if (h) x = cmul(x, Tw::kPassTables ? twl.low(m) : c);
+                if (h) x = cmul(x, c);
                 v[r] = x;
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
-            if (!Tw::kPassTables && h) twist_const<2 * P, -1, P>(v);
+            if (h) twist_const<2 * P, -1, P>(v);
         } else {
             // samples through the buffer resource over [0, N): the range
             // check zeroes s[m + tau] for m >= N - tau; an inactive lag reads
@@ -542,12 +539,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             for (int r = 0; r < P; ++r) {
                 const int m = l + r * L;
                 float2 x = cmulc(buf_load2(s_rs, (m + tz) * 8), buf_load2(s_rs, m * 8));
-                if (h) x = cmul(x, Tw::kPassTables ? twl.low(m) : c);
+                if (h) x = cmul(x, c);
                 v[r] = x;
                 // bound how many loads the scheduler keeps in flight
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
-            if (!Tw::kPassTables && h) twist_const<2 * P, -1, P>(v);
+            if (h) twist_const<2 * P, -1, P>(v);
         }
         fft_group<MH, P, -1, (WGS >= 1024)>(v, buf, l, twl, sync);
     };
@@ -558,8 +555,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         if (h) {
             const float2 c = odd_base(h);
 #pragma unroll
-            for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], Tw::kPassTables ? twl.low(l + q * L) : c);
-            if (!Tw::kPassTables) twist_const<2 * P, +1, P>(v);
+            for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], c);
+            twist_const<2 * P, +1, P>(v);
         }
         if constexpr (L % 32 == 0) {
             const int bi = lds_index(l);
