@@ -499,8 +499,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
 
     // the odd half's factor w_M^m at the lane's points m = l + r L: w_M^l,
     // read once per lane (returned here), times the constant
-    // w_M^(r L) = exp(-j 2 pi r / 2P)
-    auto odd_base = [&](int h) { return h ? twl.low(l) : make_float2(1.f, 0.f); };
+    // w_M^(r L) = exp(-j 2 pi r / 2P).  The 1024-thread variant (128
+    // registers) keeps one table read per point: the constants' extra live
+    // values cost its backward more than the reads
+    constexpr bool FOLD = WGS < 1024;
+    auto odd_base = [&](int h) { return (FOLD && h) ? twl.low(l) : make_float2(1.f, 0.f); };
     // Y' of lag tau, half h, in the exit layout v[q] = Y'[2 (l + qL) + h]
     auto lag_spectrum = [&](float2* v, int h, int tau, bool active) {
         if (CIRC) {
@@ -539,12 +542,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             for (int r = 0; r < P; ++r) {
                 const int m = l + r * L;
                 float2 x = cmulc(buf_load2(s_rs, (m + tz) * 8), buf_load2(s_rs, m * 8));
-                if (h) x = cmul(x, c);
+                if (h) x = cmul(x, FOLD ? c : twl.low(m));
                 v[r] = x;
                 // bound how many loads the scheduler keeps in flight
                 if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
-            if (h) twist_const<2 * P, -1, P>(v);
+            if (FOLD && h) twist_const<2 * P, -1, P>(v);
         }
         fft_group<MH, P, -1, (WGS >= 1024)>(v, buf, l, twl, sync);
     };
@@ -555,8 +558,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
         if (h) {
             const float2 c = odd_base(h);
 #pragma unroll
-            for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], c);
-            twist_const<2 * P, +1, P>(v);
+            for (int q = 0; q < P; ++q) v[q] = cmulc(v[q], FOLD ? c : twl.low(l + q * L));
+            if (FOLD) twist_const<2 * P, +1, P>(v);
         }
         if constexpr (L % 32 == 0) {
             const int bi = lds_index(l);
