@@ -25,7 +25,8 @@ __all__ = [
     "to_c64_exact", "energy", "chi", "chi_rows", "magnitude", "power",
     "centred_bins", "mainlobe_mask", "isl_weights", "LossParams", "loss_terms",
     "loss_and_grad", "loss_grad_from_chi", "sigmoid", "soft_mainlobe_width", "modulus_variance",
-    "phase_smoothness", "spectral_projection", "cross_chi", "cross_magnitude_backward",
+    "phase_smoothness", "spectral_projection", "cross_chi", "cross_magnitude_backward", "cross_chi_circular",
+    "cross_magnitude_backward_circular",
     "multi_scenario_loss_and_grad", "combine_scenario_weights", "magnitude_backward", "grad_from_upstream", "phase_grad",
     "adam_step", "bf16_round", "gelu", "gelu_grad", "mlp_forward",
     "mlp_backward", "psl_db", "chi_rows_fft", "magnitude_backward_fft",
@@ -563,6 +564,55 @@ def cross_magnitude_backward(s, u, m, max_lag, grad_mag, eps):
         ok = (j >= 0) & (j < n)
         gs[ok] += u[j[ok]] * Q[i, ok]
         np.add.at(gu, j[ok], s[ok] * np.conj(Q[i, ok]))
+    q = float(np.sum(ga * p / a))
+    return gs - q / (2.0 * Es) * s, gu - q / (2.0 * Eu) * u
+
+
+# periodic form (the circular lags of Eq. 2 applied to the cross-AF): rows
+# tau = 0..N-1, bins k over N, chi_su[tau, k] = sum_n s[n] conj(u[(n - tau)
+# mod N]) exp(-j 2 pi k n / N)
+
+def _cross_products_circular(s, u):
+    """Rows tau = 0..N-1 of x_tau[n] = s[n] conj(u[(n - tau) mod N])."""
+    n = s.shape[0]
+    idx = np.arange(n)
+    X = np.empty((n, n), dtype=np.complex128)
+    for tau in range(n):
+        X[tau] = s * np.conj(u[(idx - tau) % n])
+    return X
+
+
+def cross_chi_circular(s, u, bins=None):
+    """The periodic cross-AF grid [N, N] by its defining sum; with bins,
+    only those columns."""
+    s = np.asarray(s, dtype=np.complex128)
+    u = np.asarray(u, dtype=np.complex128)
+    n = s.shape[0]
+    return _cross_products_circular(s, u) @ _dft_matrix(n, n, bins)
+
+
+def cross_magnitude_backward_circular(s, u, grad_mag, eps):
+    """(dL/d conj(s), dL/d conj(u)) for an upstream dL/da on the periodic
+    cross-AF magnitude grid: as cross_magnitude_backward with the sample
+    indices taken modulo N and Q_tau[n] = sum_k G[tau, k] exp(+j 2 pi k n / N)."""
+    s = np.asarray(s, dtype=np.complex128)
+    u = np.asarray(u, dtype=np.complex128)
+    n = s.shape[0]
+    F = _dft_matrix(n, n)
+    c = _cross_products_circular(s, u) @ F
+    Es, Eu = energy(s), energy(u)
+    p = (c.real ** 2 + c.imag ** 2) / (Es * Eu)
+    a = np.sqrt(p + eps)
+    ga = np.asarray(grad_mag, dtype=np.float64)
+    G = ga * c / (2.0 * Es * Eu * a)
+    Q = G @ np.conj(F).T
+    gs = np.zeros(n, dtype=np.complex128)
+    gu = np.zeros(n, dtype=np.complex128)
+    idx = np.arange(n)
+    for tau in range(n):
+        j = (idx - tau) % n
+        gs += u[j] * Q[tau]
+        np.add.at(gu, j, s * np.conj(Q[tau]))
     q = float(np.sum(ga * p / a))
     return gs - q / (2.0 * Es) * s, gu - q / (2.0 * Eu) * u
 

@@ -830,6 +830,57 @@ def test_cross_magnitude_backward_finite_differences():
     assert np.max(np.abs(ga + gb - ref)) < 1e-9 * np.max(np.abs(ref))
 
 
+def test_cross_af_periodic_pins():
+    n = 16
+    s = rand_complex(n, 56)
+    u = rand_complex(n, 57)
+    c = O.cross_chi_circular(s, u)
+    # u = s: the periodic AF (the C core's direct sum)
+    cs = O.cross_chi_circular(s, s)
+    ref = O.chi_circular(s)
+    assert np.max(np.abs(cs - ref)) < 1e-12 * np.max(np.abs(ref))
+    # periodic lag tau collects the aperiodic cross lags tau and tau - N (M = N)
+    ap = O.cross_chi(s, u, n)
+    T = n - 1
+    for tau in range(n):
+        row = ap[T + tau] + (ap[T + tau - n] if tau > 0 else 0.0)
+        assert np.max(np.abs(c[tau] - row)) < 1e-12 * np.max(np.abs(c))
+    # Parseval over each row: sum over the grid of |chi_su|^2 = N E_s E_u
+    vol = float(np.sum(np.abs(c) ** 2))
+    assert abs(vol - n * O.energy(s) * O.energy(u)) < 1e-12 * vol
+    # a circular delay of u moves the rows: u[n] = s[(n - d) mod N] gives
+    # chi_su[tau] = chi_ss[(tau + d) mod N]
+    d = 5
+    c2 = O.cross_chi_circular(s, np.roll(s, d))
+    assert np.max(np.abs(c2 - np.roll(ref, -d, axis=0))) < 1e-12 * np.max(np.abs(ref))
+    # selected bins are the matching columns
+    assert np.max(np.abs(O.cross_chi_circular(s, u, bins=[0, 3, 15]) - c[:, [0, 3, 15]])) < 1e-12
+
+
+def test_cross_magnitude_backward_circular_finite_differences():
+    n = 8
+    s = rand_complex(n, 58)
+    u = rand_complex(n, 59)
+    w = np.random.default_rng(60).standard_normal((n, n))
+    eps = 1e-9
+
+    def f(x, y):
+        c = O.cross_chi_circular(x, y)
+        p = np.abs(c) ** 2 / (O.energy(x) * O.energy(y))
+        return float(np.sum(w * np.sqrt(p + eps)))
+
+    gs, gu = O.cross_magnitude_backward_circular(s, u, w, eps)
+    fs = _fd_grad(lambda x: f(x, u), s)
+    fu = _fd_grad(lambda y: f(s, y), u)
+    assert np.max(np.abs(gs - fs)) < 1e-6 * np.max(np.abs(fs))
+    assert np.max(np.abs(gu - fu)) < 1e-6 * np.max(np.abs(fu))
+    # with u = s the two gradients add up to the periodic AF's magnitude
+    # backward (the C core's adjoint)
+    ga, gb = O.cross_magnitude_backward_circular(s, s, w, eps)
+    ref = O.magnitude_backward_circular(s, w, eps)
+    assert np.max(np.abs(ga + gb - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
 # ---- multi-scenario loss (Eq. 24) and per-cell weight grids
 
 def test_cell_weights_reduce_to_weighted_isl():
