@@ -1139,7 +1139,7 @@ namespace {
 af_status check_cross(const af_plan* p, const void* s, const void* u) {
     if (!p || !s || !u || !aligned(s, 8) || !aligned(u, 8)) return AF_ERR_INVALID_ARG;
     for (const af_plan::XClass& k : p->xclasses)
-        if (k.circ || !graf::cross_lg_supported(k.lg)) return AF_ERR_UNSUPPORTED;
+        if (!graf::cross_lg_supported(k.lg)) return AF_ERR_UNSUPPORTED;
     // the kernels move the a and dL/da grids as 8-byte bin pairs
     for (const af_wave& w : p->waves)
         if (w.grid_off & 1) return AF_ERR_INVALID_ARG;
@@ -1165,7 +1165,7 @@ af_status launch_cross_classes(const af_plan* p, int mode, graf::CrossArgs a, hi
     const SegDesc* segs = p->one_active ? p->d_segs_x : p->d_segs;
     for (const af_plan::XClass& k : p->xclasses) {
         a.segs = segs + k.begin;
-        if (graf::launch_cross(mode, k.lg, a, k.count, st) != hipSuccess) return AF_ERR_HIP;
+        if (graf::launch_cross(mode, k.lg, k.circ, a, k.count, st) != hipSuccess) return AF_ERR_HIP;
     }
     return AF_OK;
 }

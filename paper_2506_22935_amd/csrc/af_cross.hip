@@ -22,6 +22,12 @@
 // (the gather splits into two outputs).  Per-segment slabs of both, and the
 // segment's sum of g_a p / a, are added in a fixed order by xreduce_kernel,
 // which applies dL/dE_s = -sum g_a p / (2 a E_s) (and E_u alike).
+//
+// CIRC: the periodic cross-AF of N = MH samples (sample indices modulo N, N
+// Doppler bins, grid [N][N] with row tau in [0, N)): lag tau of the plan's
+// list (tau in [0, N/2]) gives rows tau and N - tau, each one N-point
+// transform (the even half of the M = 2N split), and the gather takes its
+// indices modulo N.
 #include "af_internal.h"
 #include "af_device.h"
 
@@ -49,7 +55,7 @@ struct XShape {
     static constexpr int lds_bytes() { return (G * BUF + 2 * MH) * 8; }
 };
 
-template <int MODE, int LG>
+template <int MODE, int LG, bool CIRC>
 __global__ __launch_bounds__(XWGS) void xaf_kernel(CrossArgs a) {
     using S = XShape<LG>;
     constexpr int MH = S::MH, L = S::L, G = S::G, BUF = S::BUF, NJ = S::NJ;
@@ -92,19 +98,20 @@ __global__ __launch_bounds__(XWGS) void xaf_kernel(CrossArgs a) {
     for (int j = 0; j < NJ; ++j) gs[j] = gu[j] = make_float2(0.f, 0.f);
     float qsum = 0.f;
     auto sync = []() { __syncthreads(); };
-    // job j of the segment: lag tau_begin + j/2, sign + (j even) or - (j odd)
+    // job j of the segment: lag tau_begin + j/2, sign + (j even) or - (j odd);
+    // periodic: the row N - lag for the minus sign (none for lags 0 and N/2)
     auto job_tau = [&](int job, bool& active) {
         const int lag = sg.tau_begin + (job >> 1);
         const bool neg = (job & 1) != 0;
-        active = job < 2 * (sg.tau_end - sg.tau_begin) && !(neg && lag == 0);
-        return active ? (neg ? -lag : lag) : 0;
+        active = job < 2 * (sg.tau_end - sg.tau_begin) && !(neg && (lag == 0 || (CIRC && 2 * lag == N)));
+        return active ? (neg ? (CIRC ? N - lag : -lag) : lag) : 0;
     };
 
     const int jobs = 2 * (sg.tau_end - sg.tau_begin);
     for (int j0 = 0; j0 < jobs; j0 += G) {
         bool active;
         const int tau = job_tau(j0 + grp, active);
-        const int64_t row = w.grid_off + (int64_t)(T + tau) * M;
+        const int64_t row = CIRC ? w.grid_off + (int64_t)tau * MH : w.grid_off + (int64_t)(T + tau) * M;
         float2 qa[XP];
         // the forward writes bins 2(l + qL) and 2(l + qL) + 1 of the row (the
         // two halves) as one 8-byte pair, holding the even half's magnitudes
@@ -112,29 +119,38 @@ __global__ __launch_bounds__(XWGS) void xaf_kernel(CrossArgs a) {
         // per bin: reading pairs and holding the odd half measured slower)
         float hold[XP];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < (CIRC ? 1 : 2); ++h) {
             float2 v[XP];
 #pragma unroll
             for (int r = 0; r < XP; ++r) {
                 const int n = l + r * L;
-                const int j = n - tau;
-                const bool in = active && n < N && j >= 0 && j < N;
-                float2 x = cmulc(sv[n], uv[in ? j : 0]);
-                x = in ? x : make_float2(0.f, 0.f);
-                if (h) x = cmul(x, twl(n));
-                v[r] = x;
+                if constexpr (CIRC) {
+                    // u[(n - tau) mod N], N = MH
+                    const float2 x = cmulc(sv[n], uv[(n - tau) & (MH - 1)]);
+                    v[r] = active ? x : make_float2(0.f, 0.f);
+                } else {
+                    const int j = n - tau;
+                    const bool in = active && n < N && j >= 0 && j < N;
+                    float2 x = cmulc(sv[n], uv[in ? j : 0]);
+                    x = in ? x : make_float2(0.f, 0.f);
+                    if (h) x = cmul(x, twl(n));
+                    v[r] = x;
+                }
             }
             fft_group<MH, XP, -1>(v, buf, l, twl, sync);
 #pragma unroll
             for (int q = 0; q < XP; ++q) {
-                const int k = 2 * (l + q * L) + h;
+                const int k = CIRC ? l + q * L : 2 * (l + q * L) + h;
                 const float pw = cabs2(v[q]) * invEE;
                 if constexpr (MODE == 0) {
                     const float av = __builtin_amdgcn_sqrtf(pw + a.eps);
-                    if (h == 0)
+                    if (CIRC) {
+                        if (active && a.mag) a.mag[row + k] = av;
+                    } else if (h == 0) {
                         hold[q] = av;
-                    else if (active && a.mag)
+                    } else if (active && a.mag) {
                         *reinterpret_cast<float2*>(a.mag + row + 2 * (l + q * L)) = make_float2(hold[q], av);
+                    }
                     if (active && a.chi) a.chi[row + k] = v[q];
                 } else {
                     const float g = active ? a.grad_mag[row + k] : 0.f;
@@ -167,10 +183,16 @@ __global__ __launch_bounds__(XWGS) void xaf_kernel(CrossArgs a) {
                     const int tg = job_tau(j0 + g, act);
                     if (!act) continue;
                     const float2* Q = dyn + g * BUF;
-                    const int jm = i - tg;
-                    if (jm >= 0 && jm < N) gs[jj] = cadd(gs[jj], cmul(uv[jm], Q[lds_index(i)]));
-                    const int jp = i + tg;
-                    if (jp >= 0 && jp < N) gu[jj] = cadd(gu[jj], cmulc(sv[jp], Q[lds_index(jp)]));
+                    if constexpr (CIRC) {
+                        const int jm = (i - tg) & (MH - 1), jp = (i + tg) & (MH - 1);
+                        gs[jj] = cadd(gs[jj], cmul(uv[jm], Q[lds_index(i)]));
+                        gu[jj] = cadd(gu[jj], cmulc(sv[jp], Q[lds_index(jp)]));
+                    } else {
+                        const int jm = i - tg;
+                        if (jm >= 0 && jm < N) gs[jj] = cadd(gs[jj], cmul(uv[jm], Q[lds_index(i)]));
+                        const int jp = i + tg;
+                        if (jp >= 0 && jp < N) gu[jj] = cadd(gu[jj], cmulc(sv[jp], Q[lds_index(jp)]));
+                    }
                 }
             }
             __syncthreads();
@@ -221,30 +243,30 @@ __global__ __launch_bounds__(256) void xreduce_kernel(CrossArgs a) {
     a.grad_u[w.s_off + i] = cadd(gu, cscale(u, -q / (2.f * Eu)));
 }
 
-template <int MODE, int LG>
+template <int MODE, int LG, bool CIRC>
 hipError_t launch_lg(const CrossArgs& a, int grid, hipStream_t st) {
     static bool attr = false;
-    const void* k = (const void*)xaf_kernel<MODE, LG>;
+    const void* k = (const void*)xaf_kernel<MODE, LG, CIRC>;
     constexpr int lds = XShape<LG>::lds_bytes();
     if (!attr) {
         const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((xaf_kernel<MODE, LG>), dim3(grid), dim3(XWGS), (size_t)lds, st, a);
+    hipLaunchKernelGGL((xaf_kernel<MODE, LG, CIRC>), dim3(grid), dim3(XWGS), (size_t)lds, st, a);
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool CIRC>
 hipError_t launch_mode(int lg, const CrossArgs& a, int grid, hipStream_t st) {
     switch (lg) {
-        case 6: return launch_lg<MODE, 6>(a, grid, st);
-        case 7: return launch_lg<MODE, 7>(a, grid, st);
-        case 8: return launch_lg<MODE, 8>(a, grid, st);
-        case 9: return launch_lg<MODE, 9>(a, grid, st);
-        case 10: return launch_lg<MODE, 10>(a, grid, st);
-        case 11: return launch_lg<MODE, 11>(a, grid, st);
-        case 12: return launch_lg<MODE, 12>(a, grid, st);
+        case 6: return launch_lg<MODE, 6, CIRC>(a, grid, st);
+        case 7: return launch_lg<MODE, 7, CIRC>(a, grid, st);
+        case 8: return launch_lg<MODE, 8, CIRC>(a, grid, st);
+        case 9: return launch_lg<MODE, 9, CIRC>(a, grid, st);
+        case 10: return launch_lg<MODE, 10, CIRC>(a, grid, st);
+        case 11: return launch_lg<MODE, 11, CIRC>(a, grid, st);
+        case 12: return launch_lg<MODE, 12, CIRC>(a, grid, st);
     }
     return hipErrorInvalidValue;
 }
@@ -253,9 +275,10 @@ hipError_t launch_mode(int lg, const CrossArgs& a, int grid, hipStream_t st) {
 
 bool cross_lg_supported(int lg) { return lg >= 6 && lg <= 12; }
 
-hipError_t launch_cross(int mode, int lg, const CrossArgs& a, int grid, hipStream_t st) {
+hipError_t launch_cross(int mode, int lg, int circ, const CrossArgs& a, int grid, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
-    return mode == 0 ? launch_mode<0>(lg, a, grid, st) : launch_mode<1>(lg, a, grid, st);
+    if (circ) return mode == 0 ? launch_mode<0, true>(lg, a, grid, st) : launch_mode<1, true>(lg, a, grid, st);
+    return mode == 0 ? launch_mode<0, false>(lg, a, grid, st) : launch_mode<1, false>(lg, a, grid, st);
 }
 
 hipError_t launch_cross_reduce(const CrossArgs& a, int batch, int max_n, hipStream_t st) {

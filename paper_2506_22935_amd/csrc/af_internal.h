@@ -213,7 +213,7 @@ struct CrossArgs {
     float2* grad_u;
 };
 bool cross_lg_supported(int lg);
-hipError_t launch_cross(int mode, int lg, const CrossArgs& a, int grid, hipStream_t st);
+hipError_t launch_cross(int mode, int lg, int circ, const CrossArgs& a, int grid, hipStream_t st);
 hipError_t launch_cross_reduce(const CrossArgs& a, int batch, int max_n, hipStream_t st);
 
 // launchers (af_reduce.hip)

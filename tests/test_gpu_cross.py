@@ -1,7 +1,8 @@
 """Cross-ambiguity of two waveforms on the HIP path against the oracle
 (GPU): the magnitude and chi_su grids, and the backward for both inputs, over
-one-waveform and uneven plans (the cross-AF extension of the paper's
-limitations section)."""
+one-waveform and uneven plans, aperiodic and periodic (circular lags) and
+both in one plan (the cross-AF extension of the paper's limitations
+section)."""
 import sys
 
 import numpy as np
@@ -115,13 +116,88 @@ def test_cross_uneven_batch(af):
         so += n
 
 
+@pytest.mark.parametrize("n", [64, 256, 1024, 4096])
+def test_cross_periodic_forward(af, n):
+    # the periodic cross-AF (circular lags, N x N grid) against the oracle's
+    # defining sum; sampled bins at N = 4096
+    say("cross periodic forward", n)
+    s, u = rand_c64(n, 8000 + n), rand_c64(n, 8100 + n)
+    plan = af.Plan([n], [n], eps=EPS, periodic=True)
+    mag, chi, e = plan.cross_forward(to_dev(s), to_dev(u), mag=True, chi=True)
+    torch.cuda.synchronize()
+    Es, Eu = O.energy(s), O.energy(u)
+    assert abs(e[0, 0].item() - Es) <= 1e-5 * Es and abs(e[0, 1].item() - Eu) <= 1e-5 * Eu
+    bins = None if n <= 1024 else np.random.default_rng(n).choice(n, 64, replace=False)
+    ref = O.cross_chi_circular(s, u, bins)
+    a_ref = np.sqrt(np.abs(ref) ** 2 / (Es * Eu) + EPS)
+    g_mag = mag.cpu().numpy().reshape(n, n).astype(np.float64)
+    g_chi = chi.cpu().numpy().reshape(n, n).astype(np.complex128)
+    if bins is not None:
+        g_mag, g_chi = g_mag[:, bins], g_chi[:, bins]
+    assert np.max(np.abs(g_mag - a_ref)) <= 1e-5
+    assert np.max(np.abs(g_chi - ref)) <= 1e-5 * np.sqrt(Es * Eu)
+
+
+def test_cross_periodic_with_itself_is_the_periodic_af(af):
+    say("cross periodic u = s")
+    n = 256
+    s = rand_c64(n, 8200)
+    plan = af.Plan([n], [n], eps=EPS, periodic=True)
+    mag, _, _ = plan.cross_forward(to_dev(s), to_dev(s))
+    torch.cuda.synchronize()
+    ref = O.magnitude(O.chi_circular(s), O.energy(s), EPS)
+    assert np.max(np.abs(mag.cpu().numpy().reshape(n, n) - ref)) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [64, 256, 1024])
+def test_cross_periodic_backward(af, n):
+    say("cross periodic backward", n)
+    s, u = rand_c64(n, 8300 + n), rand_c64(n, 8400 + n)
+    w = np.random.default_rng(n + 7).standard_normal((n, n)).astype(np.float32)
+    plan = af.Plan([n], [n], eps=EPS, periodic=True)
+    gs, gu = plan.cross_backward(to_dev(s), to_dev(u), torch.from_numpy(w.ravel()).cuda())
+    gs2, gu2 = plan.cross_backward(to_dev(s), to_dev(u), torch.from_numpy(w.ravel()).cuda())
+    torch.cuda.synchronize()
+    rs, ru = O.cross_magnitude_backward_circular(s, u, w.astype(np.float64), EPS)
+    for g, r, name in ((gs, rs, "s"), (gu, ru, "u")):
+        err = np.max(np.abs(g.cpu().numpy().astype(np.complex128) - r))
+        assert err <= 1e-4 * np.max(np.abs(r)), (name, err, np.max(np.abs(r)))
+    assert torch.equal(gs, gs2) and torch.equal(gu, gu2)
+
+
+def test_cross_mixed_periodic_and_aperiodic(af):
+    # periodic and aperiodic waveforms of several sizes in one plan
+    say("cross mixed lag kinds")
+    sizes, ms, per = [64, 100, 256, 300, 128], [64, 256, 256, 1024, 128], [True, False, True, False, True]
+    ss = [rand_c64(n, 8500 + i) for i, n in enumerate(sizes)]
+    us = [rand_c64(n, 8600 + i) for i, n in enumerate(sizes)]
+    plan = af.Plan(sizes, ms, eps=EPS, periodic=per)
+    rows = [n if p else 2 * n - 1 for n, p in zip(sizes, per)]
+    ws_ = [np.random.default_rng(40 + i).standard_normal((r, m)).astype(np.float32) for i, (r, m) in
+           enumerate(zip(rows, ms))]
+    sd, ud = to_dev(np.concatenate(ss)), to_dev(np.concatenate(us))
+    mag, _, _ = plan.cross_forward(sd, ud)
+    gs, gu = plan.cross_backward(sd, ud, torch.from_numpy(np.concatenate([w.ravel() for w in ws_])).cuda())
+    torch.cuda.synchronize()
+    mg, gsn, gun = mag.cpu().numpy(), gs.cpu().numpy(), gu.cpu().numpy()
+    go = so = 0
+    for s, u, n, m, p, r, w in zip(ss, us, sizes, ms, per, rows, ws_):
+        c = O.cross_chi_circular(s, u) if p else O.cross_chi(s, u, m, n - 1)
+        ref = np.sqrt(np.abs(c) ** 2 / (O.energy(s) * O.energy(u)) + EPS)
+        assert np.max(np.abs(mg[go:go + r * m].reshape(r, m) - ref)) <= 1e-5, n
+        if p:
+            rs, ru = O.cross_magnitude_backward_circular(s, u, w.astype(np.float64), EPS)
+        else:
+            rs, ru = O.cross_magnitude_backward(s, u, m, n - 1, w.astype(np.float64), EPS)
+        assert np.max(np.abs(gsn[so:so + n] - rs)) <= 1e-4 * np.max(np.abs(rs)), n
+        assert np.max(np.abs(gun[so:so + n] - ru)) <= 1e-4 * np.max(np.abs(ru)), n
+        go += r * m
+        so += n
+
+
 def test_cross_rejections(af):
     from paper_2506_22935_amd import _lib
     s = to_dev(rand_c64(128, 1))
-    per = af.Plan([128], [128], eps=EPS, periodic=True)
-    with pytest.raises(_lib.AfError) as ei:
-        per.cross_forward(s, s)
-    assert ei.value.code == -2
     big = af.Plan([5000], [16384], [10], eps=EPS)
     b = to_dev(rand_c64(5000, 2))
     with pytest.raises(_lib.AfError) as ei:
