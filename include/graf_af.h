@@ -123,9 +123,8 @@ typedef struct af_plan af_plan;
  * (p(tau, 0) - 1/2)) (p(0, 0) = 1 for every waveform, so half of it is the
  * -3 dB level of Eq. 20; |tau| is min(tau, N - tau) on the periodic AF);
  * gamma >= 0 sets the sharpness; like L_match it does not combine with the
- * soft PSL.  The hard PSL, L_match and the width need plans whose size
- * classes run split variants (M <= 8192, or a periodic N <= 4096);
- * AF_ERR_UNSUPPORTED otherwise.  w_const weights var(|s|) (L_const of
+ * soft PSL.  The hard PSL, L_match, the width and the cell weights run on
+ * every size class (M up to 32768).  w_const weights var(|s|) (L_const of
  * Sec. 5.2, population variance; its gradient is taken as 0 at s[n] = 0),
  * w_smooth a phase-continuity term (Sec. 6.2), sum_{n < N-1} |s[n+1] -
  * s[n]|^2 / E, which for a unit-modulus code is (2/N) sum (1 - cos of the

@@ -643,11 +643,11 @@ af_status check_loss(const af_plan* p, const af_loss_params* lp) {
     // ISL passes: not with the soft PSL
     if ((lp->w_match != 0.f || lp->w_width != 0.f || lp->w_cell != 0.f) && lp->w_psl != 0.f && !lp->psl_hard)
         return AF_ERR_UNSUPPORTED;
-    // the hard PSL, L_match, the width and the cell weights run in the split
-    // variants (M <= 8192)
+    // the hard PSL, L_match, the width and the cell weights need every
+    // class's extended instances
     if (extended_terms(lp))
         for (const af_plan::Class& k : p->classes)
-            if (!graf::variant_info(k.variant, k.lg).split) return AF_ERR_UNSUPPORTED;
+            if (k.grid[graf::MODE_FUSED_EXT] <= 0 || k.grid[graf::MODE_FWD_EXT] <= 0) return AF_ERR_UNSUPPORTED;
     if (lp->w_spec != 0.f && p->max_n > kMaxSpecN) return AF_ERR_UNSUPPORTED;
     return AF_OK;
 }

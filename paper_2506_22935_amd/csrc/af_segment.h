@@ -474,9 +474,8 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     double isl = 0.0, ls = 0.0, dle = 0.0, mt = 0.0;
     // L_match against a target power grid, the soft mainlobe width, a
     // per-cell weight grid and the hard-PSL maximum (forward and fused ISL
-    // modes; the extended epilogue copy; split variants only: the
-    // halves-in-turn variant keeps its registers)
-    constexpr bool EXT_OK = SPLIT && EXT_MODE<MODE, EXTK>();
+    // modes; the extended epilogue copy)
+    constexpr bool EXT_OK = EXT_MODE<MODE, EXTK>();
     const bool match = EXT_OK && a.match_t != nullptr;
     const bool width = EXT_OK && a.w_width != 0.f;
     const bool cellw = EXT_OK && a.cell_w != nullptr;
@@ -670,10 +669,12 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                 // out together before the cells' arithmetic, so one memory
                 // round trip serves the lane's P cells.  Plain per-lane
                 // pointers: the lag, and so the row, differs between the lane
-                // groups of a wavefront
-                constexpr int XR = EXT == 2 ? P : 1;
+                // groups of a wavefront.  The halves-in-turn variant (128
+                // registers) reads each cell's values where it uses them.
+                constexpr bool BATCH = EXT == 2 && SPLIT;
+                constexpr int XR = BATCH ? P : 1;
                 float tg_p[XR], tg_n[XR], cw_p[XR], cw_n[XR];
-                if constexpr (EXT == 2) {
+                if constexpr (BATCH) {
 #pragma unroll
                     for (int q = 0; q < P; ++q) {
                         const int k = CIRC ? l + q * L : 2 * (l + q * L) + h;
@@ -762,8 +763,9 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                     }
                     if (EXT == 2 && cellw) {
                         // W p on both cells of the pair, each with its own weight
-                        const float wp = cw_p[EXT == 2 ? q : 0];
-                        const float wn = cw_n[EXT == 2 ? q : 0];
+                        const float wp = BATCH ? cw_p[BATCH ? q : 0] : (active ? x_cell_w[row_p + k] : 0.f);
+                        const float wn = BATCH ? cw_n[BATCH ? q : 0]
+                                               : ((active && two_rows) ? x_cell_w[row_n + kn] : 0.f);
                         cw_f = fmaf(wp + wn, pw, cw_f);
                         if constexpr (NEEDS_INV) {
                             cm += x_w_cell * (wp + wn) * invE2;
@@ -771,8 +773,11 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                         }
                     }
                     if (EXT == 2 && match) {
-                        const float dp = active ? pw - tg_p[EXT == 2 ? q : 0] : 0.f;
-                        const float dn = (active && two_rows) ? pw - tg_n[EXT == 2 ? q : 0] : 0.f;
+                        const float tp = BATCH ? tg_p[BATCH ? q : 0] : (active ? x_match_t[row_p + k] : 0.f);
+                        const float tn = BATCH ? tg_n[BATCH ? q : 0]
+                                               : ((active && two_rows) ? x_match_t[row_n + kn] : 0.f);
+                        const float dp = active ? pw - tp : 0.f;
+                        const float dn = (active && two_rows) ? pw - tn : 0.f;
                         mt_f = fmaf(dp, dp, fmaf(dn, dn, mt_f));
                         if constexpr (NEEDS_INV) {
                             cm += 2.f * x_w_match * (dp + dn) * invE2;
@@ -832,16 +837,14 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             };
             // the hot fused passes also get a copy without mainlobe logic for
             // the lags beyond the mainlobe (tau > h_tau: all but a few)
-            // the extended copies exist in split variants only: the hard-PSL
-            // maximum alone (the experiment loss's forward pass) keeps a copy
-            // without the other extensions' per-cell tests
+            // of the extended copies, the hard-PSL maximum alone (the
+            // experiment loss's forward pass) keeps a copy without the other
+            // extensions' per-cell tests
             auto ext_copy = [&]() {
-                if constexpr (SPLIT) {
-                    if (ext_full)
-                        by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 2>{});
-                    else
-                        by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 1>{});
-                }
+                if (ext_full)
+                    by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 2>{});
+                else
+                    by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 1>{});
             };
             if constexpr (MODE == MODE_FWD && MAGONLY) {
                 by_loss(T_{}, F_{}, T_{}, F_{});

@@ -34,12 +34,8 @@ static void* pick_mode(int mode, int lg) {
         case MODE_BWD_LOSS: return pick_lg<MODE_BWD_LOSS, 1, CIRC>(lg);
         case MODE_FUSED_ISL: return pick_lg<MODE_FUSED_ISL, 1, CIRC>(lg);
         case MODE_LOSS: return pick_lg<MODE_LOSS, 1, CIRC>(lg);
-        case MODE_FUSED_EXT:
-            if constexpr (VSel::SPLIT) return pick_lg<MODE_FUSED_ISL, 1, CIRC, true>(lg);
-            return nullptr;
-        case MODE_FWD_EXT:
-            if constexpr (VSel::SPLIT) return pick_lg<MODE_FWD, 1, CIRC, true>(lg);
-            return nullptr;
+        case MODE_FUSED_EXT: return pick_lg<MODE_FUSED_ISL, 1, CIRC, true>(lg);
+        case MODE_FWD_EXT: return pick_lg<MODE_FWD, 1, CIRC, true>(lg);
         case MODE_FWD_MAG:
             if constexpr (VSel::SPLIT) return pick_lg<MODE_FWD, 1, CIRC>(lg);
             return pick_lg<MODE_FWD, 1, CIRC, false, true>(lg);

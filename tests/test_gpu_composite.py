@@ -98,11 +98,6 @@ def test_match_at_its_own_surface_and_rejections(af):
     with pytest.raises(_lib.AfError) as ei:
         plan.loss(to_dev(s), w_isl=0.0, w_psl=1.0, match=tgt, w_match=1.0)
     assert ei.value.code == -2
-    # nor the hard PSL on the halves-in-turn variant (M >= 16384)
-    big = af.Plan([9000], [32768], [100], eps=EPS)
-    with pytest.raises(_lib.AfError) as ei:
-        big.loss(to_dev(W.random_code(9000, seed=1)), w_isl=0.0, w_psl=1.0, psl_hard=True)
-    assert ei.value.code == -2
 
 
 def rand_c64(n, seed, modulated=True):
@@ -244,9 +239,6 @@ def test_new_terms_rejections(af):
     assert ei.value.code == -1
     big = af.Plan([5000], [16384], [100], eps=EPS)
     with pytest.raises(_lib.AfError) as ei:
-        big.loss(to_dev(rand_c64(5000, 2)), w_isl=1.0, w_width=1.0)  # halves-in-turn variant
-    assert ei.value.code == -2
-    with pytest.raises(_lib.AfError) as ei:
         big.project(to_dev(rand_c64(5000, 2)), torch.ones(5000, device="cuda"))  # mask beyond N = 4096
     assert ei.value.code == -2
 
@@ -294,12 +286,47 @@ def test_cell_weights_rejections(af):
     assert ei.value.code == -1
 
 
+def unique_max_code(n, m, T, seed0):
+    # a code whose largest sidelobe power is unique (the hard PSL's cell is
+    # then the same for float32 and float64)
+    side = ~O.mainlobe_mask(m, T, 1, 1)
+    for seed in range(seed0, seed0 + 40):
+        s = rand_c64(n, seed)
+        c = O.chi(s, m, T)
+        p = O.power(c, O.energy(s))
+        top = np.sort(np.unique(np.round(p[side], 9)))
+        if top[-1] - top[-2] > 1e-4 * top[-1]:
+            return s, c, side
+    raise AssertionError("no code with a unique maximum")
+
+
+@pytest.mark.parametrize("n,m,T", [(600, 16384, 20), (1500, 32768, 10)])
+def test_hard_psl_alone_halves_in_turn(af, n, m, T):
+    # the forward pass alone records the maximum (the extended forward
+    # instance of the 1024-thread halves-in-turn variant); its gradient is
+    # the single-cell adjoint
+    say("hard PSL halves in turn", n, m, T)
+    s, c, side = unique_max_code(n, m, T, 2200)
+    E = O.energy(s)
+    plan = af.Plan([n], [m], [T], eps=EPS)
+    assert plan.summary()["variant"] == 2
+    terms, g, _ = plan.loss(to_dev(s), w_isl=0.0, w_psl=1.0, psl_hard=True)
+    torch.cuda.synchronize()
+    psl, cell = O.hard_psl(c, E, side)
+    G = np.zeros_like(c)
+    G[cell] = c[cell] / (E * E)
+    g_psl = O.grad_from_upstream(s, m, T, G, -2.0 * psl / E)
+    assert abs(terms[0, 0].item() - psl) <= 1e-4 * psl, (terms[0, 0].item(), psl)
+    check_grad(g.cpu().numpy().astype(np.complex128), g_psl, "hard PSL M = %d" % m)
+
+
 @pytest.mark.parametrize("variant,n,m,T", [(0, 300, 1024, 40), (3, 300, 1024, 40), (4, 1500, 4096, 30),
-                                           (1, 3000, 8192, 20), (5, 3000, 8192, 20)])
-def test_extended_terms_every_split_variant(af, variant, n, m, T):
+                                           (1, 3000, 8192, 20), (5, 3000, 8192, 20), (2, 600, 16384, 20),
+                                           (2, 1500, 32768, 10)])
+def test_extended_terms_every_variant(af, variant, n, m, T):
     # every extended term at once (hard PSL, L_match, width, cell weights,
-    # var(|s|), smoothness, ISL) on each split variant's extended instances,
-    # with a lag window
+    # var(|s|), smoothness, ISL) on each variant's extended instances, with
+    # a lag window (variant 2: the halves-in-turn variant of M >= 16384)
     say("extended terms variant", variant, n, m, T)
     rows = 2 * T + 1
     side = ~O.mainlobe_mask(m, T, 1, 1)
