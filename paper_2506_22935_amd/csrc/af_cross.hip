@@ -97,7 +97,17 @@ __global__ __launch_bounds__(XWGS) void xaf_kernel(CrossArgs a) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) gs[j] = gu[j] = make_float2(0.f, 0.f);
     float qsum = 0.f;
-    auto sync = []() { __syncthreads(); };
+    // a lane group within one wavefront (L divides 64) orders its own LDS
+    // accesses; larger groups synchronise the work group
+    auto sync = []() {
+        if constexpr (L <= 64) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    };
     // job j of the segment: lag tau_begin + j/2, sign + (j even) or - (j odd);
     // periodic: the row N - lag for the minus sign (none for lags 0 and N/2)
     auto job_tau = [&](int job, bool& active) {

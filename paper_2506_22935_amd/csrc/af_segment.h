@@ -363,9 +363,10 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
     const float2* __restrict__ sg_s = a.s + w.s_off;
     const float2* __restrict__ tw = a.tw;
     // transform passes exchange data only inside the lane group: when the
-    // group is exactly one wavefront, ordering its own LDS accesses suffices
+    // group lies within one wavefront (L divides 64), ordering the
+    // wavefront's own LDS accesses suffices
     auto sync = []() {
-        if constexpr (L == 64) {
+        if constexpr (L <= 64) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
