@@ -45,7 +45,7 @@ def timed(fn, reps, torch):
 EAGER = False  # --eager: time launches from the host instead (for counter runs)
 
 
-def graph_ms(fn, k, torch, reps=5):
+def graph_ms(fn, k, torch, reps=10):
     """Per-call ms of fn: k calls captured in one HIP graph, the graph replayed
     reps times on the current stream between HIP events; the median replay
     divided by k.  Launch overhead from the host is out of the timed region;
@@ -228,7 +228,7 @@ def bench_single(args, torch):
                            n=n, m=m, lags=2 * n - 1, cells=cells, variant=plan.summary()["variant"],
                            path="fused loss pass + reduce",
                            timing=("%d host-launched steps" % args.steps) if EAGER else
-                                  ("%d steps in one HIP graph, median of 5 replays" % args.steps),
+                                  ("%d steps in one HIP graph, median of 10 replays" % args.steps),
                            stage_ms=dict(fused_pass=round(stage_ms[0], 5), reduce=round(stage_ms[1], 5)),
                            a_grid_hbm_gbs=round(hbm_step, 1), a_grid_hbm_frac=round(hbm_step / HBM_PEAK_GBS, 4),
                            materialised_fwd_bwd=mat),
@@ -762,11 +762,15 @@ WORKLOADS = {"single": bench_single, "uneven": bench_uneven, "large": bench_larg
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 1000 for the single-waveform workload, 200 for the others)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="single", choices=sorted(WORKLOADS))
     ap.add_argument("--store", default="auto", choices=["auto", "store", "recompute"])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", default=None,
+                    help="comma-separated input seeds: run the workload once per seed and report the median run, "
+                         "with every seed's value in config.seeds (the CPU baseline on the median seed only)")
     ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: the library's default)")
     ap.add_argument("--sweep", action="store_true", help="single workload: time variants 0, 3, 4, report the best")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -788,8 +792,30 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.steps is None:
+        args.steps = 1000 if args.workload == "single" else 200
     log("workload", args.workload, "steps", args.steps, "warmup", args.warmup)
-    res = WORKLOADS[args.workload](args, torch)
+    if args.seeds:
+        seeds = [int(x) for x in args.seeds.split(",")]
+        want_cpu = not args.no_cpu_baseline
+        args.no_cpu_baseline = True
+        runs = {}
+        for sd in seeds:
+            args.seed = sd
+            log("seed", sd)
+            runs[sd] = WORKLOADS[args.workload](args, torch)
+        order = sorted(seeds, key=lambda sd: runs[sd]["value"])
+        med = order[len(order) // 2]
+        res = runs[med]
+        res["config"]["seeds"] = {str(sd): dict(value=runs[sd]["value"], ms_per_step=runs[sd]["ms_per_step"])
+                                  for sd in seeds}
+        res["config"]["median_seed"] = med
+        if want_cpu:
+            args.seed = med
+            args.no_cpu_baseline = False
+            res["cpu_baseline"] = WORKLOADS[args.workload](args, torch).get("cpu_baseline")
+    else:
+        res = WORKLOADS[args.workload](args, torch)
     line = dict(metric=res.get("metric", "AF fwd+bwd cells/s"), value=res["value"], unit=res.get("unit", "cells/s"),
                 n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=res["ms_per_step"], higher_is_better=True,
