@@ -628,6 +628,13 @@ bool extended_terms(const af_loss_params* lp) {
     return (lp->psl_hard != 0 && lp->w_psl != 0.f) || lp->w_match != 0.f || lp->w_width != 0.f ||
            lp->w_cell != 0.f;
 }
+// The forward pass of a loss: the extended instance when a term needs it,
+// the hard-PSL-only one when the maximum is the only such term
+int forward_mode(const af_loss_params* lp) {
+    if (!extended_terms(lp)) return graf::MODE_FWD;
+    return (lp->w_match != 0.f || lp->w_width != 0.f || lp->w_cell != 0.f) ? graf::MODE_FWD_EXT
+                                                                            : graf::MODE_FWD_HARD;
+}
 
 af_status check_loss(const af_plan* p, const af_loss_params* lp) {
     if (!lp) return AF_ERR_INVALID_ARG;
@@ -647,7 +654,9 @@ af_status check_loss(const af_plan* p, const af_loss_params* lp) {
     // class's extended instances
     if (extended_terms(lp))
         for (const af_plan::Class& k : p->classes)
-            if (k.grid[graf::MODE_FUSED_EXT] <= 0 || k.grid[graf::MODE_FWD_EXT] <= 0) return AF_ERR_UNSUPPORTED;
+            if (k.grid[graf::MODE_FUSED_EXT] <= 0 || k.grid[graf::MODE_FWD_EXT] <= 0 ||
+                k.grid[graf::MODE_FWD_HARD] <= 0)
+                return AF_ERR_UNSUPPORTED;
     if (lp->w_spec != 0.f && p->max_n > kMaxSpecN) return AF_ERR_UNSUPPORTED;
     return AF_OK;
 }
@@ -744,7 +753,7 @@ af_status loss_passes(const af_plan* p, const void* s, const af_loss_params* lp,
     AfArgs a = loss_args(p, s, lp, mag, v);
     af_status rc;
     if (forward_only(lp, want_grad)) {
-        rc = launch(p, extended_terms(lp) ? graf::MODE_FWD_EXT : graf::MODE_FWD, a, st, only_class);
+        rc = launch(p, forward_mode(lp), a, st, only_class);
     } else if (a.w_psl == 0.f) {
         rc = launch(p, extended_terms(lp) ? graf::MODE_FUSED_EXT : graf::MODE_FUSED_ISL, a, st, only_class);
     } else if (fused_loss_ok(p, lp)) {
@@ -1069,7 +1078,7 @@ af_status af_loss_stage(const af_plan* p, int32_t stage, const void* s, const af
             if (fused) return launch(p, extended_terms(lp) ? graf::MODE_FUSED_EXT : graf::MODE_FUSED_ISL, a, st);
             if (fused_loss) return launch(p, graf::MODE_LOSS, a, st);
             a.ystore = fwd_only ? nullptr : v.store;
-            return launch(p, (fwd_only && extended_terms(lp)) ? graf::MODE_FWD_EXT : graf::MODE_FWD, a, st);
+            return launch(p, fwd_only ? forward_mode(lp) : graf::MODE_FWD, a, st);
         case 1:
             if (!(fwd_only || fused || fused_loss)) {
                 a.mag = nullptr;

@@ -66,14 +66,20 @@ enum Mode : int {
     MODE_FWD_EXT = 6,   // launch id only: the MODE_FWD pass with the extended
                         // epilogue terms, likewise; the plain forward carries
                         // none of their code and keeps every value in registers
-    MODE_FWD_MAG = 7    // launch id only: af_forward without chi rows: a grid and
+    MODE_FWD_MAG = 7,   // launch id only: af_forward without chi rows: a grid and
                         // spectra only (its own instance in the halves-in-turn
                         // variant, whose full forward does not fit 128 registers;
                         // MODE_FWD elsewhere)
+    MODE_FWD_HARD = 8   // launch id only: the MODE_FWD pass recording the hard-PSL
+                        // maximum and no other extended term (the experiment
+                        // loss's pass), in an instance without the per-cell
+                        // code of the other terms
 };
-constexpr int kNumModes = 8;
-// launch ids that run the extended epilogue (split variants only)
-constexpr bool is_ext_mode(int mode) { return mode == MODE_FUSED_EXT || mode == MODE_FWD_EXT; }
+constexpr int kNumModes = 9;
+// launch ids that run the extended epilogue
+constexpr bool is_ext_mode(int mode) {
+    return mode == MODE_FUSED_EXT || mode == MODE_FWD_EXT || mode == MODE_FWD_HARD;
+}
 
 struct AfArgs {
     WaveDesc w0;          // the waveform of a one-waveform class (single != 0)

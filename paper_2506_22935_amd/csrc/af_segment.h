@@ -323,8 +323,9 @@ constexpr bool EXT_MODE() {
 // MAGONLY (forward): a and spectra only, no loss sums and no chi rows, so the
 // instance carries a single family of epilogue copies (the halves-in-turn
 // variant then keeps every value in its 128 registers)
+// HARDONLY (extended forward): the hard-PSL maximum is the only extended term
 template <int MODE, int MH, int P, int SPLIT, int WGS, int NACC, bool CIRC, bool EXTK, bool MAGONLY = false,
-          bool UNPAD = false, typename Tw>
+          bool UNPAD = false, bool HARDONLY = false, typename Tw>
 __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc sg, float2* lds, const Tw& twl,
                                                 const float2* s_lds, bool s_in_lds, double* scratch,
                                                 const WaveState& ws) {
@@ -842,10 +843,14 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             // experiment loss's forward pass) keeps a copy without the other
             // extensions' per-cell tests
             auto ext_copy = [&]() {
-                if (ext_full)
-                    by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 2>{});
-                else
+                if constexpr (HARDONLY) {
                     by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 1>{});
+                } else {
+                    if (ext_full)
+                        by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 2>{});
+                    else
+                        by_loss(T_{}, F_{}, T_{}, std::integral_constant<int, 1>{});
+                }
             };
             if constexpr (MODE == MODE_FWD && MAGONLY) {
                 by_loss(T_{}, F_{}, T_{}, F_{});
@@ -1159,7 +1164,8 @@ using V5 = Variant<32, 1, 256, 1, 12, 12, 1, 0>; // M 8192: 32 points per lane, 
 // Persistent kernel over one size class: work group g runs items g, g + grid,
 // g + 2 grid, ... of the class's list, which the planner sorted longest first
 // (a static, deterministic assignment).
-template <int MODE, typename V, int LG, bool CIRC = false, bool EXTK = false, bool MAGONLY = false>
+template <int MODE, typename V, int LG, bool CIRC = false, bool EXTK = false, bool MAGONLY = false,
+          bool HARDONLY = false>
 __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
     static_assert(!CIRC || (V::SPLIT && V::S_LDS), "periodic AF: split variants with samples in LDS");
     static_assert(!V::TW_LDS || (1 << LG) + PassTables<(1 << LG), V::P>::total() <= (2 << LG),
@@ -1209,8 +1215,8 @@ __global__ __launch_bounds__(V::WGS, V::WAVES) void af_kernel(AfArgs a) {
             const WaveDesc w = a.single ? a.w0 : a.waves[sg.wave];
             stage_wave<MODE, V::WGS, MH, CIRC, V::P>(a, w, sg.wave, s_lds, V::S_LDS != 0, scratch, st, nullptr, 0);
         }
-        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG), CIRC, EXTK, MAGONLY>(a, sg, lds, twl, s_lds,
-                                                                                  V::S_LDS != 0, scratch, st);
+        process_segment<MODE, MH, V::P, V::SPLIT, V::WGS, V::nacc(LG), CIRC, EXTK, MAGONLY, false, HARDONLY>(
+            a, sg, lds, twl, s_lds, V::S_LDS != 0, scratch, st);
     }
 }
 

@@ -14,6 +14,7 @@ static void* union_mode(int mode) {
         case MODE_FUSED_EXT: return (void*)af_union_kernel<MODE_FUSED_ISL, CIRC, true>;
         case MODE_FWD_EXT: return (void*)af_union_kernel<MODE_FWD, CIRC, true>;
         case MODE_FWD_MAG: return (void*)af_union_kernel<MODE_FWD, CIRC>;
+        case MODE_FWD_HARD: return (void*)af_union_kernel<MODE_FWD, CIRC, true>;
     }
     return nullptr;
 }

@@ -12,17 +12,17 @@ namespace graf {
 #define GRAF_CAT(a, b) GRAF_CAT2(a, b)
 using VSel = GRAF_CAT(V, GRAF_VARIANT);
 
-template <int MODE, int LG, bool CIRC, bool EXTK = false, bool MAGONLY = false>
+template <int MODE, int LG, bool CIRC, bool EXTK = false, bool MAGONLY = false, bool HARDONLY = false>
 static void* pick_lg(int lg) {
     if constexpr (LG > 15) {
         return nullptr;
     } else {
         if (lg == LG) {
             if constexpr (VSel::fits(LG) && (!CIRC || (VSel::SPLIT && VSel::S_LDS)))
-                return (void*)af_kernel<MODE, VSel, LG, CIRC, EXTK, MAGONLY>;
+                return (void*)af_kernel<MODE, VSel, LG, CIRC, EXTK, MAGONLY, HARDONLY>;
             return nullptr;
         }
-        return pick_lg<MODE, LG + 1, CIRC, EXTK, MAGONLY>(lg);
+        return pick_lg<MODE, LG + 1, CIRC, EXTK, MAGONLY, HARDONLY>(lg);
     }
 }
 
@@ -36,6 +36,7 @@ static void* pick_mode(int mode, int lg) {
         case MODE_LOSS: return pick_lg<MODE_LOSS, 1, CIRC>(lg);
         case MODE_FUSED_EXT: return pick_lg<MODE_FUSED_ISL, 1, CIRC, true>(lg);
         case MODE_FWD_EXT: return pick_lg<MODE_FWD, 1, CIRC, true>(lg);
+        case MODE_FWD_HARD: return pick_lg<MODE_FWD, 1, CIRC, true, false, true>(lg);
         case MODE_FWD_MAG:
             if constexpr (VSel::SPLIT) return pick_lg<MODE_FWD, 1, CIRC>(lg);
             return pick_lg<MODE_FWD, 1, CIRC, false, true>(lg);
