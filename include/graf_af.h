@@ -277,9 +277,8 @@ af_status af_scenario_combine(const af_plan* plan, int32_t n_scen, const float* 
  * (E_s E_u) + eps) (|chi_su|^2 <= E_s E_u; chi_su = chi when u = s).
  * Periodic waveforms (AF_WAVE_PERIODIC, Eq. 2's circular lags) take
  *   chi_su[tau, k] = sum_n s[n] conj(u[(n - tau) mod N]) exp(-j 2 pi k n / N)
- * on their [N][N] grids (row tau in [0, N)).  Plans whose classes have
- * M <= 8192 (aperiodic N <= 4096; periodic N <= 4096) only;
- * AF_ERR_UNSUPPORTED otherwise.  Grid offsets must be even and mag 8-byte
+ * on their [N][N] grids (row tau in [0, N)).  Aperiodic M up to 32768,
+ * periodic N up to 4096 (every size a plan takes).  Grid offsets must be even and mag 8-byte
  * aligned (the aperiodic forward writes the a grids as pairs of bins);
  * AF_ERR_INVALID_ARG otherwise.
  * af_cross_forward: mag (a grids), chi (chi_su grids) and energy (device

@@ -1154,7 +1154,7 @@ namespace {
 af_status check_cross(const af_plan* p, const void* s, const void* u) {
     if (!p || !s || !u || !aligned(s, 8) || !aligned(u, 8)) return AF_ERR_INVALID_ARG;
     for (const af_plan::XClass& k : p->xclasses)
-        if (!graf::cross_lg_supported(k.lg)) return AF_ERR_UNSUPPORTED;
+        if (!graf::cross_lg_supported(k.lg, k.circ)) return AF_ERR_UNSUPPORTED;
     // the kernels move the a and dL/da grids as 8-byte bin pairs
     for (const af_wave& w : p->waves)
         if (w.grid_off & 1) return AF_ERR_INVALID_ARG;

@@ -226,6 +226,142 @@ __global__ __launch_bounds__(XWGS) void xaf_kernel(CrossArgs a) {
     }
 }
 
+// Fixed-order sum over the work group's waves (every thread gets the total).
+template <int WGS, typename T>
+__device__ T xblock_sum_w(T v, T* sh) {
+    v = wave_allsum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T t = sh[0];
+#pragma unroll
+    for (int i = 1; i < WGS / 64; ++i) t += sh[i];
+    return t;
+}
+
+// Transform sizes M = 16384 and 32768 (aperiodic): a row's lane group spans
+// the whole work group (MH / 16 lanes), so a work group takes one row per
+// iteration, both halves in turn.  The samples come from global memory
+// through buffer resources over [0, N) (zero outside, which also zeroes the
+// lag product beyond the overlap), the twiddles from the plan's table, and
+// the backward accumulates each segment's two gradients in its slabs in
+// global memory (each thread reads, adds and writes its own samples per row)
+// instead of registers.
+template <int MODE, int LG>
+__global__ __launch_bounds__((1 << LG) / XP) void xaf_big_kernel(CrossArgs a) {
+    constexpr int MH = 1 << LG, L = MH / XP, WGS = L, M = 2 * MH;
+    constexpr int NJ = MH / WGS;  // samples owned per thread
+    extern __shared__ float2 dyn[];
+    __shared__ float shf[WGS / 64];
+    __shared__ double shd[WGS / 64];
+    const SegDesc sg = a.segs[blockIdx.x];
+    const WaveDesc w = a.waves[sg.wave];
+    const int N = w.n, T = w.T;
+    const int tid = threadIdx.x;
+    const int l = tid;
+    float2* buf = dyn;
+    const TwTable twl{a.tw, a.log2_mmax - w.log2m};
+    const Rsrc s_rs = make_rsrc(a.s + w.s_off, (unsigned)N * 8u);
+    const Rsrc u_rs = make_rsrc(a.u + w.s_off, (unsigned)N * 8u);
+
+    float es = 0.f, eu = 0.f;
+    for (int i = tid; i < N; i += WGS) {
+        es += cabs2(buf_load2(s_rs, i * 8));
+        eu += cabs2(buf_load2(u_rs, i * 8));
+    }
+    const float Es = xblock_sum_w<WGS>(es, shf);
+    const float Eu = xblock_sum_w<WGS>(eu, shf);
+    const float invEE = 1.f / (Es * Eu);
+    if (sg.tau_begin == 0 && tid == 0 && a.energy) {
+        a.energy[2 * sg.wave] = Es;
+        a.energy[2 * sg.wave + 1] = Eu;
+    }
+    float2* const gs_sl = MODE == 1 ? a.slab_s + w.slab_off + (int64_t)(sg.rec - w.seg_begin) * N : nullptr;
+    float2* const gu_sl = MODE == 1 ? a.slab_u + w.slab_off + (int64_t)(sg.rec - w.seg_begin) * N : nullptr;
+    if constexpr (MODE == 1) {
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int i = tid + jj * WGS;
+            if (i < N) {
+                gs_sl[i] = make_float2(0.f, 0.f);
+                gu_sl[i] = make_float2(0.f, 0.f);
+            }
+        }
+    }
+    float qsum = 0.f;
+    auto sync = []() { __syncthreads(); };
+    const int jobs = 2 * (sg.tau_end - sg.tau_begin);
+    for (int job = 0; job < jobs; ++job) {
+        const int lag = sg.tau_begin + (job >> 1);
+        const bool neg = (job & 1) != 0;
+        if (neg && lag == 0) continue;  // the same for the whole work group
+        const int tau = neg ? -lag : lag;
+        const int64_t row = w.grid_off + (int64_t)(T + tau) * M;
+        float2 qa[XP];
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            float2 v[XP];
+#pragma unroll
+            for (int r = 0; r < XP; ++r) {
+                const int n = l + r * L;
+                // u[n - tau] is zero outside [0, N) (the range check), as is s[n]
+                float2 x = cmulc(buf_load2(s_rs, n * 8), buf_load2(u_rs, (n - tau) * 8));
+                if (h) x = cmul(x, twl(n));
+                v[r] = x;
+                if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+            fft_group<MH, XP, -1, true>(v, buf, l, twl, sync);
+#pragma unroll
+            for (int q = 0; q < XP; ++q) {
+                const int k = 2 * (l + q * L) + h;
+                const float pw = cabs2(v[q]) * invEE;
+                if constexpr (MODE == 0) {
+                    if (a.mag) a.mag[row + k] = __builtin_amdgcn_sqrtf(pw + a.eps);
+                    if (a.chi) a.chi[row + k] = v[q];
+                } else {
+                    const float g = a.grad_mag[row + k];
+                    const float ia = __builtin_amdgcn_rsqf(pw + a.eps);
+                    qsum = fmaf(g * pw, ia, qsum);
+                    v[q] = cscale(v[q], 0.5f * g * invEE * ia);
+                }
+            }
+            if constexpr (MODE == 1) {
+                fft_group<MH, XP, +1, true>(v, buf, l, twl, sync);
+#pragma unroll
+                for (int q = 0; q < XP; ++q) {
+                    if (h) v[q] = cmulc(v[q], twl(l + q * L));
+                    qa[q] = h ? cadd(qa[q], v[q]) : v[q];
+                }
+            }
+        }
+        if constexpr (MODE == 1) {
+            // Q of the row into the buffer, natural order, then the gather
+            // into this thread's samples of the two slabs
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < XP; ++q) buf[lds_index(l + q * L)] = qa[q];
+            __syncthreads();
+#pragma unroll 4
+            for (int jj = 0; jj < NJ; ++jj) {
+                const int i = tid + jj * WGS;
+                if (i >= N) break;
+                float2 gsv = gs_sl[i], guv = gu_sl[i];
+                // u[i - tau] is zero outside [0, N) (the range check)
+                gsv = cadd(gsv, cmul(buf_load2(u_rs, (i - tau) * 8), buf[lds_index(i)]));
+                const int jp = i + tau;
+                if (jp >= 0 && jp < N) guv = cadd(guv, cmulc(buf_load2(s_rs, jp * 8), buf[lds_index(jp)]));
+                gs_sl[i] = gsv;
+                gu_sl[i] = guv;
+            }
+            __syncthreads();
+        }
+    }
+    if constexpr (MODE == 1) {
+        const double qw = xblock_sum_w<WGS>((double)qsum, shd);
+        if (tid == 0) a.part[sg.rec] = qw;
+    }
+}
+
 // dL/d conj(s) and dL/d conj(u): the waveform's slabs in segment order plus
 // the energy terms; one thread per sample, blockIdx.y the waveform.
 __global__ __launch_bounds__(256) void xreduce_kernel(CrossArgs a) {
@@ -281,12 +417,28 @@ hipError_t launch_mode(int lg, const CrossArgs& a, int grid, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+template <int MODE, int LG>
+hipError_t launch_big(const CrossArgs& a, int grid, hipStream_t st) {
+    static bool attr = false;
+    const void* k = (const void*)xaf_big_kernel<MODE, LG>;
+    constexpr int lds = LdsSize<(1 << LG)>::value * 8;
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((xaf_big_kernel<MODE, LG>), dim3(grid), dim3((1 << LG) / XP), (size_t)lds, st, a);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-bool cross_lg_supported(int lg) { return lg >= 6 && lg <= 12; }
+bool cross_lg_supported(int lg, int circ) { return lg >= 6 && lg <= (circ ? 12 : 14); }
 
 hipError_t launch_cross(int mode, int lg, int circ, const CrossArgs& a, int grid, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
+    if (!circ && lg == 13) return mode == 0 ? launch_big<0, 13>(a, grid, st) : launch_big<1, 13>(a, grid, st);
+    if (!circ && lg == 14) return mode == 0 ? launch_big<0, 14>(a, grid, st) : launch_big<1, 14>(a, grid, st);
     if (circ) return mode == 0 ? launch_mode<0, true>(lg, a, grid, st) : launch_mode<1, true>(lg, a, grid, st);
     return mode == 0 ? launch_mode<0, false>(lg, a, grid, st) : launch_mode<1, false>(lg, a, grid, st);
 }

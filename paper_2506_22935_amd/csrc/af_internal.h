@@ -218,7 +218,7 @@ struct CrossArgs {
     float2* grad_s;       // reduction outputs, packed like s
     float2* grad_u;
 };
-bool cross_lg_supported(int lg);
+bool cross_lg_supported(int lg, int circ);
 hipError_t launch_cross(int mode, int lg, int circ, const CrossArgs& a, int grid, hipStream_t st);
 hipError_t launch_cross_reduce(const CrossArgs& a, int batch, int max_n, hipStream_t st);
 
