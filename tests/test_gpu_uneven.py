@@ -220,6 +220,30 @@ def test_one_launch_largest_size_edges(af):
         assert np.max(np.abs(g1[o:o + n] - ref["g"])) <= 1e-4 * np.max(np.abs(ref["g"])), b
 
 
+@pytest.mark.parametrize("mmax", [2048, 4096])
+def test_one_launch_smaller_largest_size(af, mmax):
+    # plans whose largest M is 2048 or 4096: the stride-256 pass table holds
+    # only the entries those sizes read (whole indices of the plan's table)
+    say("one launch, largest M", mmax)
+    ns = [mmax // 2, mmax // 4 - 3, 300, 100, 40]
+    ms = [mmax, mmax // 2, 1024, 256, 128]
+    codes = [W.random_code(n, seed=990 + i) for i, n in enumerate(ns)]
+    s = torch.from_numpy(np.concatenate(codes)).cuda()
+    one = af.Plan(ns, ms, eps=EPS)
+    per = af.Plan(ns, ms, eps=EPS, one_launch=False)
+    assert one.summary()["variant"] == 6 and per.summary()["variant"] != 6
+    t1, g1, a1 = one.loss(s, w_isl=1.0, grad=True, mag=True)
+    t2, g2, a2 = per.loss(s, w_isl=1.0, grad=True, mag=True)
+    torch.cuda.synchronize()
+    assert np.allclose(t1.cpu().numpy(), t2.cpu().numpy(), rtol=1e-5, atol=1e-6)
+    assert float((a1 - a2).abs().max()) <= 1e-6
+    g1 = g1.cpu().numpy().astype(np.complex128)
+    g2 = g2.cpu().numpy().astype(np.complex128)
+    for b, n in enumerate(ns):
+        o = one.s_offsets[b]
+        assert np.max(np.abs(g1[o:o + n] - g2[o:o + n])) <= 1e-5 * np.max(np.abs(g2[o:o + n])), b
+
+
 def test_one_launch_is_deterministic(af):
     # work groups take items by atomic ticket, so the assignment changes from
     # run to run; every item writes its own slab and record, so the results
