@@ -606,6 +606,14 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
             }
         }
 
+        // magnitude-only forward of the halves-in-turn variant: the even
+        // half's magnitudes wait in registers for the odd half's, so that
+        // each row goes out in whole lines (one half alone would leave every
+        // other 4-byte bin of a line to a later write).  Reading the
+        // backward's upstream rows in pairs the same way measured slower:
+        // the held values push its 128 registers into spills
+        constexpr bool PAIR = !SPLIT && MAGONLY;
+        float hold[PAIR ? P : 1];
 #pragma unroll 1
         for (int hh = 0; hh < (SPLIT ? 1 : 2); ++hh) {
             const int h = SPLIT ? hsel : hh;
@@ -725,6 +733,18 @@ __device__ __forceinline__ void process_segment(const AfArgs& a, const SegDesc s
                             if (SPLIT) {
                                 rowbuf[k] = av;
                                 rowbuf[RL + kn] = av;
+                            } else if constexpr (PAIR) {
+                                if (h == 0) {
+                                    hold[PAIR ? q : 0] = av;
+                                } else if (active) {
+                                    // bins k - 1 (even) and k of row tau as one pair;
+                                    // row -tau holds them at M - k + 1 and M - k
+                                    buf_store2(mag_p, (k - 1) * 4, make_float2(hold[PAIR ? q : 0], av));
+                                    if (tau > 0) {
+                                        buf_store1(mag_n, (k == 1 ? 0 : RL - k + 1) * 4, hold[PAIR ? q : 0]);
+                                        buf_store1(mag_n, (RL - k) * 4, av);
+                                    }
+                                }
                             } else if (active) {
                                 buf_store1(mag_p, k * 4, av);
                                 if (tau > 0) buf_store1(mag_n, kn * 4, av);
